@@ -1,0 +1,997 @@
+/*
+ * mstar_oracle.c -- plain, slow, FP64 CPU oracle of the MSTAR algorithmically
+ * regularised integrator (Rantala, Pihajoki, Mannerkoski, Johansson & Naab
+ * 2020, "MSTAR - a fast parallelised algorithmically regularised integrator
+ * with minimum spanning tree coordinates").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
+ * is checked against.  It is used by tests/, by __graft_entry__.smoke() and by
+ * bench.py's cpu_baseline leg, and by nothing else; the product library never
+ * links or calls it, and it shares no code with the product library.
+ *
+ * Arithmetic: IEEE-754 binary64, round to nearest even, compiled with
+ * -ffp-contract=off and without fast-math, so every +,-,*,/ and sqrt below is
+ * one correctly rounded operation in the order written.  OpenMP, where used,
+ * parallelises over independent i (each a_i is still summed by one thread in
+ * ascending j), so results are bit-identical for any thread count.
+ *
+ * Each function names the passage of the paper it follows.  Readings taken
+ * where the paper is silent are marked READING and listed in the design doc.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_E_INVAL -1
+#define ORC_E_NOMEM -2
+#define ORC_E_NONFINITE -4
+#define ORC_E_COINCIDENT -5
+#define ORC_E_NOCONV -6
+#define ORC_E_MAXSTEPS -7
+#define ORC_W_TIME_TOL 1
+
+/* Parameters of the method (Sec. 2.1 triplet, Sec. 2.3 GBS, Sec. 2.4 time
+ * iteration, Sec. 3.4 N_d, Sec. 4.2 k_fix).  Layout mirrored by oracle/__init__.py. */
+typedef struct {
+    double G;
+    double eta;            /* GBS tolerance eta_GBS, eq. gbs-criterion */
+    double alpha, beta, gamma; /* time-transformation triplet, eq. ttl */
+    double omega_mass_max; /* READING: Omega couples only bodies with m <= this */
+    double a_gbs, f_min, f_max; /* eq. hnext safety factor and READING clamps */
+    double q_first;        /* Sec. 2.4 first-step safety factor */
+    double t_tol;          /* relative end-time tolerance */
+    double h_init;         /* >0: first fictitious step; 0: automatic */
+    int64_t max_steps;
+    int32_t k_fix;         /* number of substep divisions, n_k = 2k */
+    int32_t n_d;           /* MST closeness N_d, eq. LCA */
+    int32_t max_halvings;
+    int32_t max_time_iter;
+    int32_t rebuild_every; /* accepted steps between MST rebuilds */
+    int32_t nthreads;      /* OpenMP threads for the force loop (0 = default) */
+} orc_params;
+
+typedef struct {
+    int64_t steps_accepted, steps_rejected, force_evals, mst_rebuilds, topo_changes, time_iters;
+    double t_reached, eps_last, h_next, h_last;
+} orc_stats;
+
+/* ------------------------------------------------------------------ */
+/* Neumaier compensated summation (Neumaier 1974; Sec. 3.5 mentions it). */
+typedef struct { double s, c; } nsum;
+static void ns_init(nsum *a) { a->s = 0.0; a->c = 0.0; }
+static void ns_add(nsum *a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double ns_get(const nsum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------ */
+/* Centre of mass of a set of vectors, Neumaier sums in index order. */
+static void com3(int n, const double *m, const double *x, double out[3]) {
+    nsum M, s[3];
+    ns_init(&M);
+    for (int k = 0; k < 3; ++k) ns_init(&s[k]);
+    for (int i = 0; i < n; ++i) {
+        ns_add(&M, m[i]);
+        for (int k = 0; k < 3; ++k) ns_add(&s[k], m[i] * x[3 * i + k]);
+    }
+    double Mt = ns_get(&M);
+    for (int k = 0; k < 3; ++k) out[k] = ns_get(&s[k]) / Mt;
+}
+
+/* Squared edge length used as the MST weight (Sec. 3.1 weights by Euclidean
+ * length; READING: the square, which orders edges identically, evaluated as
+ * (dx*dx + dy*dy) + dz*dz with d = x_j - x_i, so w_ij = w_ji bit for bit). */
+static double edge_w(const double *xi, const double *xj) {
+    double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+/* Strict total order on edges: (w, min(i,j), max(i,j)) lexicographic.  Makes the
+ * MST unique (Sec. 3.1: unique weights give a unique MST). */
+static int key_less(double w1, int a1, int b1, double w2, int a2, int b2) {
+    int lo1 = a1 < b1 ? a1 : b1, hi1 = a1 < b1 ? b1 : a1;
+    int lo2 = a2 < b2 ? a2 : b2, hi2 = a2 < b2 ? b2 : a2;
+    if (w1 < w2) return 1;
+    if (w1 > w2) return 0;
+    if (lo1 != lo2) return lo1 < lo2;
+    return hi1 < hi2;
+}
+
+/* Root choice (Sec. 3.2): the body closest to the centre of mass.  Ties go to
+ * the lowest index. */
+int orc_root_nearest_com(int n, const double *m, const double *x) {
+    double c[3];
+    com3(n, m, x, c);
+    int best = 0;
+    double bw = edge_w(c, x);
+    for (int i = 1; i < n; ++i) {
+        double w = edge_w(c, x + 3 * i);
+        if (w < bw) { bw = w; best = i; }
+    }
+    return best;
+}
+
+/* Prim's algorithm on the complete graph (Sec. 3.2).  Starts at `root`, then
+ * repeatedly adds the minimum edge joining the tree to a vertex outside it.
+ * parent[] and level[] are assigned as vertices are added, so edges point away
+ * from the root and order[] is the order of addition (Sec. 3.4). */
+int orc_mst_prim(int n, const double *x, int root, int *parent, int *level, int *order) {
+    if (n < 1 || root < 0 || root >= n) return ORC_E_INVAL;
+    char *in = (char *)calloc((size_t)n, 1);
+    double *bw = (double *)malloc(sizeof(double) * (size_t)n);
+    int *bu = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!in || !bw || !bu) { free(in); free(bw); free(bu); return ORC_E_NOMEM; }
+    in[root] = 1; parent[root] = -1; level[root] = 0; order[0] = root;
+    for (int v = 0; v < n; ++v) {
+        if (v == root) continue;
+        bw[v] = edge_w(x + 3 * root, x + 3 * v);
+        bu[v] = root;
+    }
+    for (int step = 1; step < n; ++step) {
+        int pick = -1;
+        for (int v = 0; v < n; ++v) {
+            if (in[v]) continue;
+            if (pick < 0 || key_less(bw[v], bu[v], v, bw[pick], bu[pick], pick)) pick = v;
+        }
+        in[pick] = 1;
+        parent[pick] = bu[pick];
+        level[pick] = level[bu[pick]] + 1;
+        order[step] = pick;
+        for (int u = 0; u < n; ++u) {
+            if (in[u]) continue;
+            double w = edge_w(x + 3 * pick, x + 3 * u);
+            if (key_less(w, pick, u, bw[u], bu[u], u)) { bw[u] = w; bu[u] = pick; }
+        }
+    }
+    free(in); free(bw); free(bu);
+    return ORC_OK;
+}
+
+/* Levels and a parents-before-children order from a parent array (root has
+ * parent -1).  Returns the root, or -1 if parent[] is not a rooted tree. */
+int orc_tree_levels(int n, const int *parent, int *level, int *order) {
+    int root = -1;
+    for (int v = 0; v < n; ++v) {
+        if (parent[v] < 0) { if (root >= 0) return -1; root = v; }
+        else if (parent[v] >= n || parent[v] == v) return -1;
+    }
+    if (root < 0) return -1;
+    for (int v = 0; v < n; ++v) level[v] = -1;
+    level[root] = 0;
+    /* walk each vertex up to a vertex of known level (with a cycle guard) */
+    for (int v = 0; v < n; ++v) {
+        int u = v, len = 0;
+        while (level[u] < 0) { u = parent[u]; if (++len > n) return -1; }
+        int L = level[u];
+        u = v;
+        /* assign levels top-down along the walked path */
+        int depth = len;
+        while (level[u] < 0) { level[u] = L + depth; u = parent[u]; --depth; }
+    }
+    /* counting sort by level, ties by vertex id */
+    int maxL = 0;
+    for (int v = 0; v < n; ++v) if (level[v] > maxL) maxL = level[v];
+    int *cnt = (int *)calloc((size_t)maxL + 2, sizeof(int));
+    if (!cnt) return -1;
+    for (int v = 0; v < n; ++v) cnt[level[v] + 1]++;
+    for (int l = 0; l <= maxL; ++l) cnt[l + 1] += cnt[l];
+    for (int v = 0; v < n; ++v) order[cnt[level[v]]++] = v;
+    free(cnt);
+    return root;
+}
+
+/* Deconstruction (Sec. 2.2 / 3.4): original-frame positions relative to the
+ * root, rho_root = 0 and rho_v = rho_parent(v) + X_v, parents first. */
+void orc_deconstruct(int n, const int *parent, const int *order, const double *X, double *rho) {
+    int root = order[0];
+    rho[3 * root] = rho[3 * root + 1] = rho[3 * root + 2] = 0.0;
+    for (int k = 1; k < n; ++k) {
+        int v = order[k], p = parent[v];
+        for (int c = 0; c < 3; ++c) rho[3 * v + c] = rho[3 * p + c] + X[3 * v + c];
+    }
+}
+
+/* Tree closeness by the lowest common ancestor, eq. LCA: i and j are close iff
+ * (L(i) - L(LCA)) + (L(j) - L(LCA)) <= N_d.  Climbs at most N_d steps from each
+ * side.  On success returns 1 and the two climb lengths a (from i) and b (from j). */
+static int tree_close(int i, int j, const int *parent, const int *level, int nd, int *pa, int *pb) {
+    int di = level[i] - level[j];
+    if (di > nd || -di > nd) return 0;
+    int anc[16];
+    int u = i;
+    int na = 0;
+    for (int a = 0; a <= nd; ++a) {
+        anc[na++] = u;
+        if (parent[u] < 0) break;
+        u = parent[u];
+    }
+    int w = j;
+    for (int b = 0; b <= nd; ++b) {
+        for (int a = 0; a < na && a + b <= nd; ++a) {
+            if (anc[a] == w) { *pa = a; *pb = b; return 1; }
+        }
+        if (parent[w] < 0) break;
+        w = parent[w];
+    }
+    return 0;
+}
+
+/* Sum of the edge vectors on the path from the ancestor `steps` levels above v
+ * down to v, accumulated top-down (the vector from that ancestor to v). */
+static void path_down(int v, int steps, const int *parent, const double *X, double out[3]) {
+    int path[16];
+    int u = v;
+    for (int s = 0; s < steps; ++s) { path[s] = u; u = parent[u]; }
+    out[0] = out[1] = out[2] = 0.0;
+    for (int s = steps - 1; s >= 0; --s)
+        for (int c = 0; c < 3; ++c) out[c] = out[c] + X[3 * path[s] + c];
+}
+
+/* Separation vector d_ij = r_j - r_i (Sec. 3.4 final rule): for pairs within
+ * N_d tree edges, the walk i -> LCA -> j summed from MST edge vectors, written
+ * as S_j - S_i with S_v the LCA-to-v path sum; otherwise rho_j - rho_i.
+ * Returns 1 if the MST path was used.  d_ji = -d_ij bitwise. */
+int orc_separation(int i, int j, const int *parent, const int *level, const double *X,
+                   const double *rho, int nd, double d[3]) {
+    int a, b;
+    if (i != j && nd > 0 && tree_close(i, j, parent, level, nd, &a, &b)) {
+        double si[3], sj[3];
+        path_down(i, a, parent, X, si);
+        path_down(j, b, parent, X, sj);
+        for (int c = 0; c < 3; ++c) d[c] = sj[c] - si[c];
+        return 1;
+    }
+    for (int c = 0; c < 3; ++c) d[c] = rho[3 * j + c] - rho[3 * i + c];
+    return 0;
+}
+
+/* Newtonian accelerations and force function (Sec. 2.1):
+ *   a_i = G sum_{j!=i} m_j d_ij / |d_ij|^3,  phi_i = sum_{j!=i} m_j / |d_ij|,
+ *   U = (G/2) sum_i m_i phi_i.
+ * With beta != 0 also Omega = (G/2) sum_i mo_i sum_{j!=i} mo_j/|d_ij| and its
+ * gradient dOm_i = G mo_i sum_j mo_j d_ij/|d_ij|^3, where mo_i = m_i if
+ * m_i <= omega_mass_max else 0 (READING of the paper's "force function of the
+ * least massive particles").  Separations follow orc_separation. */
+int orc_force(int n, const double *m, const int *parent, const int *level, const double *X,
+              const double *rho, const orc_params *p, double *acc, double *phi,
+              double *U, double *Om, double *dOm) {
+    const int nd = p->n_d;
+    const int want_om = p->beta != 0.0;
+    double *mo = NULL, *pom = NULL;
+    if (want_om) {
+        mo = (double *)malloc(sizeof(double) * (size_t)n);
+        pom = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!mo || !pom) { free(mo); free(pom); return ORC_E_NOMEM; }
+        for (int i = 0; i < n; ++i) mo[i] = (m[i] <= p->omega_mass_max) ? m[i] : 0.0;
+    }
+#ifdef _OPENMP
+    int nt = p->nthreads > 0 ? p->nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
+#endif
+    for (int i = 0; i < n; ++i) {
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        double ox = 0.0, oy = 0.0, oz = 0.0, po = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            orc_separation(i, j, parent, level, X, rho, nd, d);
+            double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            double rinv = 1.0 / sqrt(r2);
+            double rinv3 = (rinv * rinv) * rinv;
+            double s = m[j] * rinv3;
+            ax = ax + s * d[0];
+            ay = ay + s * d[1];
+            az = az + s * d[2];
+            ph = ph + m[j] * rinv;
+            if (want_om) {
+                double so = mo[j] * rinv3;
+                ox = ox + so * d[0];
+                oy = oy + so * d[1];
+                oz = oz + so * d[2];
+                po = po + mo[j] * rinv;
+            }
+        }
+        acc[3 * i] = p->G * ax;
+        acc[3 * i + 1] = p->G * ay;
+        acc[3 * i + 2] = p->G * az;
+        phi[i] = ph;
+        if (want_om) {
+            dOm[3 * i] = p->G * mo[i] * ox;
+            dOm[3 * i + 1] = p->G * mo[i] * oy;
+            dOm[3 * i + 2] = p->G * mo[i] * oz;
+            pom[i] = po;
+        }
+    }
+    nsum su;
+    ns_init(&su);
+    for (int i = 0; i < n; ++i) ns_add(&su, m[i] * phi[i]);
+    *U = 0.5 * p->G * ns_get(&su);
+    if (want_om) {
+        nsum so;
+        ns_init(&so);
+        for (int i = 0; i < n; ++i) ns_add(&so, mo[i] * pom[i]);
+        *Om = 0.5 * p->G * ns_get(&so);
+        free(mo); free(pom);
+    } else {
+        *Om = 0.0;
+        if (dOm) memset(dOm, 0, sizeof(double) * 3 * (size_t)n);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* The integrated state (READING of Sec. 2.2 with Sec. 3.4): MST edge vectors
+ * X_v, V_v (row v = the edge from parent(v) to v; the root row is zero), the
+ * centre of mass r_cm, v_cm, physical time t, binding energy B = -H and the TTL
+ * variable w.  The tree (parent/level/order) is fixed within a GBS step. */
+typedef struct {
+    int n;
+    const double *m;
+    int *parent, *level, *order;
+    double *X, *V;
+    double t, B, w;
+    double rcm[3], vcm[3];
+} ostate;
+
+/* A substep division works on increments from the step's start state y0
+ * (READING: the tableau is formed on Y_k - Y_0, which gives the same
+ * extrapolation in exact arithmetic because the Neville weights sum to one,
+ * but keeps the rounding of large absolute values such as t out of it).
+ * Current values are X = X0 + dX, V = V0 + dV, t = t0 + tau, w = w0 + dw. */
+typedef struct {
+    const ostate *y0;
+    double *dX, *dV;
+    double tau, dw, drcm[3];
+} odiv;
+
+/* Scratch buffers for one leapfrog evaluation. */
+typedef struct {
+    double *rho, *ups, *acc, *phi, *dom, *vt_old, *vt_new, *Xc, *Vc;
+} oscratch;
+
+static int scratch_alloc(oscratch *s, int n) {
+    size_t b = sizeof(double) * 3 * (size_t)n;
+    s->rho = (double *)malloc(b); s->ups = (double *)malloc(b); s->acc = (double *)malloc(b);
+    s->phi = (double *)malloc(b / 3); s->dom = (double *)malloc(b);
+    s->vt_old = (double *)malloc(b); s->vt_new = (double *)malloc(b);
+    s->Xc = (double *)malloc(b); s->Vc = (double *)malloc(b);
+    return (s->rho && s->ups && s->acc && s->phi && s->dom && s->vt_old && s->vt_new && s->Xc && s->Vc)
+               ? ORC_OK : ORC_E_NOMEM;
+}
+static void scratch_free(oscratch *s) {
+    free(s->rho); free(s->ups); free(s->acc); free(s->phi); free(s->dom); free(s->vt_old); free(s->vt_new);
+    free(s->Xc); free(s->Vc);
+}
+
+/* Centre-of-mass-frame velocities from MST velocity edges V (Sec. 2.2: the
+ * velocities are transformed back to the original frame) and the kinetic
+ * energy T = 1/2 sum m |v|^2 in the COM frame (READING: B = -H is defined with
+ * the internal kinetic energy; the uniform COM motion is carried separately). */
+static double com_frame_velocities(const ostate *y, const double *V, double *ups, double *vt) {
+    const int n = y->n;
+    orc_deconstruct(n, y->parent, y->order, V, ups);
+    double ub[3];
+    com3(n, y->m, ups, ub);
+    nsum T;
+    ns_init(&T);
+    for (int i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) vt[3 * i + c] = ups[3 * i + c] - ub[c];
+        double s2 = (vt[3 * i] * vt[3 * i] + vt[3 * i + 1] * vt[3 * i + 1]) + vt[3 * i + 2] * vt[3 * i + 2];
+        ns_add(&T, y->m[i] * s2);
+    }
+    return 0.5 * ns_get(&T);
+}
+
+/* Force evaluation at positions given by edge vectors X: rho from the MST
+ * (Sec. 2.2 deconstruction), then orc_force. */
+static int eval_force(const ostate *y, const double *X, const orc_params *p, oscratch *s, double *U,
+                      double *Om) {
+    orc_deconstruct(y->n, y->parent, y->order, X, s->rho);
+    return orc_force(y->n, y->m, y->parent, y->level, X, s->rho, p, s->acc, s->phi, U, Om, s->dom);
+}
+
+static void current_X(const odiv *d, double *Xc) {
+    const int n = d->y0->n;
+    for (int k = 0; k < 3 * n; ++k) Xc[k] = d->y0->X[k] + d->dX[k];
+}
+static void current_V(const odiv *d, double *Vc) {
+    const int n = d->y0->n;
+    for (int k = 0; k < 3 * n; ++k) Vc[k] = d->y0->V[k] + d->dV[k];
+}
+
+/* Drift D(ds), Sec. 2.1 and the chained equations of Sec. 2.2:
+ * dt = ds / (alpha (T + B) + beta w + gamma);  X += dt V;  r_cm += dt v_cm;
+ * t += dt. */
+static void drift(odiv *d, const orc_params *p, oscratch *s, double ds) {
+    const ostate *y = d->y0;
+    const int n = y->n;
+    current_V(d, s->Vc);
+    double T = com_frame_velocities(y, s->Vc, s->ups, s->vt_old);
+    double w = y->w + d->dw;
+    double dt = ds / ((p->alpha * (T + y->B) + p->beta * w) + p->gamma);
+    for (int v = 0; v < n; ++v) {
+        if (y->parent[v] < 0) continue;
+        for (int c = 0; c < 3; ++c) d->dX[3 * v + c] = d->dX[3 * v + c] + dt * s->Vc[3 * v + c];
+    }
+    for (int c = 0; c < 3; ++c) d->drcm[c] = d->drcm[c] + dt * y->vcm[c];
+    d->tau = d->tau + dt;
+}
+
+/* Kick K(ds): dt = ds / (alpha U + beta Omega + gamma);  V_v += dt (a_v -
+ * a_parent(v)) (the MST analogue of A_k in eq. chained);  with beta != 0 also
+ * w += dt sum_i dOmega_i . (v_i_old + v_i_new)/2 (TTL, Mikkola & Aarseth 2002).
+ * B is unchanged without external perturbations (Sec. 2.1). */
+static int kick(odiv *d, const orc_params *p, oscratch *s, double ds, int64_t *nforce) {
+    const ostate *y = d->y0;
+    const int n = y->n;
+    double U, Om;
+    current_X(d, s->Xc);
+    int rc = eval_force(y, s->Xc, p, s, &U, &Om);
+    if (rc) return rc;
+    (*nforce)++;
+    double dt = ds / ((p->alpha * U + p->beta * Om) + p->gamma);
+    if (p->beta != 0.0) {
+        current_V(d, s->Vc);
+        com_frame_velocities(y, s->Vc, s->ups, s->vt_old);
+    }
+    for (int v = 0; v < n; ++v) {
+        int q = y->parent[v];
+        if (q < 0) continue;
+        for (int c = 0; c < 3; ++c)
+            d->dV[3 * v + c] = d->dV[3 * v + c] + dt * (s->acc[3 * v + c] - s->acc[3 * q + c]);
+    }
+    if (p->beta != 0.0) {
+        current_V(d, s->Vc);
+        com_frame_velocities(y, s->Vc, s->ups, s->vt_new);
+        nsum dw;
+        ns_init(&dw);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c)
+                ns_add(&dw, s->dom[3 * i + c] * (0.5 * (s->vt_old[3 * i + c] + s->vt_new[3 * i + c])));
+        d->dw = d->dw + dt * ns_get(&dw);
+    }
+    return ORC_OK;
+}
+
+/* Leapfrog with n substeps over the fictitious interval H (Sec. 2.3):
+ * D(H/2n) [K(H/n) D(H/n)]^(n-1) K(H/n) D(H/2n), starting from zero increments. */
+static int leapfrog(odiv *d, const orc_params *p, oscratch *s, double H, int nsub, int64_t *nforce) {
+    const int n = d->y0->n;
+    memset(d->dX, 0, sizeof(double) * 3 * (size_t)n);
+    memset(d->dV, 0, sizeof(double) * 3 * (size_t)n);
+    d->tau = 0.0; d->dw = 0.0; d->drcm[0] = d->drcm[1] = d->drcm[2] = 0.0;
+    double h = H / (double)nsub;
+    drift(d, p, s, 0.5 * h);
+    for (int k = 0; k < nsub - 1; ++k) {
+        int rc = kick(d, p, s, h, nforce);
+        if (rc) return rc;
+        drift(d, p, s, h);
+    }
+    int rc = kick(d, p, s, h, nforce);
+    if (rc) return rc;
+    drift(d, p, s, 0.5 * h);
+    return ORC_OK;
+}
+
+/* Flattened extrapolated variables: X (3n), V (3n), t, r_cm (3), w. */
+static int nvars(int n) { return 6 * n + 5; }
+static void pack_state(const ostate *y, double *out) {
+    const int n = y->n;
+    memcpy(out, y->X, sizeof(double) * 3 * (size_t)n);
+    memcpy(out + 3 * n, y->V, sizeof(double) * 3 * (size_t)n);
+    out[6 * n] = y->t;
+    out[6 * n + 1] = y->rcm[0]; out[6 * n + 2] = y->rcm[1]; out[6 * n + 3] = y->rcm[2];
+    out[6 * n + 4] = y->w;
+}
+static void pack_incr(const odiv *d, double *out) {
+    const int n = d->y0->n;
+    memcpy(out, d->dX, sizeof(double) * 3 * (size_t)n);
+    memcpy(out + 3 * n, d->dV, sizeof(double) * 3 * (size_t)n);
+    out[6 * n] = d->tau;
+    out[6 * n + 1] = d->drcm[0]; out[6 * n + 2] = d->drcm[1]; out[6 * n + 3] = d->drcm[2];
+    out[6 * n + 4] = d->dw;
+}
+/* y += increments */
+static void apply_incr(ostate *y, const double *in) {
+    const int n = y->n;
+    for (int k = 0; k < 3 * n; ++k) { y->X[k] = y->X[k] + in[k]; y->V[k] = y->V[k] + in[3 * n + k]; }
+    y->t = y->t + in[6 * n];
+    for (int c = 0; c < 3; ++c) y->rcm[c] = y->rcm[c] + in[6 * n + 1 + c];
+    y->w = y->w + in[6 * n + 4];
+}
+
+/* Aitken-Neville polynomial extrapolation to h -> 0 in the variable h^2
+ * (Sec. 2.3: the leapfrog error has only even powers; Sec. 4.2: Neville-Aitken).
+ * tab holds k_fix rows of L values (row k = result of division n_k).
+ * On return diag[k] = T_{k,k} for every k (the extrapolation using rows 0..k). */
+int orc_neville(int kf, int L, const int *nk, const double *tab, double *diag) {
+    /* column j of row k: T_{k,j+1} = T_{k,j} + (T_{k,j} - T_{k-1,j}) / ((n_k/n_{k-j})^2 - 1) */
+    double *prev = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    double *cur = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    if (!prev || !cur) { free(prev); free(cur); return ORC_E_NOMEM; }
+    /* prev = row k-1's entries T_{k-1,0..k-1}; cur = row k */
+    for (int v = 0; v < L; ++v) { prev[v] = tab[v]; diag[v] = tab[v]; }
+    for (int k = 1; k < kf; ++k) {
+        for (int v = 0; v < L; ++v) cur[v] = tab[(size_t)k * L + v];
+        for (int j = 1; j <= k; ++j) {
+            double r = (double)nk[k] / (double)nk[k - j];
+            double den = r * r - 1.0;
+            for (int v = 0; v < L; ++v) {
+                double a = cur[(size_t)(j - 1) * L + v];
+                double b = prev[(size_t)(j - 1) * L + v];
+                cur[(size_t)j * L + v] = a + (a - b) / den;
+            }
+        }
+        for (int v = 0; v < L; ++v) diag[(size_t)k * L + v] = cur[(size_t)k * L + v];
+        double *tmp = prev; prev = cur; cur = tmp;
+    }
+    free(prev); free(cur);
+    return ORC_OK;
+}
+
+/* Euclidean norm of a short vector. */
+static double norm_k(const double *a, int k) {
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s = s + a[c] * a[c];
+    return sqrt(s);
+}
+
+/* Error measure of eq. gbs-criterion (READING): for every variable group g
+ * (each X_v and each V_v as a 3-vector; t; r_cm; w when beta != 0)
+ *   eps_g = |dS_g| / |S_g(s0) + (H/n) S'_g(s0)|,
+ * skipped when the denominator is zero; eps = max_g eps_g.  A non-finite
+ * value anywhere gives eps = +inf. */
+static double gbs_error(const ostate *y0, const double *dS, const double *S0, const double *dS0ds,
+                        double hn, int beta_on) {
+    const int n = y0->n;
+    double eps = 0.0;
+    for (int g = 0; g < 2 * n + 2 + (beta_on ? 1 : 0); ++g) {
+        int off, k;
+        if (g < 2 * n) {
+            int v = g % n;
+            if (y0->parent[v] < 0) continue;
+            off = 3 * g; k = 3;   /* X rows 0..n-1, V rows n..2n-1 */
+        } else if (g == 2 * n) { off = 6 * n; k = 1; }
+        else if (g == 2 * n + 1) { off = 6 * n + 1; k = 3; }
+        else { off = 6 * n + 4; k = 1; }
+        double num[3], den[3];
+        for (int c = 0; c < k; ++c) {
+            num[c] = dS[off + c];
+            den[c] = S0[off + c] + hn * dS0ds[off + c];
+            if (!isfinite(num[c])) return INFINITY;
+        }
+        double dd = norm_k(den, k);
+        if (!(dd > 0.0)) continue;
+        double e = norm_k(num, k) / dd;
+        if (isnan(e)) return INFINITY;
+        if (e > eps) eps = e;
+    }
+    return eps;
+}
+
+/* Start-of-step quantities for eq. gbs-criterion: S(s0) and S'(s0) (one force
+ * evaluation at the start state, READING) and the force function at the start
+ * state, which the driver's end-time clip also uses (Sec. 2.4). */
+static int start_eval(ostate *y, const orc_params *p, oscratch *s, double *S0, double *dS0,
+                      double *gk_out, int64_t *nforce) {
+    const int n = y->n;
+    double U0, Om0;
+    pack_state(y, S0);
+    memset(dS0, 0, sizeof(double) * (size_t)nvars(n));
+    int rc = eval_force(y, y->X, p, s, &U0, &Om0);
+    if (rc) return rc;
+    (*nforce)++;
+    double T0 = com_frame_velocities(y, y->V, s->ups, s->vt_old);
+    double gd = (p->alpha * (T0 + y->B) + p->beta * y->w) + p->gamma;
+    double gk = (p->alpha * U0 + p->beta * Om0) + p->gamma;
+    for (int v = 0; v < n; ++v) {
+        int q = y->parent[v];
+        if (q < 0) continue;
+        for (int c = 0; c < 3; ++c) {
+            dS0[3 * v + c] = y->V[3 * v + c] / gd;
+            dS0[3 * n + 3 * v + c] = (s->acc[3 * v + c] - s->acc[3 * q + c]) / gk;
+        }
+    }
+    dS0[6 * n] = 1.0 / gd;
+    for (int c = 0; c < 3; ++c) dS0[6 * n + 1 + c] = y->vcm[c] / gd;
+    if (p->beta != 0.0) {
+        nsum dw;
+        ns_init(&dw);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) ns_add(&dw, s->dom[3 * i + c] * s->vt_old[3 * i + c]);
+        dS0[6 * n + 4] = ns_get(&dw) / gk;
+    }
+    *gk_out = gk;
+    return ORC_OK;
+}
+
+/* One GBS step (Sec. 2.3 and Sec. 4.2): all k_fix divisions n_k = 2k from the
+ * same start state, Neville-Aitken extrapolation, error test at k_fix.  On
+ * accept the state is replaced by T_{k_fix,k_fix}.  *h_next follows eq. hnext
+ * with a_GBS and the clamps [f_min, f_max] (READING); on reject it is H/2. */
+static int gbs_divisions(ostate *y, const orc_params *p, oscratch *s, double H, const double *S0,
+                         const double *dS0, int *accepted, double *eps_out, double *h_next,
+                         int64_t *nforce) {
+    const int n = y->n, kf = p->k_fix, L = nvars(n);
+    int rc;
+    double *tab = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    double *diag = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    double *Xw = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *Vw = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    int *nk = (int *)malloc(sizeof(int) * (size_t)kf);
+    if (!tab || !diag || !Xw || !Vw || !nk) { rc = ORC_E_NOMEM; goto done; }
+    for (int k = 0; k < kf; ++k) nk[k] = 2 * (k + 1);   /* Deuflhard sequence, eq. seq-deuflhard */
+    /* the k_fix divisions (independent of each other, Sec. 4.2) */
+    for (int k = 0; k < kf; ++k) {
+        odiv d;
+        d.y0 = y; d.dX = Xw; d.dV = Vw;
+        rc = leapfrog(&d, p, s, H, nk[k], nforce);
+        if (rc) goto done;
+        pack_incr(&d, tab + (size_t)k * L);
+    }
+    rc = orc_neville(kf, L, nk, tab, diag);
+    if (rc) goto done;
+    {
+        double *dS = tab; /* reuse: dS = T_{kf,kf} - T_{kf-1,kf-1} (Sec. 4.2) */
+        for (int v = 0; v < L; ++v) dS[v] = diag[(size_t)(kf - 1) * L + v] - diag[(size_t)(kf - 2) * L + v];
+        double eps = gbs_error(y, dS, S0, dS0, H / (double)nk[kf - 1], p->beta != 0.0);
+        *eps_out = eps;
+        *accepted = (eps <= p->eta);
+        if (*accepted) {
+            apply_incr(y, diag + (size_t)(kf - 1) * L);
+            double e = eps > 1e-300 ? eps : 1e-300;
+            double f = p->a_gbs * pow(p->eta / e, 1.0 / (double)(2 * kf - 1));
+            if (f < p->f_min) f = p->f_min;
+            if (f > p->f_max) f = p->f_max;
+            *h_next = H * f;
+        } else {
+            *h_next = 0.5 * H;
+        }
+    }
+    rc = ORC_OK;
+done:
+    free(tab); free(diag); free(Xw); free(Vw); free(nk);
+    return rc;
+}
+
+static int gbs_step(ostate *y, const orc_params *p, oscratch *s, double H, int *accepted,
+                    double *eps_out, double *h_next, int64_t *nforce) {
+    const int L = nvars(y->n);
+    double *S0 = (double *)malloc(sizeof(double) * (size_t)L);
+    double *dS0 = (double *)malloc(sizeof(double) * (size_t)L);
+    double gk;
+    int rc = (S0 && dS0) ? ORC_OK : ORC_E_NOMEM;
+    if (!rc) rc = start_eval(y, p, s, S0, dS0, &gk, nforce);
+    if (!rc) rc = gbs_divisions(y, p, s, H, S0, dS0, accepted, eps_out, h_next, nforce);
+    free(S0); free(dS0);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exported single-stage entry points (state passed as arrays; scal holds
+ * t, B, w, r_cm[3], v_cm[3]). */
+
+static int make_state(ostate *y, int n, const double *m, int *parent, int *level, int *order,
+                      double *X, double *V, const double *scal) {
+    y->n = n; y->m = m; y->parent = parent; y->level = level; y->order = order;
+    y->X = X; y->V = V;
+    if (orc_tree_levels(n, parent, level, order) < 0) return ORC_E_INVAL;
+    y->t = scal[0]; y->B = scal[1]; y->w = scal[2];
+    for (int c = 0; c < 3; ++c) { y->rcm[c] = scal[3 + c]; y->vcm[c] = scal[6 + c]; }
+    return ORC_OK;
+}
+static void store_scal(const ostate *y, double *scal) {
+    scal[0] = y->t; scal[1] = y->B; scal[2] = y->w;
+    for (int c = 0; c < 3; ++c) { scal[3 + c] = y->rcm[c]; scal[6 + c] = y->vcm[c]; }
+}
+
+/* Force with MST separations given parent[], edge vectors X and rho. */
+int orc_force_tree(int n, const double *m, const int *parent, const double *X, const double *rho,
+                   const orc_params *p, double *acc, double *phi, double *U, double *Om, double *dOm) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!level || !order) { free(level); free(order); return ORC_E_NOMEM; }
+    int rc = orc_tree_levels(n, parent, level, order) < 0 ? ORC_E_INVAL : ORC_OK;
+    if (!rc) rc = orc_force(n, m, parent, level, X, rho, p, acc, phi, U, Om, dOm);
+    free(level); free(order);
+    return rc;
+}
+
+/* One leapfrog division with nsub substeps over H, in place. */
+int orc_leapfrog(int n, const double *m, int *parent, double *X, double *V, double *scal,
+                 const orc_params *p, double H, int nsub, int64_t *nforce) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    oscratch s;
+    int rc = scratch_alloc(&s, n);
+    ostate y;
+    double *dX = (double *)malloc(sizeof(double) * 3 * (size_t)n), *dV = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *inc = (double *)malloc(sizeof(double) * (size_t)nvars(n));
+    if (!rc && (!level || !order || !dX || !dV || !inc)) rc = ORC_E_NOMEM;
+    if (!rc) rc = make_state(&y, n, m, parent, level, order, X, V, scal);
+    if (!rc) {
+        odiv d;
+        d.y0 = &y; d.dX = dX; d.dV = dV;
+        rc = leapfrog(&d, p, &s, H, nsub, nforce);
+        if (!rc) { pack_incr(&d, inc); apply_incr(&y, inc); }
+    }
+    if (!rc) store_scal(&y, scal);
+    free(dX); free(dV); free(inc);
+    scratch_free(&s); free(level); free(order);
+    return rc;
+}
+
+/* One GBS step, in place on accept. */
+int orc_gbs_step(int n, const double *m, int *parent, double *X, double *V, double *scal,
+                 const orc_params *p, double H, int *accepted, double *eps, double *h_next,
+                 int64_t *nforce) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    oscratch s;
+    int rc = scratch_alloc(&s, n);
+    ostate y;
+    if (!rc && (!level || !order)) rc = ORC_E_NOMEM;
+    if (!rc) rc = make_state(&y, n, m, parent, level, order, X, V, scal);
+    if (!rc) rc = gbs_step(&y, p, &s, H, accepted, eps, h_next, nforce);
+    if (!rc) store_scal(&y, scal);
+    scratch_free(&s); free(level); free(order);
+    return rc;
+}
+
+/* Neville extrapolation exported for tests: tab[kf][L] -> diag[kf][L]. */
+int orc_neville_export(int kf, int L, const double *tab, double *diag) {
+    int nk[64];
+    if (kf < 1 || kf > 64) return ORC_E_INVAL;
+    for (int k = 0; k < kf; ++k) nk[k] = 2 * (k + 1);
+    return orc_neville(kf, L, nk, tab, diag);
+}
+
+/* Build the MST state from Cartesian x, v (Sec. 3.2, 3.4): root nearest the
+ * COM, Prim tree, edge vectors X_v = x_v - x_parent, V_v likewise. */
+int orc_build_state(int n, const double *m, const double *x, const double *v,
+                    int *parent, double *X, double *V, double *scal) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!level || !order) { free(level); free(order); return ORC_E_NOMEM; }
+    int root = orc_root_nearest_com(n, m, x);
+    int rc = orc_mst_prim(n, x, root, parent, level, order);
+    if (!rc) {
+        for (int c = 0; c < 3; ++c) { X[3 * root + c] = 0.0; V[3 * root + c] = 0.0; }
+        for (int u = 0; u < n; ++u) {
+            int q = parent[u];
+            if (q < 0) continue;
+            for (int c = 0; c < 3; ++c) {
+                X[3 * u + c] = x[3 * u + c] - x[3 * q + c];
+                V[3 * u + c] = v[3 * u + c] - v[3 * q + c];
+            }
+        }
+        double rc3[3], vc3[3];
+        com3(n, m, x, rc3);
+        com3(n, m, v, vc3);
+        scal[0] = 0.0; scal[1] = 0.0; scal[2] = 0.0;
+        for (int c = 0; c < 3; ++c) { scal[3 + c] = rc3[c]; scal[6 + c] = vc3[c]; }
+    }
+    free(level); free(order);
+    return rc;
+}
+
+/* Cartesian positions and velocities from the MST state (Sec. 2.2 deconstruction):
+ * x_i = r_cm + (rho_i - rho_bar), v_i = v_cm + (ups_i - ups_bar). */
+int orc_state_to_cartesian(int n, const double *m, const int *parent, const double *X, const double *V,
+                           const double *scal, double *x, double *v) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    double *rho = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!level || !order || !rho) { free(level); free(order); free(rho); return ORC_E_NOMEM; }
+    int rc = orc_tree_levels(n, parent, level, order) < 0 ? ORC_E_INVAL : ORC_OK;
+    if (!rc) {
+        double c[3];
+        orc_deconstruct(n, parent, order, X, rho);
+        com3(n, m, rho, c);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) x[3 * i + k] = scal[3 + k] + (rho[3 * i + k] - c[k]);
+        orc_deconstruct(n, parent, order, V, rho);
+        com3(n, m, rho, c);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) v[3 * i + k] = scal[6 + k] + (rho[3 * i + k] - c[k]);
+    }
+    free(level); free(order); free(rho);
+    return rc;
+}
+
+/* MST rebuild during integration (Sec. 3.5: the structure is built,
+ * deconstructed and rebuilt).  New tree from rho (root nearest the COM of rho);
+ * READING: the edge vector of each new tree edge (q -> u) is the separation the
+ * old tree gives for that pair under the close-pair rule (so edges that persist
+ * keep their bits, a reversed edge is negated exactly, and only genuinely new
+ * far pairs fall back to rho_u - rho_q).  Velocities likewise.  Returns 1 if the
+ * parent array changed. */
+static int rebuild(ostate *y, const orc_params *p, oscratch *s, int *topo_changed) {
+    const int n = y->n;
+    int *np = (int *)malloc(sizeof(int) * (size_t)n), *nl = (int *)malloc(sizeof(int) * (size_t)n);
+    int *no = (int *)malloc(sizeof(int) * (size_t)n);
+    double *nX = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *nV = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!np || !nl || !no || !nX || !nV) { free(np); free(nl); free(no); free(nX); free(nV); return ORC_E_NOMEM; }
+    orc_deconstruct(n, y->parent, y->order, y->X, s->rho);
+    orc_deconstruct(n, y->parent, y->order, y->V, s->ups);
+    int root = orc_root_nearest_com(n, y->m, s->rho);
+    int rc = orc_mst_prim(n, s->rho, root, np, nl, no);
+    if (rc) goto out;
+    int changed = 0;
+    for (int u = 0; u < n; ++u) if (np[u] != y->parent[u]) { changed = 1; break; }
+    *topo_changed = changed;
+    if (changed) {
+        for (int u = 0; u < n; ++u) {
+            int q = np[u];
+            if (q < 0) { for (int c = 0; c < 3; ++c) { nX[3 * u + c] = 0.0; nV[3 * u + c] = 0.0; } continue; }
+            orc_separation(q, u, y->parent, y->level, y->X, s->rho, p->n_d, nX + 3 * u);
+            orc_separation(q, u, y->parent, y->level, y->V, s->ups, p->n_d, nV + 3 * u);
+        }
+        memcpy(y->parent, np, sizeof(int) * (size_t)n);
+        memcpy(y->level, nl, sizeof(int) * (size_t)n);
+        memcpy(y->order, no, sizeof(int) * (size_t)n);
+        memcpy(y->X, nX, sizeof(double) * 3 * (size_t)n);
+        memcpy(y->V, nV, sizeof(double) * 3 * (size_t)n);
+    }
+out:
+    free(np); free(nl); free(no); free(nX); free(nV);
+    return rc;
+}
+
+static int all_finite(int k, const double *a) {
+    for (int i = 0; i < k; ++i) if (!isfinite(a[i])) return 0;
+    return 1;
+}
+
+/* The driver (Sec. 2.4): integrate from t0 to t_end in physical time.
+ * First step ds = q U dt (eq. t-aika times a safety factor).  Before each step
+ * the predicted end time tau + ds/(alpha U + beta Omega + gamma) is compared
+ * with t_end and the step is clipped to land on it; an overshoot is undone with
+ * a step of negative ds (the leapfrog is time symmetric), until
+ * |t_end - tau| <= t_tol |t_end - t0| or max_time_iter extra steps were taken.
+ * Unconverged GBS steps are halved (Sec. 2.3).  x, v are replaced by the state
+ * at t_reached. */
+int orc_integrate(int n, const double *m, double *x, double *v, double t0, double t_end,
+                  const orc_params *p, orc_stats *st) {
+    memset(st, 0, sizeof(*st));
+    st->t_reached = t0;
+    if (n < 2 || p->k_fix < 2 || p->k_fix > 32 || p->n_d < 0 || p->n_d > 8 || !(p->eta > 0.0) ||
+        !(p->G > 0.0) || !(t_end != t0) || !isfinite(t0) || !isfinite(t_end))
+        return ORC_E_INVAL;
+    for (int i = 0; i < n; ++i) if (!(m[i] > 0.0) || !isfinite(m[i])) return ORC_E_INVAL;
+    if (!all_finite(3 * n, x) || !all_finite(3 * n, v)) return ORC_E_NONFINITE;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (edge_w(x + 3 * i, x + 3 * j) == 0.0) return ORC_E_COINCIDENT;
+
+    int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    double *X = (double *)malloc(sizeof(double) * 3 * (size_t)n), *V = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double scal[9];
+    oscratch s;
+    int rc = scratch_alloc(&s, n);
+    if (!rc && (!parent || !level || !order || !X || !V)) rc = ORC_E_NOMEM;
+    if (rc) goto out;
+    rc = orc_build_state(n, m, x, v, parent, X, V, scal);
+    if (rc) goto out;
+    ostate y;
+    make_state(&y, n, m, parent, level, order, X, V, scal);
+    y.t = t0;
+    {
+        double U0, Om0;
+        rc = eval_force(&y, y.X, p, &s, &U0, &Om0);
+        if (rc) goto out;
+        st->force_evals++;
+        double T0 = com_frame_velocities(&y, y.V, s.ups, s.vt_old);
+        y.B = U0 - T0;                 /* B = -H = -(T - U) */
+        y.w = Om0;
+        double gk = (p->alpha * U0 + p->beta * Om0) + p->gamma;
+        double H = p->h_init > 0.0 ? p->h_init : p->q_first * gk * (t_end - t0);
+        const double span = fabs(t_end - t0);
+        const int L = nvars(n);
+        double *S0 = (double *)malloc(sizeof(double) * (size_t)L);
+        double *dS0 = (double *)malloc(sizeof(double) * (size_t)L);
+        int halvings = 0, since_rebuild = 0, fresh = 1;
+        int64_t iters = 0;
+        if (!S0 || !dS0) rc = ORC_E_NOMEM;
+        while (!rc) {
+            if (st->steps_accepted + st->steps_rejected >= p->max_steps) { rc = ORC_E_MAXSTEPS; break; }
+            if (fresh) {
+                if (since_rebuild >= p->rebuild_every) {
+                    int ch = 0;
+                    rc = rebuild(&y, p, &s, &ch);
+                    if (rc) break;
+                    st->mst_rebuilds++;
+                    st->topo_changes += ch;
+                    since_rebuild = 0;
+                }
+                rc = start_eval(&y, p, &s, S0, dS0, &gk, &st->force_evals);
+                if (rc) break;
+                fresh = 0;
+            }
+            /* end-time clip with the force function at the step start (Sec. 2.4) */
+            double rem = t_end - y.t;
+            double dt_est = H / gk;
+            int clipped = 0;
+            if (dt_est / rem > 1.0 || dt_est / rem < 0.0) { H = gk * rem; clipped = 1; }
+            int acc = 0;
+            double eps = 0.0, hn = 0.0;
+            rc = gbs_divisions(&y, p, &s, H, S0, dS0, &acc, &eps, &hn, &st->force_evals);
+            if (rc) break;
+            st->eps_last = eps;
+            if (!acc) {
+                st->steps_rejected++;
+                if (++halvings > p->max_halvings) { rc = ORC_E_NOCONV; break; }
+                H = hn;
+                continue;
+            }
+            st->steps_accepted++;
+            st->h_last = H;
+            halvings = 0;
+            since_rebuild++;
+            fresh = 1;
+            if (clipped) iters++;
+            H = hn;
+            st->h_next = hn;
+            if (fabs(t_end - y.t) <= p->t_tol * span) { rc = ORC_OK; break; }
+            if (iters > p->max_time_iter) { rc = ORC_W_TIME_TOL; break; }
+        }
+        free(S0); free(dS0);
+        st->time_iters = iters;
+    }
+    st->t_reached = y.t;
+    if (rc == ORC_OK || rc == ORC_W_TIME_TOL || rc == ORC_E_NOCONV || rc == ORC_E_MAXSTEPS) {
+        store_scal(&y, scal);
+        orc_state_to_cartesian(n, m, parent, X, V, scal, x, v);
+    }
+out:
+    scratch_free(&s);
+    free(parent); free(level); free(order); free(X); free(V);
+    return rc;
+}
+
+/* Plain Cartesian diagnostics (Sec. 5.1): E = T - U, total momentum P and
+ * angular momentum L = sum m r x v, Neumaier sums in index order. */
+void orc_diagnostics(int n, const double *m, const double *x, const double *v, double G, double *out) {
+    nsum T, U, P[3], L[3];
+    ns_init(&T); ns_init(&U);
+    for (int c = 0; c < 3; ++c) { ns_init(&P[c]); ns_init(&L[c]); }
+    for (int i = 0; i < n; ++i) {
+        const double *xi = x + 3 * i, *vi = v + 3 * i;
+        ns_add(&T, 0.5 * m[i] * ((vi[0] * vi[0] + vi[1] * vi[1]) + vi[2] * vi[2]));
+        for (int c = 0; c < 3; ++c) ns_add(&P[c], m[i] * vi[c]);
+        ns_add(&L[0], m[i] * (xi[1] * vi[2] - xi[2] * vi[1]));
+        ns_add(&L[1], m[i] * (xi[2] * vi[0] - xi[0] * vi[2]));
+        ns_add(&L[2], m[i] * (xi[0] * vi[1] - xi[1] * vi[0]));
+        for (int j = i + 1; j < n; ++j) ns_add(&U, G * m[i] * m[j] / sqrt(edge_w(xi, x + 3 * j)));
+    }
+    out[0] = ns_get(&T) - ns_get(&U);
+    out[1] = ns_get(&T);
+    out[2] = ns_get(&U);
+    for (int c = 0; c < 3; ++c) { out[3 + c] = ns_get(&P[c]); out[6 + c] = ns_get(&L[c]); }
+}
+
+/* Greedy assignment of substep divisions to groups (Sec. 4.2): largest n_k first
+ * to the least-loaded group, ties to the lowest group index.  Returns
+ * S_div = sum n_k / max_i C_i (eq. speedup-div); group[k] receives the group
+ * of division k. */
+double orc_sdiv(int kf, int ndiv, int *group) {
+    int64_t C[64] = {0};
+    int64_t total = 0;
+    if (ndiv < 1 || ndiv > 64) return 0.0;
+    for (int k = kf; k >= 1; --k) {
+        int nkk = 2 * k;
+        int g = 0;
+        for (int q = 1; q < ndiv; ++q) if (C[q] < C[g]) g = q;
+        C[g] += nkk;
+        total += nkk;
+        if (group) group[k - 1] = g;
+    }
+    int64_t mx = 0;
+    for (int q = 0; q < ndiv; ++q) if (C[q] > mx) mx = C[q];
+    return (double)total / (double)mx;
+}
