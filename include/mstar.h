@@ -1,0 +1,167 @@
+/*
+ * mstar.h -- C ABI of the MI355X (gfx950) FP64 implementation of the MSTAR
+ * algorithmically regularised integrator with minimum-spanning-tree
+ * coordinates (Rantala, Pihajoki, Mannerkoski, Johansson & Naab 2020).
+ *
+ * The problem statement follows the paper (Sec. 2.4): masses, positions and
+ * velocities at t0 in, the state at t_end out, with the GBS tolerance eta
+ * (eq. gbs-criterion) as the accuracy parameter.  Every step of the method
+ * runs in this library's HIP kernels; the host only sequences launches and
+ * makes the accept/halve decision from a few scalars read back per step.
+ *
+ * Conventions for every entry point:
+ *  - FP64 throughout; G = params->G.
+ *  - Array arguments are caller-owned, read or written only during the call,
+ *    never retained.  With MSTAR_DEVICE_PTRS in params->flags (or the
+ *    `flags` argument of a stage call) they are device pointers on the
+ *    context's device (e.g. contiguous float64 torch tensors); otherwise host
+ *    pointers.  Vectors are [n][3] row-major (x, y, z of body i at 3i..3i+2).
+ *  - MST state arrays: parent[n] (int32, the root has -1); X[n][3], V[n][3]
+ *    with row v holding the edge vector from parent(v) to v (root row 0).
+ *  - Return value: MSTAR_OK (0), a negative MSTAR_E_* code, or the positive
+ *    warning MSTAR_W_TIME_TOL.  Validation errors leave outputs untouched;
+ *    runtime errors of mstar_integrate leave the last accepted state in x, v
+ *    with stats->t_reached set.  No exception or abort crosses the ABI.
+ *  - A context is not thread-safe; distinct contexts are independent.  Work
+ *    is enqueued on the context's stream; calls return after completion.
+ *  - Same inputs, parameters and device give bitwise identical outputs.
+ */
+#ifndef MSTAR_H
+#define MSTAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSTAR_ABI_VERSION 1
+
+#define MSTAR_OK 0
+#define MSTAR_E_INVAL -1       /* invalid argument or parameter */
+#define MSTAR_E_NOMEM -2       /* device or host allocation failed */
+#define MSTAR_E_DEVICE -3      /* HIP runtime error */
+#define MSTAR_E_NONFINITE -4   /* NaN/Inf in the inputs */
+#define MSTAR_E_COINCIDENT -5  /* two bodies at the same position */
+#define MSTAR_E_NOCONV -6      /* GBS did not converge within max_halvings */
+#define MSTAR_E_MAXSTEPS -7    /* max_steps GBS steps taken before t_end */
+#define MSTAR_E_UNSUPPORTED -8 /* valid for the method but not implemented here */
+#define MSTAR_W_TIME_TOL 1     /* t_end not met within t_tol after max_time_iter clipped steps */
+
+#define MSTAR_DEVICE_PTRS 1u   /* array arguments are device pointers */
+
+/* Parameters of the method.  struct_size must be sizeof(mstar_params);
+ * mstar_params_default fills every field. */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t flags;         /* MSTAR_DEVICE_PTRS */
+    double G;               /* gravitational constant (Sec. 2.1) */
+    double eta;             /* GBS tolerance eta_GBS, eq. gbs-criterion; default 1e-12 */
+    double alpha, beta, gamma; /* time-transformation triplet, eq. ttl; default LogH (1,0,0) */
+    double omega_mass_max;  /* TTL Omega couples bodies with m <= this (beta != 0) */
+    double a_gbs;           /* safety factor of eq. hnext; default 0.9 */
+    double f_min, f_max;    /* clamps of the eq. hnext step ratio; default 0.1, 4 */
+    double q_first;         /* first step ds = q U dt (Sec. 2.4); default 0.1 */
+    double t_tol;           /* stop when |t_end - t| <= t_tol |t_end - t0|; default 1e-14 */
+    double h_init;          /* > 0: first fictitious step; 0: automatic */
+    int64_t max_steps;      /* GBS step attempts (accepted + rejected) */
+    int32_t k_fix;          /* substep divisions n_k = 2k, k = 1..k_fix (Sec. 4.2); 2..16, default 8 */
+    int32_t n_d;            /* MST closeness N_d of eq. LCA; 0..2 here, default 2 */
+    int32_t max_halvings;   /* consecutive rejections before MSTAR_E_NOCONV; default 60 */
+    int32_t max_time_iter;  /* clipped end-time steps before MSTAR_W_TIME_TOL; default 8 */
+    int32_t rebuild_every;  /* accepted steps between MST rebuilds (Sec. 3.5); default 1 */
+    int32_t reserved;
+} mstar_params;
+
+/* Per-call statistics. */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    int64_t steps_accepted, steps_rejected;
+    int64_t force_evals;    /* full O(N^2) force evaluations */
+    int64_t mst_rebuilds, topo_changes, time_iters;
+    double t_reached;       /* physical time of the returned state */
+    double eps_last;        /* error measure of the last GBS step */
+    double h_next;          /* suggested next fictitious step (pass as h_init to continue) */
+    double h_last;          /* last accepted fictitious step */
+} mstar_stats;
+
+typedef struct mstar_ctx mstar_ctx;
+
+/* Version of this ABI (MSTAR_ABI_VERSION). */
+int mstar_abi_version(void);
+
+/* Fill *p with the defaults listed above; sets p->struct_size. */
+void mstar_params_default(mstar_params *p);
+
+/* Static string for a return code. */
+const char *mstar_strerror(int code);
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * to enqueue work on, or NULL for a stream owned by the context.  Device
+ * scratch is allocated on demand and kept until mstar_destroy.
+ * Errors: MSTAR_E_INVAL (bad device), MSTAR_E_DEVICE, MSTAR_E_NOMEM. */
+int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream);
+
+/* Free the context and its device memory.  NULL is allowed. */
+void mstar_destroy(mstar_ctx *ctx);
+
+/* Message of the last error on ctx (context-owned, valid until the next call). */
+const char *mstar_last_error(const mstar_ctx *ctx);
+
+/* Integrate n bodies from t0 to t_end (paper Sec. 2.4 driver; Sec. 2.3 GBS
+ * with the Deuflhard sequence; Sec. 3 MST coordinates).  x, v [n][3] are read
+ * at t0 and overwritten with the state at stats->t_reached.  m [n] > 0.
+ * Errors: MSTAR_E_INVAL (n < 2, bad masses or parameters), MSTAR_E_NONFINITE,
+ * MSTAR_E_COINCIDENT, MSTAR_E_NOCONV, MSTAR_E_MAXSTEPS, MSTAR_E_UNSUPPORTED
+ * (beta != 0 or n_d > 2), device errors; warning MSTAR_W_TIME_TOL. */
+int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
+                    double *x, double *v, double t0, double t_end, mstar_stats *stats);
+
+/* ---- stage entry points (each is one row of the method; used by parity
+ * tests, the benchmark and callers that drive the steps themselves) ---- */
+
+/* Minimum spanning tree (Sec. 3.1-3.4) of the complete graph on positions
+ * x [n][3] under the strict edge order (w = |x_j - x_i|^2 evaluated as
+ * (dx*dx + dy*dy) + dz*dz without fused multiply-add, then min index, then max
+ * index), rooted at the body nearest the centre of mass of masses m (ties to
+ * the lowest index), or at `root_in` if 0 <= root_in < n.  Outputs parent[n]
+ * (root -1), level[n] (root 0) and *root_out.  Host or device pointers per
+ * `flags`. */
+int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x,
+                    int32_t root_in, int32_t *parent, int32_t *level, int32_t *root_out);
+
+/* Accelerations and force function with MST separations (Sec. 2.1 and the
+ * close-pair rule of Sec. 3.4): acc[n][3] = G sum_j m_j d_ij/|d_ij|^3 and
+ * *U = G sum_{i<j} m_i m_j/|d_ij|, where d_ij is the MST path sum of the edge
+ * vectors X for pairs within params->n_d tree edges and rho_j - rho_i
+ * otherwise.  rho [n][3] are positions in any frame consistent with X. */
+int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
+                const double *rho, const int32_t *parent, const double *X, double *acc, double *U);
+
+/* One leapfrog division over the fictitious interval H with nsub substeps,
+ * D(H/2n)[K(H/n)D(H/n)]^(n-1)K(H/n)D(H/2n) (Sec. 2.3), on the MST state
+ * (parent, X, V) with scal[9] = (t, B, w, r_cm[3], v_cm[3]); X, V, scal are
+ * updated in place.  B must be the binding energy -H of the state. */
+int mstar_leapfrog(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
+                   const int32_t *parent, double *X, double *V, double *scal, double H, int32_t nsub);
+
+/* One GBS step of fictitious length H (Sec. 2.3, 4.2): k_fix divisions from
+ * the same start state, Neville-Aitken extrapolation, error test.  If
+ * *accepted, X, V, scal hold the extrapolated state; otherwise they are
+ * unchanged.  *eps is the error measure, *h_next the next step (eq. hnext on
+ * acceptance, H/2 on rejection).  No MST rebuild is done here. */
+int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
+                   const int32_t *parent, double *X, double *V, double *scal, double H,
+                   int32_t *accepted, double *eps, double *h_next);
+
+/* Force-kernel timing for measurement: when enabled, every force-kernel
+ * launch is bracketed by HIP events on the context stream; the totals cover
+ * all launches since the last reset. */
+int mstar_profile_enable(mstar_ctx *ctx, int enable);
+int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSTAR_H */

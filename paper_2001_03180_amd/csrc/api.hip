@@ -1,0 +1,682 @@
+// Host side of the C ABI declared in include/mstar.h: context, device
+// workspace, validation, and the sequencing of kernel launches that makes up
+// the integrator (paper Sec. 2.3 GBS step, Sec. 2.4 driver, Sec. 3.5 MST
+// rebuilds, Sec. 4.2 concurrent substep divisions).
+//
+// All substep divisions of a GBS step advance together: at substep s every
+// division that still has a kick left is drifted, has its forces evaluated
+// and is kicked in one launch per stage, so the number of dependent launches
+// per GBS step is 3 * 2 k_fix + O(1) and the force launches carry up to
+// k_fix independent O(N^2) evaluations.  The host reads back one small
+// control block per GBS step to decide acceptance and the next step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mstar.h"
+#include "common.h"
+
+using namespace mstar;
+
+struct mstar_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    Dev d{};
+    int cap_n = 0;
+    std::vector<void *> allocs;
+    double *xin = nullptr, *vin = nullptr, *xout = nullptr;   // staging [3n]
+    Ctl *h_ctl = nullptr;       // pinned host copies
+    SysScal *h_sys = nullptr;
+    // profiling of the force kernel
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t ev_used = 0;
+    int64_t prof_launches = 0;
+    double prof_pairs = 0.0;
+};
+
+namespace {
+
+constexpr int kNsplitMax = 32;
+constexpr int kTargetWG = 2560;
+
+int fail(mstar_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCK(x)                                                                          \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(ctx, MSTAR_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dalloc(mstar_ctx *ctx, T **p, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * (count ? count : 1)) != hipSuccess) {
+        *p = nullptr;
+        return fail(ctx, MSTAR_E_NOMEM, "device allocation of %zu bytes failed", sizeof(T) * count);
+    }
+    ctx->allocs.push_back(q);
+    *p = (T *)q;
+    return MSTAR_OK;
+}
+
+void free_workspace(mstar_ctx *ctx) {
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    ctx->allocs.clear();
+    ctx->d = Dev{};
+    ctx->cap_n = 0;
+}
+
+int ensure(mstar_ctx *ctx, int n) {
+    if (n <= ctx->cap_n) {
+        ctx->d.n = n;
+        ctx->d.nib = (n + 63) / 64;
+        ctx->d.nkwg = (n + kWG - 1) / kWG;
+        return MSTAR_OK;
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    free_workspace(ctx);
+    const int cap = std::max(n, 64);
+    const size_t N = (size_t)cap;
+    const int nib = (cap + 63) / 64, nkwg = (cap + kWG - 1) / kWG;
+    Dev &d = ctx->d;
+    int rc = 0;
+#define A(ptr, cnt) \
+    if ((rc = dalloc(ctx, &(ptr), (cnt))) != MSTAR_OK) { free_workspace(ctx); return rc; }
+    A(d.parent, N) A(d.level, N) A(d.parent_new, N) A(d.level_new, N) A(d.child_off, N + 1) A(d.child_idx, N)
+    A(d.root, 1) A(d.X0, N) A(d.V0, N) A(d.a0, N) A(d.m, N) A(d.sys, 1) A(d.ctl, 1)
+    A(d.P, kMaxDiv * N) A(d.Vt, kMaxDiv * N) A(d.dX, kMaxDiv * N) A(d.dV, kMaxDiv * N) A(d.dX1, N) A(d.dV1, N)
+    A(d.dscal, kMaxDiv) A(d.dscal1, 1) A(d.part, (size_t)kMaxDiv * kNsplitMax * N)
+    A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * nkwg) A(d.epspart, nkwg + 1)
+    A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)
+    A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.comp, N) A(d.ecomp_tmp, N)
+    A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.done, 1) A(d.ncomp, 1)
+    A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
+    A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N)
+    A(ctx->xin, 3 * N) A(ctx->vin, 3 * N) A(ctx->xout, 3 * N)
+#undef A
+    HIPCK(hipMemsetAsync(d.dX, 0, sizeof(d4) * kMaxDiv * N, ctx->stream));
+    HIPCK(hipMemsetAsync(d.dV, 0, sizeof(d4) * kMaxDiv * N, ctx->stream));
+    HIPCK(hipMemsetAsync(d.ctl, 0, sizeof(Ctl), ctx->stream));
+    HIPCK(hipMemsetAsync(d.sys, 0, sizeof(SysScal), ctx->stream));
+    d.kfmax = kMaxDiv;
+    d.nsplit_max = kNsplitMax;
+    ctx->cap_n = cap;
+    d.n = n;
+    d.nib = (n + 63) / 64;
+    d.nkwg = (n + kWG - 1) / kWG;
+    return MSTAR_OK;
+}
+
+constexpr int kBase = kMaxDiv - 1;   // slot of the start state
+
+int nsplit_for(const Dev &d, int nact) {
+    int ns = (kTargetWG + nact * d.nib - 1) / (nact * d.nib);
+    ns = std::max(1, std::min(ns, kNsplitMax));
+    ns = std::min(ns, std::max(1, d.n / 64));
+    return ns;
+}
+
+int check_params(mstar_ctx *ctx, const mstar_params *p) {
+    if (!p || p->struct_size != sizeof(mstar_params)) return fail(ctx, MSTAR_E_INVAL, "params: bad struct_size");
+    if (!(p->G > 0.0) || !std::isfinite(p->G)) return fail(ctx, MSTAR_E_INVAL, "params: G must be > 0");
+    if (!(p->eta > 0.0)) return fail(ctx, MSTAR_E_INVAL, "params: eta must be > 0");
+    if (p->k_fix < 2 || p->k_fix > 16) return fail(ctx, MSTAR_E_INVAL, "params: k_fix must be in [2, 16]");
+    if (p->n_d < 0) return fail(ctx, MSTAR_E_INVAL, "params: n_d must be >= 0");
+    if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: n_d > 2 is not implemented on the GPU");
+    if (p->beta != 0.0) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: beta != 0 (TTL Omega) is not implemented on the GPU");
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->gamma) || p->alpha < 0.0 || p->gamma < 0.0 ||
+        (p->alpha == 0.0 && p->gamma == 0.0))
+        return fail(ctx, MSTAR_E_INVAL, "params: need alpha, gamma >= 0, not both zero");
+    if (!(p->a_gbs > 0.0) || !(p->f_min > 0.0) || !(p->f_max >= p->f_min) || !(p->q_first > 0.0) ||
+        !(p->t_tol >= 0.0) || p->max_steps < 1 || p->max_halvings < 0 || p->max_time_iter < 0 ||
+        p->rebuild_every < 0 || !(p->h_init >= 0.0))
+        return fail(ctx, MSTAR_E_INVAL, "params: out of range");
+    return MSTAR_OK;
+}
+
+bool is_dev(uint32_t flags) { return (flags & MSTAR_DEVICE_PTRS) != 0; }
+
+// Bring an input array to the device: copy host memory into `stage`, or use a
+// device pointer as is.
+int in_dev(mstar_ctx *ctx, uint32_t flags, const void *src, void *stage, size_t bytes, const void **out) {
+    if (is_dev(flags)) {
+        *out = src;
+        return MSTAR_OK;
+    }
+    HIPCK(hipMemcpyAsync(stage, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    *out = stage;
+    return MSTAR_OK;
+}
+
+int out_copy(mstar_ctx *ctx, uint32_t flags, void *dst, const void *devsrc, size_t bytes) {
+    HIPCK(hipMemcpyAsync(dst, devsrc, bytes, is_dev(flags) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                         ctx->stream));
+    return MSTAR_OK;
+}
+
+bool finite_host(const double *a, size_t k) {
+    for (size_t i = 0; i < k; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+// Validate masses / positions / velocities (host copies) and copy masses.
+int load_bodies(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x, const double *v) {
+    std::vector<double> hm((size_t)n), hx, hv;
+    if (is_dev(flags)) {
+        HIPCK(hipMemcpy(hm.data(), m, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (x) { hx.resize(3 * (size_t)n); HIPCK(hipMemcpy(hx.data(), x, sizeof(double) * 3 * n, hipMemcpyDeviceToHost)); }
+        if (v) { hv.resize(3 * (size_t)n); HIPCK(hipMemcpy(hv.data(), v, sizeof(double) * 3 * n, hipMemcpyDeviceToHost)); }
+    } else {
+        memcpy(hm.data(), m, sizeof(double) * n);
+        if (x) hx.assign(x, x + 3 * n);
+        if (v) hv.assign(v, v + 3 * n);
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (!(hm[i] > 0.0) || !std::isfinite(hm[i])) return fail(ctx, MSTAR_E_INVAL, "mass %lld is not > 0", (long long)i);
+    if ((x && !finite_host(hx.data(), hx.size())) || (v && !finite_host(hv.data(), hv.size())))
+        return fail(ctx, MSTAR_E_NONFINITE, "non-finite position or velocity");
+    HIPCK(hipMemcpyAsync(ctx->d.m, hm.data(), sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+// Check that parent[] is one rooted tree; copy it to the device.
+int load_tree(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent) {
+    std::vector<int32_t> hp((size_t)n);
+    if (is_dev(flags)) HIPCK(hipMemcpy(hp.data(), parent, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    else memcpy(hp.data(), parent, sizeof(int32_t) * n);
+    int roots = 0;
+    std::vector<int8_t> state((size_t)n, 0);   // 0 unknown, 1 in progress, 2 reaches root
+    for (int64_t v = 0; v < n; ++v) {
+        if (hp[v] < 0) { ++roots; continue; }
+        if (hp[v] >= n || hp[v] == v) return fail(ctx, MSTAR_E_INVAL, "parent[%lld] invalid", (long long)v);
+    }
+    if (roots != 1) return fail(ctx, MSTAR_E_INVAL, "parent[] must have exactly one root");
+    for (int64_t v = 0; v < n; ++v) {
+        std::vector<int32_t> path;
+        int64_t u = v;
+        while (u >= 0 && state[u] == 0) { state[u] = 1; path.push_back((int32_t)u); u = hp[u]; }
+        if (u >= 0 && state[u] == 1) return fail(ctx, MSTAR_E_INVAL, "parent[] has a cycle");
+        for (int32_t w : path) state[w] = 2;
+    }
+    HIPCK(hipMemcpyAsync(ctx->d.parent, hp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit) {
+    if (ctx->prof) {
+        if (ctx->ev_used == ctx->ev.size()) {
+            hipEvent_t a, b;
+            HIPCK(hipEventCreate(&a));
+            HIPCK(hipEventCreate(&b));
+            ctx->ev.push_back({a, b});
+        }
+        auto &e = ctx->ev[ctx->ev_used++];
+        HIPCK(hipEventRecord(e.first, ctx->stream));
+        launch_force(ctx->d, ctx->stream, sl, nd, nsplit);
+        HIPCK(hipEventRecord(e.second, ctx->stream));
+        ctx->prof_launches++;
+        ctx->prof_pairs += (double)sl.nact * (double)ctx->d.n * (double)(ctx->d.n - 1);
+    } else {
+        launch_force(ctx->d, ctx->stream, sl, nd, nsplit);
+    }
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+// Start-of-step quantities: tree sums of the MST state, COM-frame positions
+// and velocities, T0; optionally the force at the start state (a0, U0) for
+// S'(s0) of eq. gbs-criterion and the end-time clip.
+// The start-state slot has no increments; its dX rows must read as zero for
+// the close-pair correction (the slot region moves with n, so clear it).
+int zero_base_increments(mstar_ctx *ctx) {
+    const Dev &d = ctx->d;
+    HIPCK(hipMemsetAsync(d.dX + (size_t)kBase * d.n, 0, sizeof(d4) * d.n, ctx->stream));
+    HIPCK(hipMemsetAsync(d.dV + (size_t)kBase * d.n, 0, sizeof(d4) * d.n, ctx->stream));
+    return MSTAR_OK;
+}
+
+int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool with_force, int64_t *nforce) {
+    const Dev &d = ctx->d;
+    int rc0 = zero_base_increments(ctx);
+    if (rc0) return rc0;
+    launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
+    launch_com_frame(d, ctx->stream, kBase);
+    if (with_force) {
+        SlotList sl{};
+        sl.nact = 1;
+        sl.slot[0] = kBase;
+        const int ns = nsplit_for(d, 1);
+        int rc = prof_force(ctx, sl, p->n_d, ns);
+        if (rc) return rc;
+        launch_reduce_start(d, ctx->stream, kBase, p->G, ns, d.a0, &d.ctl->U0);
+        if (nforce) ++*nforce;
+    }
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+// All divisions nlist[k] (slot k) from the start state over the step in
+// ctl->H: D(h/2)[K(h)D(h)]^(n-1)K(h)D(h/2) for every division, one stage at a
+// time across divisions.
+int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int ndiv, int64_t *nforce) {
+    const Dev &d = ctx->d;
+    launch_div_init(d, ctx->stream, ndiv, kBase);
+    int nmax = 0;
+    for (int k = 0; k < ndiv; ++k) nmax = std::max(nmax, nlist[k]);
+    for (int s = 1; s <= nmax + 1; ++s) {
+        SlotList dr{};
+        for (int k = 0; k < ndiv; ++k) {
+            const int nk = nlist[k];
+            if (s == 1) {
+                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 1; dr.first[dr.nact] = 1; dr.nact++;
+            } else if (nk >= s) {
+                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 0; dr.first[dr.nact] = 0; dr.nact++;
+            } else if (nk == s - 1) {
+                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 1; dr.first[dr.nact] = 0; dr.nact++;
+            }
+        }
+        if (dr.nact) launch_drift(d, ctx->stream, dr, p->alpha, p->gamma);
+        if (s > nmax) break;
+        SlotList fk{};
+        for (int k = 0; k < ndiv; ++k)
+            if (nlist[k] >= s) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nlist[k]; fk.nact++; }
+        const int ns = nsplit_for(d, fk.nact);
+        int rc = prof_force(ctx, fk, p->n_d, ns);
+        if (rc) return rc;
+        launch_kick(d, ctx->stream, fk, ns, p->G, p->alpha, p->gamma);
+        if (nforce) *nforce += fk.nact;
+    }
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+int read_ctl(mstar_ctx *ctx) {
+    HIPCK(hipMemcpyAsync(ctx->h_ctl, ctx->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->h_sys, ctx->d.sys, sizeof(SysScal), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+// New MST from the current state (Sec. 3.5).
+int rebuild(mstar_ctx *ctx, const mstar_params *p) {
+    const Dev &d = ctx->d;
+    launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
+    launch_mst(d, ctx->stream, d.tsA, -1, nsplit_for(d, 1));
+    launch_rebuild_edges(d, ctx->stream, d.tsA, d.tsB, p->n_d);
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+int load_state(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent, const double *X, const double *V,
+               const double *scal) {
+    int rc = load_tree(ctx, flags, n, parent);
+    if (rc) return rc;
+    const void *xd, *vd;
+    if ((rc = in_dev(ctx, flags, X, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
+    if ((rc = in_dev(ctx, flags, V, ctx->vin, sizeof(double) * 3 * n, &vd))) return rc;
+    launch_pack3(ctx->stream, (const double *)xd, nullptr, ctx->d.X0, (int)n);
+    launch_pack3(ctx->stream, (const double *)vd, nullptr, ctx->d.V0, (int)n);
+    double hs[9];
+    if (is_dev(flags)) HIPCK(hipMemcpy(hs, scal, sizeof hs, hipMemcpyDeviceToHost));
+    else memcpy(hs, scal, sizeof hs);
+    if (!finite_host(hs, 9)) return fail(ctx, MSTAR_E_NONFINITE, "non-finite scalars");
+    if (hs[2] != 0.0) return fail(ctx, MSTAR_E_UNSUPPORTED, "w != 0 needs beta != 0 (not implemented)");
+    launch_set_sys(ctx->d, ctx->stream, hs[0], hs[1], hs + 3, hs + 6, 1);
+    launch_levels_children(ctx->d, ctx->stream);
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+int store_state(mstar_ctx *ctx, uint32_t flags, int64_t n, double *X, double *V, double *scal) {
+    launch_unpack3(ctx->stream, ctx->d.X0, ctx->xout, (int)n);
+    int rc = out_copy(ctx, flags, X, ctx->xout, sizeof(double) * 3 * n);
+    if (rc) return rc;
+    launch_unpack3(ctx->stream, ctx->d.V0, ctx->vin, (int)n);
+    if ((rc = out_copy(ctx, flags, V, ctx->vin, sizeof(double) * 3 * n))) return rc;
+    if ((rc = read_ctl(ctx))) return rc;
+    const SysScal &y = *ctx->h_sys;
+    double hs[9] = {y.t, y.B, y.w, y.rcm[0], y.rcm[1], y.rcm[2], y.vcm[0], y.vcm[1], y.vcm[2]};
+    if (is_dev(flags)) HIPCK(hipMemcpy(scal, hs, sizeof hs, hipMemcpyHostToDevice));
+    else memcpy(scal, hs, sizeof hs);
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mstar_abi_version(void) { return MSTAR_ABI_VERSION; }
+
+void mstar_params_default(mstar_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(mstar_params);
+    p->G = 1.0;
+    p->eta = 1e-12;
+    p->alpha = 1.0;
+    p->beta = 0.0;
+    p->gamma = 0.0;
+    p->omega_mass_max = 0.0;
+    p->a_gbs = 0.9;
+    p->f_min = 0.1;
+    p->f_max = 4.0;
+    p->q_first = 0.1;
+    p->t_tol = 1e-14;
+    p->h_init = 0.0;
+    p->max_steps = 1000000000LL;
+    p->k_fix = 8;
+    p->n_d = 2;
+    p->max_halvings = 60;
+    p->max_time_iter = 8;
+    p->rebuild_every = 1;
+}
+
+const char *mstar_strerror(int code) {
+    switch (code) {
+        case MSTAR_OK: return "ok";
+        case MSTAR_E_INVAL: return "invalid argument";
+        case MSTAR_E_NOMEM: return "out of memory";
+        case MSTAR_E_DEVICE: return "HIP device error";
+        case MSTAR_E_NONFINITE: return "non-finite input";
+        case MSTAR_E_COINCIDENT: return "coincident bodies";
+        case MSTAR_E_NOCONV: return "GBS step did not converge";
+        case MSTAR_E_MAXSTEPS: return "maximum number of steps reached";
+        case MSTAR_E_UNSUPPORTED: return "not supported by this implementation";
+        case MSTAR_W_TIME_TOL: return "end time not met within tolerance";
+        default: return "unknown code";
+    }
+}
+
+int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) return MSTAR_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return MSTAR_E_DEVICE;
+    if (hip_device < 0 || hip_device >= ndev) return MSTAR_E_INVAL;
+    mstar_ctx *ctx = new (std::nothrow) mstar_ctx();
+    if (!ctx) return MSTAR_E_NOMEM;
+    ctx->device = hip_device;
+    if (hipSetDevice(hip_device) != hipSuccess) { delete ctx; return MSTAR_E_DEVICE; }
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return MSTAR_E_DEVICE; }
+        ctx->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_sys, sizeof(SysScal), hipHostMallocDefault) != hipSuccess) {
+        mstar_destroy(ctx);
+        return MSTAR_E_NOMEM;
+    }
+    *out = ctx;
+    return MSTAR_OK;
+}
+
+void mstar_destroy(mstar_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_workspace(ctx);
+    for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    if (ctx->h_sys) (void)hipHostFree(ctx->h_sys);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *mstar_last_error(const mstar_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int mstar_profile_enable(mstar_ctx *ctx, int enable) {
+    if (!ctx) return MSTAR_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ctx->prof = enable != 0;
+    ctx->ev_used = 0;
+    ctx->prof_launches = 0;
+    ctx->prof_pairs = 0.0;
+    return MSTAR_OK;
+}
+
+int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs) {
+    if (!ctx) return MSTAR_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (size_t k = 0; k < ctx->ev_used; ++k) {
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
+        tot += ms;
+    }
+    if (launches) *launches = ctx->prof_launches;
+    if (kernel_ms) *kernel_ms = tot;
+    if (pairs) *pairs = ctx->prof_pairs;
+    return MSTAR_OK;
+}
+
+int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x, int32_t root_in,
+                    int32_t *parent, int32_t *level, int32_t *root_out) {
+    if (!ctx) return MSTAR_E_INVAL;
+    if (n < 2 || n > (1 << 24) || !m || !x || !parent || !level || !root_out)
+        return fail(ctx, MSTAR_E_INVAL, "mst_build: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    int rc = ensure(ctx, (int)n);
+    if (rc) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr))) return rc;
+    const void *xd;
+    if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
+    const Dev &d = ctx->d;
+    launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
+    launch_mst(d, ctx->stream, d.tsA, (root_in >= 0 && root_in < n) ? root_in : -1, nsplit_for(d, 1));
+    launch_tree_finish(d, ctx->stream);
+    HIPCK(hipGetLastError());
+    if ((rc = out_copy(ctx, flags, parent, d.parent, sizeof(int32_t) * n))) return rc;
+    if ((rc = out_copy(ctx, flags, level, d.level, sizeof(int32_t) * n))) return rc;
+    if ((rc = out_copy(ctx, flags, root_out, d.root, sizeof(int32_t)))) return rc;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *rho,
+                const int32_t *parent, const double *X, double *acc, double *U) {
+    if (!ctx) return MSTAR_E_INVAL;
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n < 2 || n > (1 << 24) || !m || !rho || !parent || !X || !acc || !U)
+        return fail(ctx, MSTAR_E_INVAL, "force: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = params->flags;
+    if ((rc = ensure(ctx, (int)n))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, rho, nullptr))) return rc;
+    if ((rc = load_tree(ctx, flags, n, parent))) return rc;
+    const Dev &d = ctx->d;
+    const void *rd, *xd;
+    if ((rc = in_dev(ctx, flags, rho, ctx->xin, sizeof(double) * 3 * n, &rd))) return rc;
+    if ((rc = in_dev(ctx, flags, X, ctx->vin, sizeof(double) * 3 * n, &xd))) return rc;
+    launch_pack3(ctx->stream, (const double *)rd, d.m, d.P + (size_t)kBase * n, (int)n);
+    launch_pack3(ctx->stream, (const double *)xd, nullptr, d.X0, (int)n);
+    launch_levels_children(d, ctx->stream);
+    if ((rc = zero_base_increments(ctx))) return rc;
+    SlotList sl{};
+    sl.nact = 1;
+    sl.slot[0] = kBase;
+    const int ns = nsplit_for(d, 1);
+    if ((rc = prof_force(ctx, sl, params->n_d, ns))) return rc;
+    launch_reduce_start(d, ctx->stream, kBase, params->G, ns, d.a0, &d.ctl->U0);
+    launch_unpack3(ctx->stream, d.a0, ctx->xout, (int)n);
+    HIPCK(hipGetLastError());
+    if ((rc = out_copy(ctx, flags, acc, ctx->xout, sizeof(double) * 3 * n))) return rc;
+    if ((rc = out_copy(ctx, flags, U, &d.ctl->U0, sizeof(double)))) return rc;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return MSTAR_OK;
+}
+
+int mstar_leapfrog(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const int32_t *parent,
+                   double *X, double *V, double *scal, double H, int32_t nsub) {
+    if (!ctx) return MSTAR_E_INVAL;
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n < 2 || n > (1 << 24) || !m || !parent || !X || !V || !scal || nsub < 1 || nsub > 4096 ||
+        !std::isfinite(H))
+        return fail(ctx, MSTAR_E_INVAL, "leapfrog: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = params->flags;
+    if ((rc = ensure(ctx, (int)n))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
+    if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
+    if ((rc = prepare_start(ctx, params, false, nullptr))) return rc;
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
+    const int nl[1] = {nsub};
+    if ((rc = run_divisions(ctx, params, nl, 1, nullptr))) return rc;
+    launch_commit(ctx->d, ctx->stream, 0, 0);
+    return store_state(ctx, flags, n, X, V, scal);
+}
+
+int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const int32_t *parent,
+                   double *X, double *V, double *scal, double H, int32_t *accepted, double *eps, double *h_next) {
+    if (!ctx) return MSTAR_E_INVAL;
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n < 2 || n > (1 << 24) || !m || !parent || !X || !V || !scal || !accepted || !eps || !h_next ||
+        !std::isfinite(H) || H == 0.0)
+        return fail(ctx, MSTAR_E_INVAL, "gbs_step: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = params->flags;
+    if ((rc = ensure(ctx, (int)n))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
+    if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
+    if ((rc = prepare_start(ctx, params, true, nullptr))) return rc;
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
+    int nl[16];
+    for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
+    if ((rc = run_divisions(ctx, params, nl, params->k_fix, nullptr))) return rc;
+    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, params->alpha, params->gamma, kBase);
+    launch_control(ctx->d, ctx->stream, params->k_fix, params->eta, params->a_gbs, params->f_min, params->f_max);
+    launch_commit(ctx->d, ctx->stream, 1, 0);
+    HIPCK(hipGetLastError());
+    if ((rc = store_state(ctx, flags, n, X, V, scal))) return rc;
+    *accepted = ctx->h_ctl->accepted;
+    *eps = ctx->h_ctl->eps;
+    *h_next = ctx->h_ctl->h_next;
+    return MSTAR_OK;
+}
+
+int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                    double t0, double t_end, mstar_stats *stats) {
+    if (!ctx) return MSTAR_E_INVAL;
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n < 2 || n > (1 << 24) || !m || !x || !v || !stats || stats->struct_size != sizeof(mstar_stats))
+        return fail(ctx, MSTAR_E_INVAL, "integrate: bad arguments");
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || t0 == t_end)
+        return fail(ctx, MSTAR_E_INVAL, "integrate: need finite t0 != t_end");
+    mstar_stats st{};
+    st.struct_size = sizeof(mstar_stats);
+    st.t_reached = t0;
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = params->flags;
+    const mstar_params &p = *params;
+    if ((rc = ensure(ctx, (int)n))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, v))) return rc;
+    const Dev &d = ctx->d;
+    const void *xd, *vd;
+    if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
+    if ((rc = in_dev(ctx, flags, v, ctx->vin, sizeof(double) * 3 * n, &vd))) return rc;
+    // initial MST on the Cartesian positions, edge vectors, COM
+    launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
+    launch_mst(d, ctx->stream, d.tsA, -1, nsplit_for(d, 1));
+    launch_tree_finish(d, ctx->stream);
+    launch_set_sys(d, ctx->stream, t0, 0.0, nullptr, nullptr, 0);
+    launch_state_from_cartesian(d, ctx->stream, (const double *)xd, (const double *)vd);
+    launch_check_coincident(d, ctx->stream);
+    if ((rc = prepare_start(ctx, &p, true, &st.force_evals))) return rc;
+    launch_set_B(d, ctx->stream);
+    if ((rc = read_ctl(ctx))) return rc;
+    if (ctx->h_ctl->coincident) return fail(ctx, MSTAR_E_COINCIDENT, "two bodies share a position");
+    const double gk0 = p.alpha * ctx->h_ctl->U0 + p.gamma;
+    double H = p.h_init > 0.0 ? p.h_init : p.q_first * gk0 * (t_end - t0);
+    const double span = std::fabs(t_end - t0);
+    int halvings = 0, since_rebuild = 0;
+    bool fresh = false;   // the start state was just prepared
+    bool just_rebuilt = false;
+    int nl[16];
+    for (int k = 0; k < p.k_fix; ++k) nl[k] = 2 * (k + 1);
+    double t_now = t0;
+    for (;;) {
+        if (st.steps_accepted + st.steps_rejected >= p.max_steps) { rc = MSTAR_E_MAXSTEPS; break; }
+        if (fresh) {
+            if (since_rebuild >= p.rebuild_every) {
+                if ((rc = rebuild(ctx, &p))) break;
+                st.mst_rebuilds++;
+                since_rebuild = 0;
+                just_rebuilt = true;
+            }
+            if ((rc = prepare_start(ctx, &p, true, &st.force_evals))) break;
+            fresh = false;
+        }
+        launch_set_h(d, ctx->stream, H, t_end, 1, p.alpha, p.gamma);
+        if ((rc = run_divisions(ctx, &p, nl, p.k_fix, &st.force_evals))) break;
+        launch_extrapolate(d, ctx->stream, p.k_fix, p.alpha, p.gamma, kBase);
+        launch_control(d, ctx->stream, p.k_fix, p.eta, p.a_gbs, p.f_min, p.f_max);
+        launch_commit(d, ctx->stream, 1, 0);
+        if ((rc = read_ctl(ctx))) break;
+        const Ctl &c = *ctx->h_ctl;
+        if (just_rebuilt) { st.topo_changes += c.topo; just_rebuilt = false; }
+        st.eps_last = c.eps;
+        H = c.H;
+        if (!c.accepted) {
+            st.steps_rejected++;
+            if (++halvings > p.max_halvings) { rc = MSTAR_E_NOCONV; break; }
+            H = c.h_next;
+            continue;
+        }
+        st.steps_accepted++;
+        st.h_last = H;
+        halvings = 0;
+        since_rebuild++;
+        fresh = true;
+        if (c.clipped) st.time_iters++;
+        H = c.h_next;
+        st.h_next = H;
+        t_now = ctx->h_sys->t;
+        if (std::fabs(t_end - t_now) <= p.t_tol * span) { rc = MSTAR_OK; break; }
+        if (st.time_iters > p.max_time_iter) { rc = MSTAR_W_TIME_TOL; break; }
+    }
+    st.t_reached = ctx->h_sys->t;
+    if (rc == MSTAR_OK || rc == MSTAR_W_TIME_TOL || rc == MSTAR_E_NOCONV || rc == MSTAR_E_MAXSTEPS) {
+        launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
+        launch_output_cartesian(d, ctx->stream, ctx->xout, ctx->vin);
+        int rc2;
+        if ((rc2 = out_copy(ctx, flags, x, ctx->xout, sizeof(double) * 3 * n))) return rc2;
+        if ((rc2 = out_copy(ctx, flags, v, ctx->vin, sizeof(double) * 3 * n))) return rc2;
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, MSTAR_E_DEVICE, "sync failed");
+    }
+    *stats = st;
+    if (rc < 0 && ctx->err.empty()) fail(ctx, rc, "%s", mstar_strerror(rc));
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Shared device helpers and the launch interface between the host driver
+// (api.hip) and the kernel files.  FP64 throughout; all files are compiled
+// with -ffp-contract=off so every fused multiply-add below is explicit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mstar {
+
+// One 32-byte record per body: xyz plus a fourth slot (mass for positions,
+// zero padding for edge vectors and velocities).  32-byte rows let a wave
+// fetch a whole j-body with one scalar load.
+struct __attribute__((aligned(32))) d4 {
+    double x, y, z, w;
+};
+
+constexpr int kMaxDiv = 17;        // k_fix <= 16 divisions plus the start-state slot
+constexpr int kWG = 256;           // threads per workgroup of the O(N) kernels
+constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
+
+// 1/sqrt(x) for x > 0 to <= 1 ulp: the hardware estimate v_rsq_f64 (relative
+// error ~5e-8) refined by the second-order expansion of (1 - e)^(-1/2) =
+// 1 + e/2 + 3e^2/8 + O(e^3) with e = 1 - x y0^2 (Newton's method on
+// f(y) = y^-2 - x carried one term further).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    double y0 = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y0, y0, 1.0);
+    double c = fma(e, 0.375, 0.5);
+    return fma(y0 * e, c, y0);
+}
+
+// The O(N^2) pair term: mr = m_j/r, s = m_j/r^3; accumulate phi and a.
+__device__ __forceinline__ void pair_terms(double dx, double dy, double dz, double mj,
+                                           double &s, double &mr) {
+    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double y = rsqrt_f64(r2);
+    mr = mj * y;
+    s = mr * (y * y);
+}
+
+// Deterministic sum of a block of values held one per thread (fixed tree).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- stages
+// Per-slot description of one launch of the drift / force / kick stage over
+// several substep divisions at once ("slots"; slot kMaxDiv-1 style indices are
+// chosen by the host).
+struct SlotList {
+    int nact;
+    int slot[kMaxDiv];
+    int nsub[kMaxDiv];     // substeps of the division in this slot
+    int half[kMaxDiv];     // drift: 1 = half substep
+    int first[kMaxDiv];    // drift: 1 = first drift (uses T of the start state)
+};
+
+struct Ctl {               // device control block, read back once per GBS step
+    double H;              // fictitious step of this attempt (after the end-time clip)
+    double eps;            // GBS error measure
+    double h_next;
+    double U0, T0, gk0;    // start-state force function, kinetic energy, alpha U + gamma
+    double t_est;          // predicted physical time after the step
+    int32_t accepted;
+    int32_t clipped;
+    int32_t coincident;    // a zero-length MST edge was found
+    int32_t topo;          // the last rebuild changed the tree
+};
+
+struct SysScal {           // start-of-step scalars of the integrated state
+    double t, B, w;
+    double rcm[3], vcm[3];
+};
+
+struct DivScal {           // per-division increments of the scalar variables
+    double tau, dw, drcm[3], pad[3];
+};
+
+// Workspace pointers used by the kernels (device memory).
+struct Dev {
+    int n, nib, kfmax;          // bodies, 64-wide i-blocks, division slots allocated
+    // tree
+    int32_t *parent, *level, *child_off, *child_idx, *root;
+    int32_t *parent_new, *level_new;
+    // start state
+    d4 *X0, *V0;                // MST edge vectors / velocities (row v = edge parent->v)
+    d4 *P0, *Vt0;               // COM-frame positions (+mass) and velocities
+    d4 *a0;                     // accelerations at the start state
+    double *m;
+    SysScal *sys;
+    Ctl *ctl;
+    // divisions (slot-major)
+    d4 *P, *Vt, *dX, *dV;       // [slot][n]
+    d4 *dX1, *dV1;              // extrapolated increments
+    DivScal *dscal, *dscal1;    // [slot], extrapolated
+    d4 *part;                   // force partials [slot][nsplit_max][n]
+    double *Upart;              // [slot][nib * nsplit_max]
+    double *Tpart;              // [slot][nkwg]
+    double *epspart;            // [nkwg + 1]
+    int nsplit_max, nkwg;
+    // tree scratch
+    d4 *tsA, *tsB;              // tree sums: root-relative positions / velocities
+    d4 *tsC, *tsD, *tsE, *tsF;  // ping-pong scratch
+    int32_t *ancA, *ancB;
+    double *bor_w;              // Boruvka partial best weight [nsplit][n]
+    int32_t *bor_j;             // Boruvka partial best index [nsplit][n]
+    int32_t *comp, *ecomp_tmp;
+    unsigned long long *cw, *cidx;
+    int32_t *tgt, *elo, *ehi, *hooked, *done, *ncomp;
+    int32_t *deg, *off, *fill, *adj, *arcpos, *nxtA, *nxtB, *rkA, *rkB;
+    int32_t *cnt;
+    double *scr;                // misc scalar scratch
+};
+
+// ---------------------------------------------------------------- launches
+// kernels_force.hip
+void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit);
+void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int nsplit, d4 *acc_out,
+                         double *U_out);
+// kernels_step.hip
+void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot);
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, double alpha, double gamma);
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, double alpha,
+                 double gamma);
+void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, double alpha, double gamma);
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, double alpha, double gamma, int base_slot);
+void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max);
+void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot);
+void launch_state_from_cartesian(const Dev &d, hipStream_t s, const double *x, const double *v);
+void launch_com_frame(const Dev &d, hipStream_t s, int with_T);
+void launch_output_cartesian(const Dev &d, hipStream_t s, double *x, double *v);
+void launch_set_B(const Dev &d, hipStream_t s);
+void launch_pack3(hipStream_t s, const double *x, const double *m, d4 *out, int n);
+void launch_unpack3(hipStream_t s, const d4 *in, double *out, int n);
+void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, const double *rcm, const double *vcm,
+                    int set_com);
+void launch_check_coincident(const Dev &d, hipStream_t s);
+// kernels_tree.hip
+void launch_tree_sums(const Dev &d, hipStream_t s, const d4 *X, const d4 *V, d4 *rho, d4 *ups);
+int launch_mst(const Dev &d, hipStream_t s, const d4 *pos, int root_in, int nsplit);
+void launch_tree_finish(const Dev &d, hipStream_t s);
+void launch_rebuild_edges(const Dev &d, hipStream_t s, const d4 *rho, const d4 *ups, int nd);
+void launch_levels_children(const Dev &d, hipStream_t s);
+
+}  // namespace mstar

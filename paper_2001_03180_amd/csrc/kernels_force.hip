@@ -1,0 +1,215 @@
+// O(N^2) FP64 force / force-function kernel with MST close-pair separations
+// (paper Sec. 2.1 equations of motion, Sec. 3.4 close-pair rule, Sec. 4.1
+// force loop).
+//
+// Layout: positions are 32-byte records {x, y, z, m} in the centre-of-mass
+// frame, one array per division slot.  One workgroup = 4 waves sharing the
+// same 64 i-bodies (one per lane) and splitting the workgroup's j-range in
+// four; the j-body of each iteration is wave-uniform and is fetched with a
+// scalar load straight into SGPRs, so the inner loop is pure FP64 VALU work
+// with no LDS traffic.  Partial sums of the four waves are combined in LDS
+// in fixed order; j-splits across workgroups are combined later in fixed
+// order, so results are bitwise reproducible.
+//
+// Close pairs (tree distance <= N_d): the main loop uses Cartesian
+// differences for every pair; the split-0 workgroup of each i-block then
+// replaces the Cartesian term of each close pair by the term built from the
+// MST path sum (same operation sequence, so the subtracted term is the one
+// that was added).
+#include "common.h"
+
+namespace mstar {
+
+struct ForceArgs {
+    const d4 *P;           // [slot][n] positions + mass
+    d4 *part;              // [slot][nsplit_max][n] partial (ax, ay, az, phi)
+    double *Upart;         // [slot][nib * nsplit_max] partial sum_i m_i phi_i
+    const d4 *X0, *dX;     // MST edge vectors: current = X0 + dX[slot]
+    const int32_t *parent, *child_off, *child_idx;
+    int n, nib, nsplit, nsplit_max, jchunk;
+    SlotList sl;
+};
+
+__device__ __forceinline__ void add_close(double dpx, double dpy, double dpz, const d4 &pi, const d4 &pj,
+                                          double &ax, double &ay, double &az, double &ph) {
+    double s1, mr1, s0, mr0;
+    pair_terms(dpx, dpy, dpz, pj.w, s1, mr1);
+    const double cx = pj.x - pi.x, cy = pj.y - pi.y, cz = pj.z - pi.z;
+    pair_terms(cx, cy, cz, pj.w, s0, mr0);
+    ax = ax + fma(s1, dpx, -(s0 * cx));
+    ay = ay + fma(s1, dpy, -(s0 * cy));
+    az = az + fma(s1, dpz, -(s0 * cz));
+    ph = ph + (mr1 - mr0);
+}
+
+__device__ __forceinline__ d4 cur_edge(const d4 *X0, const d4 *dX, int u) {
+    const d4 a = X0[u], b = dX[u];
+    return d4{a.x + b.x, a.y + b.y, a.z + b.z, 0.0};
+}
+
+// Replace the Cartesian terms of all pairs (i, j) within ND tree edges by the
+// MST path-sum terms.  Separations follow the rule d_ij = S_j - S_i with S_v
+// the sum of edge vectors from the lowest common ancestor down to v.
+template <int ND>
+__device__ void close_correction(int i, const d4 *P, const d4 *X0, const d4 *dX, const int32_t *parent,
+                                 const int32_t *coff, const int32_t *cidx, double &ax, double &ay,
+                                 double &az, double &ph) {
+    const d4 pi = P[i];
+    const int p = parent[i];
+    if (p >= 0) {
+        const d4 Xi = cur_edge(X0, dX, i);
+        add_close(-Xi.x, -Xi.y, -Xi.z, pi, P[p], ax, ay, az, ph);              // parent
+        if (ND >= 2) {
+            const int g = parent[p];
+            if (g >= 0) {
+                const d4 Xp = cur_edge(X0, dX, p);
+                add_close(-(Xp.x + Xi.x), -(Xp.y + Xi.y), -(Xp.z + Xi.z), pi, P[g], ax, ay, az, ph);  // grandparent
+            }
+            for (int k = coff[p]; k < coff[p + 1]; ++k) {                        // siblings
+                const int c = cidx[k];
+                if (c == i) continue;
+                const d4 Xs = cur_edge(X0, dX, c);
+                add_close(Xs.x - Xi.x, Xs.y - Xi.y, Xs.z - Xi.z, pi, P[c], ax, ay, az, ph);
+            }
+        }
+    }
+    for (int k = coff[i]; k < coff[i + 1]; ++k) {                                // children
+        const int c = cidx[k];
+        const d4 Xc = cur_edge(X0, dX, c);
+        add_close(Xc.x, Xc.y, Xc.z, pi, P[c], ax, ay, az, ph);
+        if (ND >= 2) {
+            for (int q = coff[c]; q < coff[c + 1]; ++q) {                        // grandchildren
+                const int gc = cidx[q];
+                const d4 Xg = cur_edge(X0, dX, gc);
+                add_close(Xc.x + Xg.x, Xc.y + Xg.y, Xc.z + Xg.z, pi, P[gc], ax, ay, az, ph);
+            }
+        }
+    }
+}
+
+template <bool GUARD>
+__device__ __forceinline__ void j_loop(const d4 *__restrict__ P, int jb, int je, int ii, const d4 &pi,
+                                       double &ax, double &ay, double &az, double &ph) {
+#pragma unroll 4
+    for (int j = jb; j < je; ++j) {
+        const d4 pj = P[j];
+        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        double mj = pj.w;
+        if (GUARD) {
+            const bool self = (j == ii);
+            r2 = self ? 1.0 : r2;
+            mj = self ? 0.0 : mj;
+        }
+        const double y = rsqrt_f64(r2);
+        const double mr = mj * y;
+        const double s = mr * (y * y);
+        ph = ph + mr;
+        ax = fma(s, dx, ax);
+        ay = fma(s, dy, ay);
+        az = fma(s, dz, az);
+    }
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_force(ForceArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ib = blockIdx.x % a.nib;
+    const int slot = a.sl.slot[blockIdx.x / a.nib];
+    const int split = blockIdx.y;
+    const int n = a.n;
+    const d4 *__restrict__ P = a.P + (size_t)slot * n;
+    const int i0 = ib * 64;
+    const int i = i0 + lane;
+    const int ii = i < n ? i : n - 1;
+    const d4 pi = P[ii];
+    const int j0 = split * a.jchunk;
+    const int j1 = min(n, j0 + a.jchunk);
+    const int q = (max(j1 - j0, 0) + 3) >> 2;
+    int jb = min(j1, j0 + wv * q);
+    int je = min(j1, jb + q);
+    jb = __builtin_amdgcn_readfirstlane(jb);
+    je = __builtin_amdgcn_readfirstlane(je);
+    const int g0 = __builtin_amdgcn_readfirstlane(max(jb, i0));
+    const int g1 = __builtin_amdgcn_readfirstlane(min(je, i0 + 64));
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    if (g0 < g1) {
+        j_loop<false>(P, jb, g0, ii, pi, ax, ay, az, ph);
+        j_loop<true>(P, g0, g1, ii, pi, ax, ay, az, ph);
+        j_loop<false>(P, g1, je, ii, pi, ax, ay, az, ph);
+    } else {
+        j_loop<false>(P, jb, je, ii, pi, ax, ay, az, ph);
+    }
+    __shared__ d4 red[4][64];
+    red[wv][lane] = d4{ax, ay, az, ph};
+    __syncthreads();
+    if (wv != 0) return;
+    d4 s = red[0][lane];
+    for (int w = 1; w < 4; ++w) {
+        const d4 t = red[w][lane];
+        s.x = s.x + t.x; s.y = s.y + t.y; s.z = s.z + t.z; s.w = s.w + t.w;
+    }
+    if (ND > 0 && split == 0 && i < n)
+        close_correction<ND>(i, P, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off, a.child_idx, s.x,
+                             s.y, s.z, s.w);
+    if (i < n) a.part[((size_t)slot * a.nsplit_max + split) * n + i] = s;
+    double u = (i < n) ? pi.w * s.w : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) u = u + __shfl_xor(u, off, 64);
+    if (lane == 0) a.Upart[(size_t)slot * a.nib * a.nsplit_max + (size_t)ib * a.nsplit + split] = u;
+}
+
+void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit) {
+    ForceArgs a;
+    a.P = d.P;
+    a.part = d.part;
+    a.Upart = d.Upart;
+    a.X0 = d.X0;
+    a.dX = d.dX;
+    a.parent = d.parent;
+    a.child_off = d.child_off;
+    a.child_idx = d.child_idx;
+    a.n = d.n;
+    a.nib = d.nib;
+    a.nsplit = nsplit;
+    a.nsplit_max = d.nsplit_max;
+    a.jchunk = (d.n + nsplit - 1) / nsplit;
+    a.sl = sl;
+    dim3 grid(sl.nact * d.nib, nsplit);
+    if (nd <= 0) k_force<0><<<grid, 256, 0, s>>>(a);
+    else if (nd == 1) k_force<1><<<grid, 256, 0, s>>>(a);
+    else k_force<2><<<grid, 256, 0, s>>>(a);
+}
+
+// Reduce the force partials of one slot: acc = G sum_split part, and the
+// force function U = G/2 sum_i m_i phi_i (every workgroup reduces the same
+// partials in the same order; block 0 stores U).
+__global__ __launch_bounds__(kWG) void k_reduce_start(const d4 *part, const double *Upart, int n, int nib,
+                                                      int nsplit, int nsplit_max, double G, d4 *acc,
+                                                      double *Uout) {
+    __shared__ double sh[kWG];
+    const int cnt = nib * nsplit;
+    double u = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + Upart[k];
+    const double U = 0.5 * G * block_sum<kWG>(u, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *Uout = U;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= n) return;
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const d4 t = part[(size_t)sp * n + v];
+        x = x + t.x; y = y + t.y; z = z + t.z;
+    }
+    acc[v] = d4{G * x, G * y, G * z, 0.0};
+}
+
+void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int nsplit, d4 *acc_out,
+                         double *U_out) {
+    const int nb = (d.n + kWG - 1) / kWG;
+    k_reduce_start<<<nb, kWG, 0, s>>>(d.part + (size_t)slot * d.nsplit_max * d.n,
+                                      d.Upart + (size_t)slot * d.nib * d.nsplit_max, d.n, d.nib, nsplit,
+                                      d.nsplit_max, G, acc_out, U_out);
+}
+
+}  // namespace mstar

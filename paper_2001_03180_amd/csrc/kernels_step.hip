@@ -1,0 +1,484 @@
+// O(N) kernels of the GBS step: division set-up, the drift and kick
+// operators of the regularised leapfrog (paper Sec. 2.1-2.3), Neville-Aitken
+// extrapolation with the error measure of eq. gbs-criterion, step control
+// (eq. hnext), the end-time clip (Sec. 2.4) and state transforms.
+//
+// Each division integrates increments from the step's start state (X = X0 +
+// dX, V = V0 + dV, t = t0 + tau), so the extrapolation works on small
+// numbers.  Between kernels the only cross-body quantities are the force
+// function U and the kinetic energy T; every workgroup that needs them
+// reduces the same per-workgroup partials in the same order, so all
+// workgroups agree bit for bit without an extra launch.
+#include "common.h"
+
+namespace mstar {
+
+__global__ __launch_bounds__(kWG) void k_div_init(Dev d, int ndiv, int base) {
+    const int slot = blockIdx.y;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const int n = d.n;
+    if (slot >= ndiv) return;
+    if (v < n) {
+        const size_t o = (size_t)slot * n + v;
+        d.P[o] = d.P[(size_t)base * n + v];
+        d.Vt[o] = d.Vt[(size_t)base * n + v];
+        d.dX[o] = d4{0.0, 0.0, 0.0, 0.0};
+        d.dV[o] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{0.0, 0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+}
+
+void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
+    dim3 grid((d.n + kWG - 1) / kWG, ndiv);
+    k_div_init<<<grid, kWG, 0, s>>>(d, ndiv, base_slot);
+}
+
+// Drift D(ds): dt = ds / (alpha (T + B) + gamma); X += dt V; positions +=
+// dt v; t += dt; r_cm += dt v_cm.
+__global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha, double gamma) {
+    __shared__ double sh[kWG];
+    const int ai = blockIdx.y;
+    const int slot = sl.slot[ai];
+    const int n = d.n;
+    double T;
+    if (sl.first[ai]) {
+        T = d.ctl->T0;
+    } else {
+        const double *tp = d.Tpart + (size_t)slot * d.nkwg;
+        double t = 0.0;
+        for (int k = threadIdx.x; k < d.nkwg; k += kWG) t = t + tp[k];
+        T = 0.5 * block_sum<kWG>(t, sh);
+    }
+    const double H = d.ctl->H;
+    const double h = H / (double)sl.nsub[ai];
+    const double ds = sl.half[ai] ? 0.5 * h : h;
+    const double dt = ds / (alpha * (T + d.sys->B) + gamma);
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v < n) {
+        const size_t o = (size_t)slot * n + v;
+        if (d.parent[v] >= 0) {
+            const d4 V0 = d.V0[v], dV = d.dV[o];
+            d4 dX = d.dX[o];
+            dX.x = dX.x + dt * (V0.x + dV.x);
+            dX.y = dX.y + dt * (V0.y + dV.y);
+            dX.z = dX.z + dt * (V0.z + dV.z);
+            d.dX[o] = dX;
+        }
+        const d4 vt = d.Vt[o];
+        d4 p = d.P[o];
+        p.x = p.x + dt * vt.x;
+        p.y = p.y + dt * vt.y;
+        p.z = p.z + dt * vt.z;
+        d.P[o] = p;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DivScal &q = d.dscal[slot];
+        q.tau = q.tau + dt;
+        for (int c = 0; c < 3; ++c) q.drcm[c] = q.drcm[c] + dt * d.sys->vcm[c];
+    }
+}
+
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, double alpha, double gamma) {
+    dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
+    k_drift<<<grid, kWG, 0, s>>>(d, sl, alpha, gamma);
+}
+
+// Kick K(ds): dt = ds / (alpha U + gamma); V_v += dt (a_v - a_parent(v));
+// COM-frame velocities v += dt a; partial sums of m |v|^2 for the next drift.
+__global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, double alpha,
+                                             double gamma) {
+    __shared__ double sh[kWG];
+    const int ai = blockIdx.y;
+    const int slot = sl.slot[ai];
+    const int n = d.n;
+    const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
+    const int cnt = d.nib * nsplit;
+    double u = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
+    const double U = 0.5 * G * block_sum<kWG>(u, sh);
+    const double H = d.ctl->H;
+    const double ds = H / (double)sl.nsub[ai];
+    const double dt = ds / (alpha * U + gamma);
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    double tl = 0.0;
+    if (v < n) {
+        const d4 *pp = d.part + (size_t)slot * d.nsplit_max * n;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) {
+            const d4 t = pp[(size_t)sp * n + v];
+            ax = ax + t.x; ay = ay + t.y; az = az + t.z;
+        }
+        ax = G * ax; ay = G * ay; az = G * az;
+        const int p = d.parent[v];
+        const size_t o = (size_t)slot * n + v;
+        if (p >= 0) {
+            double bx = 0.0, by = 0.0, bz = 0.0;
+            for (int sp = 0; sp < nsplit; ++sp) {
+                const d4 t = pp[(size_t)sp * n + p];
+                bx = bx + t.x; by = by + t.y; bz = bz + t.z;
+            }
+            bx = G * bx; by = G * by; bz = G * bz;
+            d4 dV = d.dV[o];
+            dV.x = dV.x + dt * (ax - bx);
+            dV.y = dV.y + dt * (ay - by);
+            dV.z = dV.z + dt * (az - bz);
+            d.dV[o] = dV;
+        }
+        d4 vt = d.Vt[o];
+        vt.x = vt.x + dt * ax;
+        vt.y = vt.y + dt * ay;
+        vt.z = vt.z + dt * az;
+        d.Vt[o] = vt;
+        tl = d.P[o].w * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
+    }
+    const double ts = block_sum<kWG>(tl, sh);
+    if (threadIdx.x == 0) d.Tpart[(size_t)slot * d.nkwg + blockIdx.x] = ts;
+}
+
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, double alpha,
+                 double gamma) {
+    dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
+    k_kick<<<grid, kWG, 0, s>>>(d, sl, nsplit, G, alpha, gamma);
+}
+
+// Step length of this attempt with the end-time clip of Sec. 2.4: the
+// predicted time after the step, t + H/(alpha U + gamma), must not pass t_end
+// (nor may the step point away from it); otherwise ds = (alpha U + gamma)(t_end - t).
+__global__ void k_set_h(Dev d, double H, double t_end, int clip, double alpha, double gamma) {
+    Ctl &c = *d.ctl;
+    const double gk = alpha * c.U0 + gamma;
+    c.gk0 = gk;
+    c.clipped = 0;
+    if (clip) {
+        const double rem = t_end - d.sys->t;
+        const double dt_est = H / gk;
+        if (dt_est / rem > 1.0 || dt_est / rem < 0.0) {
+            H = gk * rem;
+            c.clipped = 1;
+        }
+    }
+    c.H = H;
+    c.t_est = d.sys->t + H / gk;
+}
+
+void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, double alpha, double gamma) {
+    k_set_h<<<1, 1, 0, s>>>(d, H, t_end, clip, alpha, gamma);
+}
+
+// In-place Aitken-Neville tableau over KF divisions n_k = 2(k+1); on return
+// p[k] = T_{k,k}.
+template <int KF>
+__device__ __forceinline__ void neville(double (&p)[KF]) {
+#pragma unroll
+    for (int j = 1; j < KF; ++j) {
+#pragma unroll
+        for (int k = KF - 1; k >= j; --k) {
+            const double r = (double)(2 * (k + 1)) / (double)(2 * (k - j + 1));
+            const double den = r * r - 1.0;
+            p[k] = p[k] + (p[k] - p[k - 1]) / den;
+        }
+    }
+}
+
+__device__ __forceinline__ double norm3(double x, double y, double z) { return sqrt((x * x + y * y) + z * z); }
+
+// Group error |dS| / |S0 + hn S'| of eq. gbs-criterion; groups with a zero
+// denominator are skipped (returns 0); non-finite values give +inf.
+__device__ __forceinline__ double group_err(double nx, double ny, double nz, double dx, double dy, double dz) {
+    if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) return INFINITY;
+    const double dd = norm3(dx, dy, dz);
+    if (!(dd > 0.0)) return 0.0;
+    const double e = norm3(nx, ny, nz) / dd;
+    return isnan(e) ? INFINITY : e;
+}
+
+__device__ __forceinline__ double fmax_nan(double a, double b) {
+    if (isnan(a) || isnan(b)) return INFINITY;
+    return a > b ? a : b;
+}
+
+template <int KF>
+__global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, double alpha, double gamma, int base) {
+    __shared__ double sh[kWG];
+    const int n = d.n;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const Ctl &c = *d.ctl;
+    const double H = c.H;
+    const double hn = H / (double)(2 * KF);
+    const double gd = alpha * (c.T0 + d.sys->B) + gamma;
+    const double gk = alpha * c.U0 + gamma;
+    double eps = 0.0;
+    if (v < n) {
+        double px[KF], py[KF], pz[KF], qx[KF], qy[KF], qz[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const d4 a = d.dX[(size_t)k * n + v];
+            const d4 b = d.dV[(size_t)k * n + v];
+            px[k] = a.x; py[k] = a.y; pz[k] = a.z;
+            qx[k] = b.x; qy[k] = b.y; qz[k] = b.z;
+        }
+        neville<KF>(px); neville<KF>(py); neville<KF>(pz);
+        neville<KF>(qx); neville<KF>(qy); neville<KF>(qz);
+        d.dX1[v] = d4{px[KF - 1], py[KF - 1], pz[KF - 1], 0.0};
+        d.dV1[v] = d4{qx[KF - 1], qy[KF - 1], qz[KF - 1], 0.0};
+        const int p = d.parent[v];
+        if (p >= 0) {
+            const d4 X0 = d.X0[v], V0 = d.V0[v];
+            const d4 av = d.a0[v], ap = d.a0[p];
+            const double ex = group_err(px[KF - 1] - px[KF - 2], py[KF - 1] - py[KF - 2], pz[KF - 1] - pz[KF - 2],
+                                        X0.x + hn * (V0.x / gd), X0.y + hn * (V0.y / gd), X0.z + hn * (V0.z / gd));
+            const double ev = group_err(qx[KF - 1] - qx[KF - 2], qy[KF - 1] - qy[KF - 2], qz[KF - 1] - qz[KF - 2],
+                                        V0.x + hn * ((av.x - ap.x) / gk), V0.y + hn * ((av.y - ap.y) / gk),
+                                        V0.z + hn * ((av.z - ap.z) / gk));
+            eps = fmax_nan(ex, ev);
+        }
+    }
+    // block max (exact, order independent)
+    sh[threadIdx.x] = eps;
+    __syncthreads();
+    for (int s = kWG / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax_nan(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.epspart[blockIdx.x] = sh[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // scalar groups: t (extrapolated through its increment tau) and r_cm
+        double pt[KF], rx[KF], ry[KF], rz[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const DivScal q = d.dscal[k];
+            pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2];
+        }
+        neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz);
+        DivScal out{pt[KF - 1], 0.0, {rx[KF - 1], ry[KF - 1], rz[KF - 1]}, {0.0, 0.0, 0.0}};
+        *d.dscal1 = out;
+        const SysScal &y = *d.sys;
+        const double et = group_err(pt[KF - 1] - pt[KF - 2], 0.0, 0.0, y.t + hn * (1.0 / gd), 0.0, 0.0);
+        const double er = group_err(rx[KF - 1] - rx[KF - 2], ry[KF - 1] - ry[KF - 2], rz[KF - 1] - rz[KF - 2],
+                                    y.rcm[0] + hn * (y.vcm[0] / gd), y.rcm[1] + hn * (y.vcm[1] / gd),
+                                    y.rcm[2] + hn * (y.vcm[2] / gd));
+        d.epspart[d.nkwg] = fmax_nan(et, er);
+    }
+}
+
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, double alpha, double gamma, int base) {
+    const int nb = (d.n + kWG - 1) / kWG;
+    switch (kf) {
+#define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, alpha, gamma, base); break;
+        KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
+        KFC(15) KFC(16)
+#undef KFC
+        default: break;
+    }
+}
+
+// Accept iff eps <= eta; next step per eq. hnext with the clamps, or H/2.
+__global__ void k_control(Dev d, int kf, int nparts, double eta, double a_gbs, double f_min, double f_max) {
+    Ctl &c = *d.ctl;
+    double eps = 0.0;
+    for (int k = 0; k < nparts; ++k) eps = fmax_nan(eps, d.epspart[k]);
+    c.eps = eps;
+    c.accepted = (eps <= eta) ? 1 : 0;
+    if (c.accepted) {
+        const double e = eps > 1e-300 ? eps : 1e-300;
+        double f = a_gbs * pow(eta / e, 1.0 / (double)(2 * kf - 1));
+        if (f < f_min) f = f_min;
+        if (f > f_max) f = f_max;
+        c.h_next = c.H * f;
+    } else {
+        c.h_next = 0.5 * c.H;
+    }
+}
+
+void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max) {
+    const int nb = (d.n + kWG - 1) / kWG;
+    k_control<<<1, 1, 0, s>>>(d, kf, nb + 1, eta, a_gbs, f_min, f_max);
+}
+
+// Commit the extrapolated increments (if the step was accepted) or the end
+// state of division `slot` (from_extrap = 0, used by the single-leapfrog call).
+__global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot) {
+    if (from_extrap && !d.ctl->accepted) return;
+    const int n = d.n;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const d4 *dx = from_extrap ? d.dX1 : d.dX + (size_t)slot * n;
+    const d4 *dv = from_extrap ? d.dV1 : d.dV + (size_t)slot * n;
+    if (v < n) {
+        d4 X = d.X0[v], V = d.V0[v];
+        const d4 a = dx[v], b = dv[v];
+        X.x = X.x + a.x; X.y = X.y + a.y; X.z = X.z + a.z;
+        V.x = V.x + b.x; V.y = V.y + b.y; V.z = V.z + b.z;
+        d.X0[v] = X;
+        d.V0[v] = V;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const DivScal q = from_extrap ? *d.dscal1 : d.dscal[slot];
+        SysScal &y = *d.sys;
+        y.t = y.t + q.tau;
+        for (int c = 0; c < 3; ++c) y.rcm[c] = y.rcm[c] + q.drcm[c];
+    }
+}
+
+void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot) {
+    k_commit<<<(d.n + kWG - 1) / kWG, kWG, 0, s>>>(d, from_extrap, slot);
+}
+
+// Edge vectors of the MST from Cartesian input (Sec. 3.4: vectors point away
+// from the root): X_v = x_v - x_parent(v), V_v likewise; COM of x and v.
+__global__ __launch_bounds__(kTreeWG) void k_state_from_cartesian(Dev d, const double *x, const double *v) {
+    __shared__ double sh[kTreeWG];
+    const int n = d.n;
+    double sm = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = threadIdx.x; u < n; u += kTreeWG) {
+        const int p = d.parent[u];
+        d4 X{0.0, 0.0, 0.0, 0.0}, V{0.0, 0.0, 0.0, 0.0};
+        if (p >= 0) {
+            X = d4{x[3 * u] - x[3 * p], x[3 * u + 1] - x[3 * p + 1], x[3 * u + 2] - x[3 * p + 2], 0.0};
+            V = d4{v[3 * u] - v[3 * p], v[3 * u + 1] - v[3 * p + 1], v[3 * u + 2] - v[3 * p + 2], 0.0};
+        }
+        d.X0[u] = X;
+        d.V0[u] = V;
+        const double mu = d.m[u];
+        sm = sm + mu;
+        for (int c = 0; c < 3; ++c) {
+            s[c] = s[c] + mu * x[3 * u + c];
+            s[3 + c] = s[3 + c] + mu * v[3 * u + c];
+        }
+    }
+    const double M = block_sum<kTreeWG>(sm, sh);
+    double r[6];
+    for (int c = 0; c < 6; ++c) r[c] = block_sum<kTreeWG>(s[c], sh);
+    if (threadIdx.x == 0) {
+        SysScal &y = *d.sys;
+        for (int c = 0; c < 3; ++c) {
+            y.rcm[c] = r[c] / M;
+            y.vcm[c] = r[3 + c] / M;
+        }
+        y.w = 0.0;
+    }
+}
+
+void launch_state_from_cartesian(const Dev &d, hipStream_t s, const double *x, const double *v) {
+    k_state_from_cartesian<<<1, kTreeWG, 0, s>>>(d, x, v);
+}
+
+// COM-frame positions (+mass) and velocities of the start state from the
+// root-relative tree sums rho (tsA) and ups (tsB); T0 = 1/2 sum m |v|^2.
+__global__ __launch_bounds__(kTreeWG) void k_com_frame(Dev d, int base) {
+    __shared__ double sh[kTreeWG];
+    const int n = d.n;
+    const d4 *rho = d.tsA, *ups = d.tsB;
+    double sm = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = threadIdx.x; u < n; u += kTreeWG) {
+        const double mu = d.m[u];
+        const d4 r = rho[u], w = ups[u];
+        sm = sm + mu;
+        s[0] = s[0] + mu * r.x; s[1] = s[1] + mu * r.y; s[2] = s[2] + mu * r.z;
+        s[3] = s[3] + mu * w.x; s[4] = s[4] + mu * w.y; s[5] = s[5] + mu * w.z;
+    }
+    const double M = block_sum<kTreeWG>(sm, sh);
+    double c[6];
+    for (int k = 0; k < 6; ++k) c[k] = block_sum<kTreeWG>(s[k], sh) / M;
+    double tl = 0.0;
+    d4 *P0 = d.P + (size_t)base * n;
+    d4 *V0 = d.Vt + (size_t)base * n;
+    for (int u = threadIdx.x; u < n; u += kTreeWG) {
+        const double mu = d.m[u];
+        const d4 r = rho[u], w = ups[u];
+        P0[u] = d4{r.x - c[0], r.y - c[1], r.z - c[2], mu};
+        const d4 vt{w.x - c[3], w.y - c[4], w.z - c[5], 0.0};
+        V0[u] = vt;
+        tl = tl + mu * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
+    }
+    const double T = 0.5 * block_sum<kTreeWG>(tl, sh);
+    if (threadIdx.x == 0) d.ctl->T0 = T;
+}
+
+void launch_com_frame(const Dev &d, hipStream_t s, int base) { k_com_frame<<<1, kTreeWG, 0, s>>>(d, base); }
+
+// Cartesian output x_i = r_cm + (rho_i - rho_bar), v_i = v_cm + (ups_i - ups_bar).
+__global__ __launch_bounds__(kTreeWG) void k_output_cartesian(Dev d, double *x, double *v) {
+    __shared__ double sh[kTreeWG];
+    const int n = d.n;
+    const d4 *rho = d.tsA, *ups = d.tsB;
+    double sm = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
+    for (int u = threadIdx.x; u < n; u += kTreeWG) {
+        const double mu = d.m[u];
+        const d4 r = rho[u], w = ups[u];
+        sm = sm + mu;
+        s[0] = s[0] + mu * r.x; s[1] = s[1] + mu * r.y; s[2] = s[2] + mu * r.z;
+        s[3] = s[3] + mu * w.x; s[4] = s[4] + mu * w.y; s[5] = s[5] + mu * w.z;
+    }
+    const double M = block_sum<kTreeWG>(sm, sh);
+    double c[6];
+    for (int k = 0; k < 6; ++k) c[k] = block_sum<kTreeWG>(s[k], sh) / M;
+    const SysScal y = *d.sys;
+    for (int u = threadIdx.x; u < n; u += kTreeWG) {
+        const d4 r = rho[u], w = ups[u];
+        x[3 * u] = y.rcm[0] + (r.x - c[0]);
+        x[3 * u + 1] = y.rcm[1] + (r.y - c[1]);
+        x[3 * u + 2] = y.rcm[2] + (r.z - c[2]);
+        v[3 * u] = y.vcm[0] + (w.x - c[3]);
+        v[3 * u + 1] = y.vcm[1] + (w.y - c[4]);
+        v[3 * u + 2] = y.vcm[2] + (w.z - c[5]);
+    }
+}
+
+void launch_output_cartesian(const Dev &d, hipStream_t s, double *x, double *v) {
+    k_output_cartesian<<<1, kTreeWG, 0, s>>>(d, x, v);
+}
+
+// B = -H = U - T at the start of an integration (Sec. 2.1).
+__global__ void k_set_B(Dev d) { d.sys->B = d.ctl->U0 - d.ctl->T0; }
+void launch_set_B(const Dev &d, hipStream_t s) { k_set_B<<<1, 1, 0, s>>>(d); }
+
+// [n][3] doubles <-> 32-byte rows (fourth slot = mass or 0).
+__global__ __launch_bounds__(kWG) void k_pack3(const double *x, const double *m, d4 *out, int n) {
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v < n) out[v] = d4{x[3 * v], x[3 * v + 1], x[3 * v + 2], m ? m[v] : 0.0};
+}
+void launch_pack3(hipStream_t s, const double *x, const double *m, d4 *out, int n) {
+    k_pack3<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(x, m, out, n);
+}
+__global__ __launch_bounds__(kWG) void k_unpack3(const d4 *in, double *out, int n) {
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v < n) {
+        const d4 a = in[v];
+        out[3 * v] = a.x; out[3 * v + 1] = a.y; out[3 * v + 2] = a.z;
+    }
+}
+void launch_unpack3(hipStream_t s, const d4 *in, double *out, int n) {
+    k_unpack3<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(in, out, n);
+}
+
+__global__ void k_set_sys(Dev d, double t, double B, double r0, double r1, double r2, double v0, double v1,
+                          double v2, int set_com) {
+    SysScal &y = *d.sys;
+    y.t = t;
+    y.B = B;
+    y.w = 0.0;
+    if (set_com) {
+        y.rcm[0] = r0; y.rcm[1] = r1; y.rcm[2] = r2;
+        y.vcm[0] = v0; y.vcm[1] = v1; y.vcm[2] = v2;
+    }
+    d.ctl->coincident = 0;
+}
+void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, const double *rcm, const double *vcm,
+                    int set_com) {
+    k_set_sys<<<1, 1, 0, s>>>(d, t, B, set_com ? rcm[0] : 0.0, set_com ? rcm[1] : 0.0, set_com ? rcm[2] : 0.0,
+                              set_com ? vcm[0] : 0.0, set_com ? vcm[1] : 0.0, set_com ? vcm[2] : 0.0, set_com);
+}
+
+// Coincident bodies: the nearest neighbour of every body is joined to it by
+// an MST edge, so a zero-length pair shows up as a zero edge vector.
+__global__ __launch_bounds__(kWG) void k_check_coincident(Dev d) {
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    if (v >= d.n || d.parent[v] < 0) return;
+    const d4 x = d.X0[v];
+    if (x.x == 0.0 && x.y == 0.0 && x.z == 0.0) d.ctl->coincident = 1;
+}
+void launch_check_coincident(const Dev &d, hipStream_t s) {
+    k_check_coincident<<<(d.n + kWG - 1) / kWG, kWG, 0, s>>>(d);
+}
+
+}  // namespace mstar

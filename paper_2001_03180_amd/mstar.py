@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libmstar.so (include/mstar.h).
+
+Argument marshalling only: every step of the integrator runs in the HIP
+kernels of the library.  Arrays may be numpy float64 arrays (host memory) or
+contiguous float64 torch CUDA tensors (device memory, passed with
+MSTAR_DEVICE_PTRS).  The library must have been built
+(paper_2001_03180_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmstar.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_COINCIDENT, E_NOCONV, E_MAXSTEPS, E_UNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+W_TIME_TOL = 1
+DEVICE_PTRS = 1
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("flags", C.c_uint32), ("G", C.c_double), ("eta", C.c_double),
+        ("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double), ("omega_mass_max", C.c_double),
+        ("a_gbs", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double), ("q_first", C.c_double),
+        ("t_tol", C.c_double), ("h_init", C.c_double), ("max_steps", C.c_int64), ("k_fix", C.c_int32),
+        ("n_d", C.c_int32), ("max_halvings", C.c_int32), ("max_time_iter", C.c_int32),
+        ("rebuild_every", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("reserved", C.c_uint32), ("steps_accepted", C.c_int64),
+        ("steps_rejected", C.c_int64), ("force_evals", C.c_int64), ("mst_rebuilds", C.c_int64),
+        ("topo_changes", C.c_int64), ("time_iters", C.c_int64), ("t_reached", C.c_double),
+        ("eps_last", C.c_double), ("h_next", C.c_double), ("h_last", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
+
+
+EXPORTS = {
+    "mstar_abi_version": (C.c_int, []),
+    "mstar_params_default": (None, [C.POINTER(Params)]),
+    "mstar_strerror": (C.c_char_p, [C.c_int]),
+    "mstar_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "mstar_destroy": (None, [C.c_void_p]),
+    "mstar_last_error": (C.c_char_p, [C.c_void_p]),
+    "mstar_integrate": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_double, C.c_double, C.POINTER(Stats)]),
+    "mstar_mst_build": (C.c_int, [C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_force": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_leapfrog": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
+    "mstar_gbs_step": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "mstar_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmstar.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2001_03180_amd/build.py "
+                               "(there is no CPU fallback)")
+        _lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+class MstarError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mstar error {code}: {msg}")
+        self.code = code
+
+
+def params(**kw) -> Params:
+    p = Params()
+    lib().mstar_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _Arg:
+    """Pointer to a float64 / int32 array, host (numpy) or device (torch)."""
+
+    def __init__(self, a, dtype, shape=None, writable=False):
+        self.obj = a
+        if _is_torch(a):
+            import torch
+            want = torch.float64 if dtype == np.float64 else torch.int32
+            if a.dtype != want or not a.is_contiguous() or not a.is_cuda:
+                raise TypeError("device arrays must be contiguous CUDA tensors of the right dtype")
+            if shape is not None and tuple(a.shape) != tuple(shape):
+                raise ValueError(f"shape {tuple(a.shape)} != {shape}")
+            self.dev = True
+            self.ptr = C.c_void_p(a.data_ptr())
+        else:
+            if writable:
+                if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags.c_contiguous):
+                    raise TypeError("output arrays must be C-contiguous numpy arrays of the right dtype")
+                arr = a
+            else:
+                arr = np.ascontiguousarray(a, dtype=dtype)
+            if shape is not None and arr.shape != tuple(shape):
+                raise ValueError(f"shape {arr.shape} != {shape}")
+            self.arr = arr
+            self.dev = False
+            self.ptr = C.c_void_p(arr.ctypes.data)
+
+
+def _mode(*args):
+    devs = {a.dev for a in args}
+    if len(devs) != 1:
+        raise TypeError("mix of host and device arrays")
+    if devs.pop():
+        import torch
+        torch.cuda.synchronize()
+        return DEVICE_PTRS
+    return 0
+
+
+class Context:
+    """An mstar_ctx on one HIP device (own stream)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        rc = lib().mstar_create(C.byref(self._h), int(device), None)
+        if rc != OK:
+            raise MstarError(rc, lib().mstar_strerror(rc).decode())
+
+    def close(self):
+        if self._h:
+            lib().mstar_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(OK,)):
+        if rc not in allow:
+            raise MstarError(rc, lib().mstar_last_error(self._h).decode())
+        return rc
+
+    # ---------------------------------------------------------------- calls
+    def mst_build(self, m, x, root_in=-1):
+        """MST of positions x rooted near the COM: (parent, level, root)."""
+        n = len(m)
+        M, X = _Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3))
+        flags = _mode(M, X)
+        if flags:
+            import torch
+            parent = torch.empty(n, dtype=torch.int32, device=x.device)
+            level = torch.empty(n, dtype=torch.int32, device=x.device)
+            root = torch.empty(1, dtype=torch.int32, device=x.device)
+        else:
+            parent, level, root = (np.empty(n, np.int32), np.empty(n, np.int32), np.empty(1, np.int32))
+        P, L, R = (_Arg(parent, np.int32, writable=True), _Arg(level, np.int32, writable=True),
+                   _Arg(root, np.int32, writable=True))
+        self._check(lib().mstar_mst_build(self._h, flags, n, M.ptr, X.ptr, int(root_in), P.ptr, L.ptr, R.ptr))
+        return parent, level, int(root[0])
+
+    def force(self, m, rho, parent, X, p: Params | None = None):
+        """Accelerations [n,3] and force function U with MST separations."""
+        p = p or params()
+        n = len(m)
+        args = [_Arg(m, np.float64, (n,)), _Arg(rho, np.float64, (n, 3)), _Arg(parent, np.int32, (n,)),
+                _Arg(X, np.float64, (n, 3))]
+        flags = _mode(*args)
+        p.flags = flags
+        if flags:
+            import torch
+            acc = torch.empty((n, 3), dtype=torch.float64, device=rho.device)
+            U = torch.empty(1, dtype=torch.float64, device=rho.device)
+        else:
+            acc, U = np.empty((n, 3)), np.empty(1)
+        A, Ua = _Arg(acc, np.float64, writable=True), _Arg(U, np.float64, writable=True)
+        self._check(lib().mstar_force(self._h, C.byref(p), n, args[0].ptr, args[1].ptr, args[2].ptr,
+                                      args[3].ptr, A.ptr, Ua.ptr))
+        return acc, float(U[0])
+
+    def leapfrog(self, m, parent, X, V, scal, H, nsub, p: Params | None = None):
+        """One leapfrog division; returns new (X, V, scal) (host arrays are copied)."""
+        p = p or params()
+        n = len(m)
+        X = np.array(X, dtype=np.float64) if not _is_torch(X) else X.clone()
+        V = np.array(V, dtype=np.float64) if not _is_torch(V) else V.clone()
+        scal = np.array(scal, dtype=np.float64) if not _is_torch(scal) else scal.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(parent, np.int32, (n,)), _Arg(X, np.float64, (n, 3), True),
+             _Arg(V, np.float64, (n, 3), True), _Arg(scal, np.float64, (9,), True)]
+        p.flags = _mode(*a)
+        self._check(lib().mstar_leapfrog(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, a[3].ptr,
+                                         a[4].ptr, float(H), int(nsub)))
+        return X, V, scal
+
+    def gbs_step(self, m, parent, X, V, scal, H, p: Params | None = None):
+        """One GBS step: (X, V, scal, accepted, eps, h_next)."""
+        p = p or params()
+        n = len(m)
+        X = np.array(X, dtype=np.float64) if not _is_torch(X) else X.clone()
+        V = np.array(V, dtype=np.float64) if not _is_torch(V) else V.clone()
+        scal = np.array(scal, dtype=np.float64) if not _is_torch(scal) else scal.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(parent, np.int32, (n,)), _Arg(X, np.float64, (n, 3), True),
+             _Arg(V, np.float64, (n, 3), True), _Arg(scal, np.float64, (9,), True)]
+        p.flags = _mode(*a)
+        acc, eps, hn = C.c_int32(), C.c_double(), C.c_double()
+        self._check(lib().mstar_gbs_step(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, a[3].ptr,
+                                         a[4].ptr, float(H), C.cast(C.pointer(acc), C.c_void_p),
+                                         C.cast(C.pointer(eps), C.c_void_p), C.cast(C.pointer(hn), C.c_void_p)))
+        return X, V, scal, bool(acc.value), eps.value, hn.value
+
+    def integrate(self, m, x, v, t0, t_end, p: Params | None = None, allow=(OK, W_TIME_TOL)):
+        """Integrate in place-copy: returns (x, v, rc, stats dict)."""
+        p = p or params()
+        n = len(m)
+        x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
+        v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
+        p.flags = _mode(*a)
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().mstar_integrate(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), float(t_end),
+                                   C.byref(st))
+        self._check(rc, allow)
+        return x, v, rc, st.as_dict()
+
+    def profile_enable(self, on=True):
+        self._check(lib().mstar_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(force launches, summed force-kernel ms, directed pairs) since enable."""
+        L, ms, pairs = C.c_int64(), C.c_double(), C.c_double()
+        self._check(lib().mstar_profile_read(self._h, C.byref(L), C.byref(ms), C.byref(pairs)))
+        return L.value, ms.value, pairs.value
