@@ -1,0 +1,143 @@
+"""Benchmark: FP64 pair interactions per second of the full MSTAR step at N=5000.
+
+Workload (seeded, synthetic): Plummer sphere of 5000 equal-mass stars (total
+mass 1, Henon units) with an embedded point-mass binary (2 x 0.005, a = 1e-3,
+e = 0.9, random orientation) at its centre -> N_p = 5002 bodies; eta = 1e-13,
+k_fix = 8, N_d = 2, LogH.  One "step" is one GBS step attempt of the
+integrator: MST rebuild (after an accepted step), tree transforms, the start
+force evaluation, all 8 substep divisions (72 force evaluations), Neville
+extrapolation, error test and step control -- every row of the hot path.
+
+value = (force evaluations x N_p (N_p - 1)) / wall time of the timed steps,
+inputs resident in HBM.  The roofline entry is the force kernel's algorithmic
+FLOP rate (20 FP64 flops per directed pair) from HIP events around every
+force launch in the timed region.  cpu_baseline times the CPU oracle (plain C,
+OpenMP over i) on a bounded sample: one GBS step of the same state.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 pair-interactions/s at N=5000; batched subsystems/s vs per-system"
+PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
+FLOPS_PER_PAIR = 20
+
+
+def cpu_baseline(m, x, v, eta, threads):
+    """Oracle GBS steps on the host (bounded sample)."""
+    import numpy as np
+    import oracle
+    p = oracle.params(eta=eta, nthreads=threads)
+    parent, X, V, scal = oracle.build_state(m, x, v)
+    rho = oracle.deconstruct(parent, X)
+    _, _, U, _, _ = oracle.force(m, parent, X, rho, p)
+    vt = v - (m[:, None] * v).sum(0) / m.sum()
+    scal[1] = U - 0.5 * (m * (vt ** 2).sum(1)).sum()
+    H = 1e-5
+    t0 = time.perf_counter()
+    out = oracle.gbs_step(m, parent, X, V, scal, H, p)
+    dt = time.perf_counter() - t0
+    n = len(m)
+    pairs = out[6] * n * (n - 1)
+    return dict(value=pairs / dt, unit="pair-interactions/s", cores=threads, kind="oracle",
+                sample=f"one GBS step (k_fix=8: {out[6]} force evaluations) at N_p={n}, "
+                       f"{dt:.1f} s on {threads} OpenMP threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=25)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import ics
+    import paper_2001_03180_amd as M
+
+    m, x, v, wl = ics.workload("plummer5000_binary")
+    n = len(m)
+    eta = wl["eta"]
+    ctx = M.Context(0)
+    base = dict(eta=eta, k_fix=8, n_d=2)
+
+    # warmup: from the initial conditions (absorbs the first-step halvings)
+    xw, vw, rc, stw = ctx.integrate(m, x, v, 0.0, wl["t_end"], M.params(max_steps=args.warmup, **base),
+                                    allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
+    t1, h1 = stw["t_reached"], stw["h_next"]
+    # timed: continue from the warmed-up state with the controller's step
+    mt = torch.tensor(m, device="cuda")
+    xt = torch.tensor(xw, device="cuda")
+    vt = torch.tensor(vw, device="cuda")
+    p = M.params(max_steps=args.steps, h_init=h1, **base)
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xo, vo, rc, st = ctx.integrate(mt, xt, vt, t1, wl["t_end"], p, allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, kern_ms, kern_pairs = ctx.profile_read()
+    ctx.profile_enable(False)
+    steps_done = st["steps_accepted"] + st["steps_rejected"]
+    pairs = st["force_evals"] * n * (n - 1)
+    value = pairs / wall
+    avg_launch_s = kern_ms * 1e-3 / max(launches, 1)
+    flops_per_launch = FLOPS_PER_PAIR * kern_pairs / max(launches, 1)
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": steps_done,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / max(steps_done, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plummer5000_binary: Plummer N=5000 (seed 301) + point-mass binary 2x0.005, a=1e-3, "
+                        "e=0.9 (N_p=5002); eta=1e-13, k_fix=8, N_d=2, LogH; one step = one GBS step attempt",
+            "n_bodies": n,
+            "force_evals": st["force_evals"],
+            "steps_accepted": st["steps_accepted"],
+            "steps_rejected": st["steps_rejected"],
+            "mst_rebuilds": st["mst_rebuilds"],
+            "t_start": t1,
+            "t_reached": st["t_reached"],
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "k_force (FP64 pair loop)",
+            "launches": launches,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
+        },
+    }
+    ctx.close()
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+        out["cpu_baseline"] = cpu_baseline(m, x, v, eta, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
