@@ -36,6 +36,8 @@ struct mstar_ctx {
     double *xin = nullptr, *vin = nullptr, *xout = nullptr;   // staging [3n]
     Ctl *h_ctl = nullptr;       // pinned host copies
     SysScal *h_sys = nullptr;
+    int32_t *h_flags = nullptr; // [done, rounds]
+    int mst_rounds_est = 0;     // Boruvka rounds of the previous build
     // profiling of the force kernel
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -47,7 +49,7 @@ struct mstar_ctx {
 namespace {
 
 constexpr int kNsplitMax = 32;
-constexpr int kTargetWG = 2560;
+constexpr int kTargetWaves = 8192;   // ~8 waves per SIMD over 256 CUs
 
 int fail(mstar_ctx *c, int code, const char *fmt, ...) {
     if (c) {
@@ -91,6 +93,7 @@ int ensure(mstar_ctx *ctx, int n) {
         ctx->d.n = n;
         ctx->d.nib = (n + 63) / 64;
         ctx->d.nkwg = (n + kWG - 1) / kWG;
+        ctx->d.nkwg4 = (n + kWG / 4 - 1) / (kWG / 4);
         return MSTAR_OK;
     }
     HIPCK(hipStreamSynchronize(ctx->stream));
@@ -105,10 +108,11 @@ int ensure(mstar_ctx *ctx, int n) {
     A(d.parent, N) A(d.level, N) A(d.parent_new, N) A(d.level_new, N) A(d.child_off, N + 1) A(d.child_idx, N)
     A(d.root, 1) A(d.X0, N) A(d.V0, N) A(d.a0, N) A(d.m, N) A(d.sys, 1) A(d.ctl, 1)
     A(d.P, kMaxDiv * N) A(d.Vt, kMaxDiv * N) A(d.dX, kMaxDiv * N) A(d.dV, kMaxDiv * N) A(d.dX1, N) A(d.dV1, N)
+    A(d.dP, kMaxDiv * N) A(d.dVt, kMaxDiv * N) A(d.dP1, N) A(d.dVt1, N)
     A(d.dscal, kMaxDiv) A(d.dscal1, 1) A(d.part, (size_t)kMaxDiv * kNsplitMax * N)
-    A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * nkwg) A(d.epspart, nkwg + 1)
+    A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, nkwg + 1)
     A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)
-    A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.comp, N) A(d.ecomp_tmp, N)
+    A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.rounds, 1) A(d.comp, N) A(d.ecomp_tmp, N)
     A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.done, 1) A(d.ncomp, 1)
     A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
     A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N)
@@ -124,15 +128,20 @@ int ensure(mstar_ctx *ctx, int n) {
     d.n = n;
     d.nib = (n + 63) / 64;
     d.nkwg = (n + kWG - 1) / kWG;
+    d.nkwg4 = (n + kWG / 4 - 1) / (kWG / 4);
     return MSTAR_OK;
 }
 
-constexpr int kBase = kMaxDiv - 1;   // slot of the start state
+constexpr int kBase = kBaseSlot;     // slot of the start state
+constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
 
+// Number of workgroups sharing one i-block's j-range: enough waves to fill
+// the chip, at least 16 j-bodies per wave.
 int nsplit_for(const Dev &d, int nact) {
-    int ns = (kTargetWG + nact * d.nib - 1) / (nact * d.nib);
+    const int per = nact * d.nib * kForceWaves;
+    int ns = (kTargetWaves + per - 1) / per;
     ns = std::max(1, std::min(ns, kNsplitMax));
-    ns = std::min(ns, std::max(1, d.n / 64));
+    ns = std::min(ns, std::max(1, d.n / (16 * kForceWaves)));
     return ns;
 }
 
@@ -246,24 +255,26 @@ int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit) {
     return MSTAR_OK;
 }
 
-// Start-of-step quantities: tree sums of the MST state, COM-frame positions
-// and velocities, T0; optionally the force at the start state (a0, U0) for
-// S'(s0) of eq. gbs-criterion and the end-time clip.
 // The start-state slot has no increments; its dX rows must read as zero for
 // the close-pair correction (the slot region moves with n, so clear it).
 int zero_base_increments(mstar_ctx *ctx) {
     const Dev &d = ctx->d;
     HIPCK(hipMemsetAsync(d.dX + (size_t)kBase * d.n, 0, sizeof(d4) * d.n, ctx->stream));
-    HIPCK(hipMemsetAsync(d.dV + (size_t)kBase * d.n, 0, sizeof(d4) * d.n, ctx->stream));
     return MSTAR_OK;
 }
 
-int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool with_force, int64_t *nforce) {
+// Start-of-step quantities.  With `transform`: COM-frame positions and
+// velocities of the start state from tree sums of the MST edges (Sec. 2.2
+// deconstruction) and T.  With `with_force`: the force at the start state
+// (a0, U0) for S'(s0) of eq. gbs-criterion and the end-time clip.
+int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool with_force, int64_t *nforce) {
     const Dev &d = ctx->d;
     int rc0 = zero_base_increments(ctx);
     if (rc0) return rc0;
-    launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
-    launch_com_frame(d, ctx->stream, kBase);
+    if (transform) {
+        launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
+        launch_com_frame(d, ctx->stream, kBase);
+    }
     if (with_force) {
         SlotList sl{};
         sl.nact = 1;
@@ -320,12 +331,41 @@ int read_ctl(mstar_ctx *ctx) {
     return MSTAR_OK;
 }
 
-// New MST from the current state (Sec. 3.5).
+// MST of the complete graph on `pos` (Sec. 3.1-3.4): as many Boruvka rounds
+// as the previous build needed, a check of completion on the host, more
+// rounds if needed, then rooting.
+int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in) {
+    const Dev &d = ctx->d;
+    int maxr = 2;
+    for (int m = 1; m < d.n; m <<= 1) ++maxr;
+    const int ns = std::max(1, std::min(8, d.n / 64));   // j-splits of the Boruvka scan
+    launch_mst_init(d, ctx->stream, pos, root_in);
+    int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est, maxr) : maxr - 2;
+    launch_mst_rounds(d, ctx->stream, pos, est, ns);
+    for (int extra = 0;; ++extra) {
+        HIPCK(hipMemcpyAsync(ctx->h_flags, d.done, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipMemcpyAsync(ctx->h_flags + 1, d.rounds, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipStreamSynchronize(ctx->stream));
+        if (ctx->h_flags[0]) break;
+        if (est + extra >= 4 * maxr) return fail(ctx, MSTAR_E_DEVICE, "MST did not complete");
+        launch_mst_rounds(d, ctx->stream, pos, 1, ns);
+    }
+    ctx->mst_rounds_est = ctx->h_flags[1];
+    launch_mst_root(d, ctx->stream);
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+// New MST from the current state (Sec. 3.5), built on the COM-frame positions
+// of the start state; far-pair edges of the new tree come from those
+// positions and velocities.
 int rebuild(mstar_ctx *ctx, const mstar_params *p) {
     const Dev &d = ctx->d;
-    launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
-    launch_mst(d, ctx->stream, d.tsA, -1, nsplit_for(d, 1));
-    launch_rebuild_edges(d, ctx->stream, d.tsA, d.tsB, p->n_d);
+    const d4 *pos = d.P + (size_t)kBase * d.n;
+    const d4 *vel = d.Vt + (size_t)kBase * d.n;
+    int rc = build_mst(ctx, pos, -1);
+    if (rc) return rc;
+    launch_rebuild_edges(d, ctx->stream, pos, vel, p->n_d);
     HIPCK(hipGetLastError());
     return MSTAR_OK;
 }
@@ -428,7 +468,8 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         ctx->own_stream = true;
     }
     if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_sys, sizeof(SysScal), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&ctx->h_sys, sizeof(SysScal), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         mstar_destroy(ctx);
         return MSTAR_E_NOMEM;
     }
@@ -444,6 +485,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     if (ctx->h_sys) (void)hipHostFree(ctx->h_sys);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -490,7 +532,7 @@ int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, 
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
     const Dev &d = ctx->d;
     launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
-    launch_mst(d, ctx->stream, d.tsA, (root_in >= 0 && root_in < n) ? root_in : -1, nsplit_for(d, 1));
+    if ((rc = build_mst(ctx, d.tsA, (root_in >= 0 && root_in < n) ? root_in : -1))) return rc;
     launch_tree_finish(d, ctx->stream);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, parent, d.parent, sizeof(int32_t) * n))) return rc;
@@ -547,7 +589,7 @@ int mstar_leapfrog(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     if ((rc = ensure(ctx, (int)n))) return rc;
     if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
     if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
-    if ((rc = prepare_start(ctx, params, false, nullptr))) return rc;
+    if ((rc = prepare_start(ctx, params, true, false, nullptr))) return rc;
     launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
     const int nl[1] = {nsub};
     if ((rc = run_divisions(ctx, params, nl, 1, nullptr))) return rc;
@@ -568,7 +610,7 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     if ((rc = ensure(ctx, (int)n))) return rc;
     if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
     if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
-    if ((rc = prepare_start(ctx, params, true, nullptr))) return rc;
+    if ((rc = prepare_start(ctx, params, true, true, nullptr))) return rc;
     launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
     int nl[16];
     for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
@@ -607,19 +649,19 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
     if ((rc = in_dev(ctx, flags, v, ctx->vin, sizeof(double) * 3 * n, &vd))) return rc;
     // initial MST on the Cartesian positions, edge vectors, COM
     launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
-    launch_mst(d, ctx->stream, d.tsA, -1, nsplit_for(d, 1));
+    if ((rc = build_mst(ctx, d.tsA, -1))) return rc;
     launch_tree_finish(d, ctx->stream);
     launch_set_sys(d, ctx->stream, t0, 0.0, nullptr, nullptr, 0);
     launch_state_from_cartesian(d, ctx->stream, (const double *)xd, (const double *)vd);
     launch_check_coincident(d, ctx->stream);
-    if ((rc = prepare_start(ctx, &p, true, &st.force_evals))) return rc;
+    if ((rc = prepare_start(ctx, &p, true, true, &st.force_evals))) return rc;
     launch_set_B(d, ctx->stream);
     if ((rc = read_ctl(ctx))) return rc;
     if (ctx->h_ctl->coincident) return fail(ctx, MSTAR_E_COINCIDENT, "two bodies share a position");
     const double gk0 = p.alpha * ctx->h_ctl->U0 + p.gamma;
     double H = p.h_init > 0.0 ? p.h_init : p.q_first * gk0 * (t_end - t0);
     const double span = std::fabs(t_end - t0);
-    int halvings = 0, since_rebuild = 0;
+    int halvings = 0, since_rebuild = 0, since_resync = 0;
     bool fresh = false;   // the start state was just prepared
     bool just_rebuilt = false;
     int nl[16];
@@ -634,7 +676,9 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
                 since_rebuild = 0;
                 just_rebuilt = true;
             }
-            if ((rc = prepare_start(ctx, &p, true, &st.force_evals))) break;
+            const bool resync = since_resync >= kResyncEvery;
+            if (resync) since_resync = 0;
+            if ((rc = prepare_start(ctx, &p, resync, true, &st.force_evals))) break;
             fresh = false;
         }
         launch_set_h(d, ctx->stream, H, t_end, 1, p.alpha, p.gamma);
@@ -657,6 +701,7 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
         st.h_last = H;
         halvings = 0;
         since_rebuild++;
+        since_resync++;
         fresh = true;
         if (c.clipped) st.time_iters++;
         H = c.h_next;

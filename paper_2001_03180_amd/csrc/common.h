@@ -15,7 +15,9 @@ struct __attribute__((aligned(32))) d4 {
 };
 
 constexpr int kMaxDiv = 17;        // k_fix <= 16 divisions plus the start-state slot
+constexpr int kBaseSlot = kMaxDiv - 1;   // slot holding the start state of a GBS step
 constexpr int kWG = 256;           // threads per workgroup of the O(N) kernels
+constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, split j-range)
 constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
 
 // 1/sqrt(x) for x > 0 to <= 1 ulp: the hardware estimate v_rsq_f64 (relative
@@ -101,20 +103,22 @@ struct Dev {
     SysScal *sys;
     Ctl *ctl;
     // divisions (slot-major)
-    d4 *P, *Vt, *dX, *dV;       // [slot][n]
-    d4 *dX1, *dV1;              // extrapolated increments
+    d4 *P, *Vt, *dX, *dV;       // [slot][n]: positions+mass, COM-frame velocities, edge increments
+    d4 *dP, *dVt;               // [slot][n]: increments of positions / velocities
+    d4 *dX1, *dV1, *dP1, *dVt1; // extrapolated increments
     DivScal *dscal, *dscal1;    // [slot], extrapolated
     d4 *part;                   // force partials [slot][nsplit_max][n]
     double *Upart;              // [slot][nib * nsplit_max]
-    double *Tpart;              // [slot][nkwg]
+    double *Tpart;              // [slot][nkwg4] (kick: nkwg4 workgroups; commit: nkwg)
     double *epspart;            // [nkwg + 1]
-    int nsplit_max, nkwg;
+    int nsplit_max, nkwg, nkwg4;  // nkwg = ceil(n/256), nkwg4 = ceil(n/64)
     // tree scratch
     d4 *tsA, *tsB;              // tree sums: root-relative positions / velocities
     d4 *tsC, *tsD, *tsE, *tsF;  // ping-pong scratch
     int32_t *ancA, *ancB;
-    double *bor_w;              // Boruvka partial best weight [nsplit][n]
-    int32_t *bor_j;             // Boruvka partial best index [nsplit][n]
+    double *bor_w;              // Boruvka per-split best weight [nsplit][n]
+    int32_t *bor_j;             // Boruvka per-split best index [nsplit][n]
+    int32_t *rounds;            // Boruvka rounds taken by the last build
     int32_t *comp, *ecomp_tmp;
     unsigned long long *cw, *cidx;
     int32_t *tgt, *elo, *ehi, *hooked, *done, *ncomp;
@@ -148,7 +152,9 @@ void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, const doubl
 void launch_check_coincident(const Dev &d, hipStream_t s);
 // kernels_tree.hip
 void launch_tree_sums(const Dev &d, hipStream_t s, const d4 *X, const d4 *V, d4 *rho, d4 *ups);
-int launch_mst(const Dev &d, hipStream_t s, const d4 *pos, int root_in, int nsplit);
+void launch_mst_init(const Dev &d, hipStream_t s, const d4 *pos, int root_in);
+void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, int nsplit);
+void launch_mst_root(const Dev &d, hipStream_t s);
 void launch_tree_finish(const Dev &d, hipStream_t s);
 void launch_rebuild_edges(const Dev &d, hipStream_t s, const d4 *rho, const d4 *ups, int nd);
 void launch_levels_children(const Dev &d, hipStream_t s);

@@ -3,11 +3,11 @@
 // force loop).
 //
 // Layout: positions are 32-byte records {x, y, z, m} in the centre-of-mass
-// frame, one array per division slot.  One workgroup = 4 waves sharing the
-// same 64 i-bodies (one per lane) and splitting the workgroup's j-range in
-// four; the j-body of each iteration is wave-uniform and is fetched with a
+// frame, one array per division slot.  One workgroup = kForceWaves waves
+// sharing the same 64 i-bodies (one per lane) and splitting the workgroup's
+// j-range between them; the j-body of each iteration is wave-uniform and is fetched with a
 // scalar load straight into SGPRs, so the inner loop is pure FP64 VALU work
-// with no LDS traffic.  Partial sums of the four waves are combined in LDS
+// with no LDS traffic.  Partial sums of the waves are combined in LDS
 // in fixed order; j-splits across workgroups are combined later in fixed
 // order, so results are bitwise reproducible.
 //
@@ -90,7 +90,7 @@ __device__ void close_correction(int i, const d4 *P, const d4 *X0, const d4 *dX,
 template <bool GUARD>
 __device__ __forceinline__ void j_loop(const d4 *__restrict__ P, int jb, int je, int ii, const d4 &pi,
                                        double &ax, double &ay, double &az, double &ph) {
-#pragma unroll 4
+#pragma unroll 8
     for (int j = jb; j < je; ++j) {
         const d4 pj = P[j];
         const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
@@ -111,8 +111,8 @@ __device__ __forceinline__ void j_loop(const d4 *__restrict__ P, int jb, int je,
     }
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_force(ForceArgs a) {
+template <int ND, int NW>
+__global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ib = blockIdx.x % a.nib;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     const d4 pi = P[ii];
     const int j0 = split * a.jchunk;
     const int j1 = min(n, j0 + a.jchunk);
-    const int q = (max(j1 - j0, 0) + 3) >> 2;
+    const int q = (max(j1 - j0, 0) + NW - 1) / NW;
     int jb = min(j1, j0 + wv * q);
     int je = min(j1, jb + q);
     jb = __builtin_amdgcn_readfirstlane(jb);
@@ -141,12 +141,12 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     } else {
         j_loop<false>(P, jb, je, ii, pi, ax, ay, az, ph);
     }
-    __shared__ d4 red[4][64];
+    __shared__ d4 red[NW][64];
     red[wv][lane] = d4{ax, ay, az, ph};
     __syncthreads();
     if (wv != 0) return;
     d4 s = red[0][lane];
-    for (int w = 1; w < 4; ++w) {
+    for (int w = 1; w < NW; ++w) {
         const d4 t = red[w][lane];
         s.x = s.x + t.x; s.y = s.y + t.y; s.z = s.z + t.z; s.w = s.w + t.w;
     }
@@ -177,9 +177,10 @@ void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int n
     a.jchunk = (d.n + nsplit - 1) / nsplit;
     a.sl = sl;
     dim3 grid(sl.nact * d.nib, nsplit);
-    if (nd <= 0) k_force<0><<<grid, 256, 0, s>>>(a);
-    else if (nd == 1) k_force<1><<<grid, 256, 0, s>>>(a);
-    else k_force<2><<<grid, 256, 0, s>>>(a);
+    constexpr int NW = kForceWaves;
+    if (nd <= 0) k_force<0, NW><<<grid, 64 * NW, 0, s>>>(a);
+    else if (nd == 1) k_force<1, NW><<<grid, 64 * NW, 0, s>>>(a);
+    else k_force<2, NW><<<grid, 64 * NW, 0, s>>>(a);
 }
 
 // Reduce the force partials of one slot: acc = G sum_split part, and the

@@ -24,6 +24,8 @@ __global__ __launch_bounds__(kWG) void k_div_init(Dev d, int ndiv, int base) {
         d.Vt[o] = d.Vt[(size_t)base * n + v];
         d.dX[o] = d4{0.0, 0.0, 0.0, 0.0};
         d.dV[o] = d4{0.0, 0.0, 0.0, 0.0};
+        d.dP[o] = d4{0.0, 0.0, 0.0, 0.0};
+        d.dVt[o] = d4{0.0, 0.0, 0.0, 0.0};
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{0.0, 0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
 }
@@ -34,7 +36,8 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
 }
 
 // Drift D(ds): dt = ds / (alpha (T + B) + gamma); X += dt V; positions +=
-// dt v; t += dt; r_cm += dt v_cm.
+// dt v (kept as increments dP from the start positions, P = P0 + dP);
+// t += dt; r_cm += dt v_cm.
 __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha, double gamma) {
     __shared__ double sh[kWG];
     const int ai = blockIdx.y;
@@ -44,9 +47,9 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha,
     if (sl.first[ai]) {
         T = d.ctl->T0;
     } else {
-        const double *tp = d.Tpart + (size_t)slot * d.nkwg;
+        const double *tp = d.Tpart + (size_t)slot * d.nkwg4;
         double t = 0.0;
-        for (int k = threadIdx.x; k < d.nkwg; k += kWG) t = t + tp[k];
+        for (int k = threadIdx.x; k < d.nkwg4; k += kWG) t = t + tp[k];
         T = 0.5 * block_sum<kWG>(t, sh);
     }
     const double H = d.ctl->H;
@@ -65,11 +68,13 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha,
             d.dX[o] = dX;
         }
         const d4 vt = d.Vt[o];
-        d4 p = d.P[o];
-        p.x = p.x + dt * vt.x;
-        p.y = p.y + dt * vt.y;
-        p.z = p.z + dt * vt.z;
-        d.P[o] = p;
+        const d4 p0 = d.P[(size_t)kBaseSlot * n + v];
+        d4 dp = d.dP[o];
+        dp.x = dp.x + dt * vt.x;
+        dp.y = dp.y + dt * vt.y;
+        dp.z = dp.z + dt * vt.z;
+        d.dP[o] = dp;
+        d.P[o] = d4{p0.x + dp.x, p0.y + dp.y, p0.z + dp.z, p0.w};
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DivScal &q = d.dscal[slot];
@@ -84,10 +89,12 @@ void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, double alpha,
 }
 
 // Kick K(ds): dt = ds / (alpha U + gamma); V_v += dt (a_v - a_parent(v));
-// COM-frame velocities v += dt a; partial sums of m |v|^2 for the next drift.
+// COM-frame velocities v += dt a (as increments dVt, v = v0 + dVt); partial
+// sums of m |v|^2 for the next drift.
 __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, double alpha,
                                              double gamma) {
     __shared__ double sh[kWG];
+    __shared__ d4 ra[kWG], rb[kWG];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
@@ -99,45 +106,59 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     const double H = d.ctl->H;
     const double ds = H / (double)sl.nsub[ai];
     const double dt = ds / (alpha * U + gamma);
-    const int v = blockIdx.x * kWG + threadIdx.x;
-    double tl = 0.0;
+    // four threads per body: fixed quarter of the split partials each
+    const int v = blockIdx.x * (kWG / 4) + (threadIdx.x >> 2);
+    const int part = threadIdx.x & 3;
+    const d4 *pp = d.part + (size_t)slot * d.nsplit_max * n;
+    d4 sa{0.0, 0.0, 0.0, 0.0}, sb{0.0, 0.0, 0.0, 0.0};
+    const int p = v < n ? d.parent[v] : -1;
     if (v < n) {
-        const d4 *pp = d.part + (size_t)slot * d.nsplit_max * n;
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int sp = 0; sp < nsplit; ++sp) {
+        for (int sp = part; sp < nsplit; sp += 4) {
             const d4 t = pp[(size_t)sp * n + v];
-            ax = ax + t.x; ay = ay + t.y; az = az + t.z;
+            sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
+            if (p >= 0) {
+                const d4 t2 = pp[(size_t)sp * n + p];
+                sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
+            }
         }
-        ax = G * ax; ay = G * ay; az = G * az;
-        const int p = d.parent[v];
+    }
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    double tl = 0.0;
+    if (part == 0 && v < n) {
+        for (int k = 1; k < 4; ++k) {
+            const d4 t = ra[threadIdx.x + k], t2 = rb[threadIdx.x + k];
+            sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
+            sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
+        }
+        const double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
         const size_t o = (size_t)slot * n + v;
         if (p >= 0) {
-            double bx = 0.0, by = 0.0, bz = 0.0;
-            for (int sp = 0; sp < nsplit; ++sp) {
-                const d4 t = pp[(size_t)sp * n + p];
-                bx = bx + t.x; by = by + t.y; bz = bz + t.z;
-            }
-            bx = G * bx; by = G * by; bz = G * bz;
+            const double bx = G * sb.x, by = G * sb.y, bz = G * sb.z;
             d4 dV = d.dV[o];
             dV.x = dV.x + dt * (ax - bx);
             dV.y = dV.y + dt * (ay - by);
             dV.z = dV.z + dt * (az - bz);
             d.dV[o] = dV;
         }
-        d4 vt = d.Vt[o];
-        vt.x = vt.x + dt * ax;
-        vt.y = vt.y + dt * ay;
-        vt.z = vt.z + dt * az;
+        d4 dvt = d.dVt[o];
+        dvt.x = dvt.x + dt * ax;
+        dvt.y = dvt.y + dt * ay;
+        dvt.z = dvt.z + dt * az;
+        d.dVt[o] = dvt;
+        const d4 v0 = d.Vt[(size_t)kBaseSlot * n + v];
+        const d4 vt{v0.x + dvt.x, v0.y + dvt.y, v0.z + dvt.z, 0.0};
         d.Vt[o] = vt;
         tl = d.P[o].w * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
     }
     const double ts = block_sum<kWG>(tl, sh);
-    if (threadIdx.x == 0) d.Tpart[(size_t)slot * d.nkwg + blockIdx.x] = ts;
+    if (threadIdx.x == 0) d.Tpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ts;
 }
 
 void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, double alpha,
                  double gamma) {
-    dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
+    dim3 grid((d.n + kWG / 4 - 1) / (kWG / 4), sl.nact);
     k_kick<<<grid, kWG, 0, s>>>(d, sl, nsplit, G, alpha, gamma);
 }
 
@@ -146,6 +167,12 @@ void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, do
 // (nor may the step point away from it); otherwise ds = (alpha U + gamma)(t_end - t).
 __global__ void k_set_h(Dev d, double H, double t_end, int clip, double alpha, double gamma) {
     Ctl &c = *d.ctl;
+    {   // T of the start state from the per-workgroup partials left by the commit
+        const double *tp = d.Tpart + (size_t)kBaseSlot * d.nkwg4;
+        double t = 0.0;
+        for (int k = 0; k < d.nkwg; ++k) t = t + tp[k];
+        c.T0 = 0.5 * t;
+    }
     const double gk = alpha * c.U0 + gamma;
     c.gk0 = gk;
     c.clipped = 0;
@@ -198,6 +225,29 @@ __device__ __forceinline__ double fmax_nan(double a, double b) {
 }
 
 template <int KF>
+__device__ __forceinline__ void load_col(const d4 *arr, int n, int v, double (&x)[KF], double (&y)[KF],
+                                         double (&z)[KF]) {
+#pragma unroll
+    for (int k = 0; k < KF; ++k) {
+        const d4 a = arr[(size_t)k * n + v];
+        x[k] = a.x; y[k] = a.y; z[k] = a.z;
+    }
+}
+
+// Extrapolate the increments of one 3-vector per body over the KF divisions;
+// returns T_{KF,KF} in out and T_{KF,KF} - T_{KF-1,KF-1} in diff.
+template <int KF>
+__device__ __forceinline__ void extrap3(const d4 *arr, int n, int v, d4 &out, double &ex, double &ey, double &ez) {
+    double x[KF], y[KF], z[KF];
+    load_col<KF>(arr, n, v, x, y, z);
+    neville<KF>(x); neville<KF>(y); neville<KF>(z);
+    out = d4{x[KF - 1], y[KF - 1], z[KF - 1], 0.0};
+    ex = x[KF - 1] - x[KF - 2];
+    ey = y[KF - 1] - y[KF - 2];
+    ez = z[KF - 1] - z[KF - 2];
+}
+
+template <int KF>
 __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, double alpha, double gamma, int base) {
     __shared__ double sh[kWG];
     const int n = d.n;
@@ -209,26 +259,23 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, double alpha, double
     const double gk = alpha * c.U0 + gamma;
     double eps = 0.0;
     if (v < n) {
-        double px[KF], py[KF], pz[KF], qx[KF], qy[KF], qz[KF];
-#pragma unroll
-        for (int k = 0; k < KF; ++k) {
-            const d4 a = d.dX[(size_t)k * n + v];
-            const d4 b = d.dV[(size_t)k * n + v];
-            px[k] = a.x; py[k] = a.y; pz[k] = a.z;
-            qx[k] = b.x; qy[k] = b.y; qz[k] = b.z;
-        }
-        neville<KF>(px); neville<KF>(py); neville<KF>(pz);
-        neville<KF>(qx); neville<KF>(qy); neville<KF>(qz);
-        d.dX1[v] = d4{px[KF - 1], py[KF - 1], pz[KF - 1], 0.0};
-        d.dV1[v] = d4{qx[KF - 1], qy[KF - 1], qz[KF - 1], 0.0};
+        d4 ox, ov, op, ow;
+        double xx, xy, xz, vx, vy, vz, t0, t1, t2;
+        extrap3<KF>(d.dX, n, v, ox, xx, xy, xz);
+        extrap3<KF>(d.dV, n, v, ov, vx, vy, vz);
+        extrap3<KF>(d.dP, n, v, op, t0, t1, t2);     // positions and velocities are carried
+        extrap3<KF>(d.dVt, n, v, ow, t0, t1, t2);    // along; they are not error-tested
+        d.dX1[v] = ox;
+        d.dV1[v] = ov;
+        d.dP1[v] = op;
+        d.dVt1[v] = ow;
         const int p = d.parent[v];
         if (p >= 0) {
             const d4 X0 = d.X0[v], V0 = d.V0[v];
             const d4 av = d.a0[v], ap = d.a0[p];
-            const double ex = group_err(px[KF - 1] - px[KF - 2], py[KF - 1] - py[KF - 2], pz[KF - 1] - pz[KF - 2],
-                                        X0.x + hn * (V0.x / gd), X0.y + hn * (V0.y / gd), X0.z + hn * (V0.z / gd));
-            const double ev = group_err(qx[KF - 1] - qx[KF - 2], qy[KF - 1] - qy[KF - 2], qz[KF - 1] - qz[KF - 2],
-                                        V0.x + hn * ((av.x - ap.x) / gk), V0.y + hn * ((av.y - ap.y) / gk),
+            const double ex = group_err(xx, xy, xz, X0.x + hn * (V0.x / gd), X0.y + hn * (V0.y / gd),
+                                        X0.z + hn * (V0.z / gd));
+            const double ev = group_err(vx, vy, vz, V0.x + hn * ((av.x - ap.x) / gk), V0.y + hn * ((av.y - ap.y) / gk),
                                         V0.z + hn * ((av.z - ap.z) / gk));
             eps = fmax_nan(ex, ev);
         }
@@ -296,13 +343,21 @@ void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gb
 }
 
 // Commit the extrapolated increments (if the step was accepted) or the end
-// state of division `slot` (from_extrap = 0, used by the single-leapfrog call).
+// state of division `slot` (from_extrap = 0, used by the single-leapfrog
+// call): MST edges, COM-frame positions and velocities, t, r_cm; partial sums
+// of m |v|^2 of the new start state for T.
 __global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot) {
+    __shared__ double sh[kWG];
     if (from_extrap && !d.ctl->accepted) return;
     const int n = d.n;
     const int v = blockIdx.x * kWG + threadIdx.x;
+    const size_t o = (size_t)slot * n + v;
     const d4 *dx = from_extrap ? d.dX1 : d.dX + (size_t)slot * n;
     const d4 *dv = from_extrap ? d.dV1 : d.dV + (size_t)slot * n;
+    const d4 *dp = from_extrap ? d.dP1 : d.dP + (size_t)slot * n;
+    const d4 *dw = from_extrap ? d.dVt1 : d.dVt + (size_t)slot * n;
+    (void)o;
+    double tl = 0.0;
     if (v < n) {
         d4 X = d.X0[v], V = d.V0[v];
         const d4 a = dx[v], b = dv[v];
@@ -310,7 +365,17 @@ __global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot
         V.x = V.x + b.x; V.y = V.y + b.y; V.z = V.z + b.z;
         d.X0[v] = X;
         d.V0[v] = V;
+        const size_t ob = (size_t)kBaseSlot * n + v;
+        d4 P = d.P[ob], W = d.Vt[ob];
+        const d4 e = dp[v], f = dw[v];
+        P.x = P.x + e.x; P.y = P.y + e.y; P.z = P.z + e.z;
+        W.x = W.x + f.x; W.y = W.y + f.y; W.z = W.z + f.z;
+        d.P[ob] = P;
+        d.Vt[ob] = W;
+        tl = P.w * ((W.x * W.x + W.y * W.y) + W.z * W.z);
     }
+    const double ts = block_sum<kWG>(tl, sh);
+    if (threadIdx.x == 0) d.Tpart[(size_t)kBaseSlot * d.nkwg4 + blockIdx.x] = ts;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const DivScal q = from_extrap ? *d.dscal1 : d.dscal[slot];
         SysScal &y = *d.sys;
@@ -390,8 +455,10 @@ __global__ __launch_bounds__(kTreeWG) void k_com_frame(Dev d, int base) {
         V0[u] = vt;
         tl = tl + mu * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
     }
-    const double T = 0.5 * block_sum<kTreeWG>(tl, sh);
-    if (threadIdx.x == 0) d.ctl->T0 = T;
+    const double T2 = block_sum<kTreeWG>(tl, sh);
+    double *tp = d.Tpart + (size_t)kBaseSlot * d.nkwg4;
+    for (int k = threadIdx.x; k < d.nkwg; k += kTreeWG) tp[k] = (k == 0) ? T2 : 0.0;
+    if (threadIdx.x == 0) d.ctl->T0 = 0.5 * T2;
 }
 
 void launch_com_frame(const Dev &d, hipStream_t s, int base) { k_com_frame<<<1, kTreeWG, 0, s>>>(d, base); }

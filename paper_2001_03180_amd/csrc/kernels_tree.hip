@@ -86,10 +86,14 @@ __global__ __launch_bounds__(kTreeWG) void k_mst_init(Dev d, const d4 *pos, int 
     for (int v = threadIdx.x; v < n; v += kTreeWG) {
         d.comp[v] = v;
         d.hooked[v] = 0;
+        d.cw[v] = ~0ull;
+        d.cidx[v] = ~0ull;
+        d.parent_new[v] = -1;
     }
     if (threadIdx.x == 0) {
         *d.done = 0;
         *d.ncomp = n;
+        *d.rounds = 0;
     }
     if (root_in >= 0 && root_in < n) {
         if (threadIdx.x == 0) *d.root = root_in;
@@ -128,9 +132,10 @@ __global__ __launch_bounds__(kTreeWG) void k_mst_init(Dev d, const d4 *pos, int 
 }
 
 // One Boruvka scan: for every body i the lightest edge (w, j) to a body of
-// another component, over the workgroup's j-range (j ascending per lane, so
+// another component over the workgroup's j-range (j ascending per lane, so
 // equal weights keep the smaller j, i.e. the strict order for fixed i).
-__global__ __launch_bounds__(256) void k_bor_scan(Dev d, const d4 *__restrict__ pos, int nsplit, int jchunk) {
+// Workgroup = 4 waves sharing 64 bodies, each a quarter of the j-range.
+__global__ __launch_bounds__(256) void k_bor_scan(Dev d, const d4 *__restrict__ pos, int jchunk) {
     if (*d.done) return;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -173,95 +178,140 @@ __global__ __launch_bounds__(256) void k_bor_scan(Dev d, const d4 *__restrict__ 
     d.bor_j[(size_t)blockIdx.y * n + i] = bj;
 }
 
-// Component minimum, hooking and contraction (one workgroup).
-__global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d, int nsplit) {
-    __shared__ int changed;
-    __shared__ int cnt;
+// Per body: the best of the split results in (w, j) order (four threads per
+// body, each a fixed quarter of the splits, combined in fixed order); the
+// component's minimum weight is lowered with a 64-bit atomic on the weight bits.
+__global__ __launch_bounds__(kWG) void k_bor_vreduce(Dev d, int nsplit) {
     if (*d.done) return;
+    __shared__ double rw[kWG];
+    __shared__ int rj[kWG];
     const int n = d.n;
-    double *mw = d.scr;                 // [n]
-    int32_t *mj = d.ecomp_tmp;          // [n]
-    for (int i = threadIdx.x; i < n; i += kTreeWG) {
-        double bw = INFINITY;
-        int bj = -1;
-        for (int s = 0; s < nsplit; ++s) {
+    const int i = blockIdx.x * (kWG / 4) + (threadIdx.x >> 2);
+    const int part = threadIdx.x & 3;
+    double bw = INFINITY;
+    int bj = -1;
+    if (i < n) {
+        for (int s = part; s < nsplit; s += 4) {
             const double w2 = d.bor_w[(size_t)s * n + i];
             const int j2 = d.bor_j[(size_t)s * n + i];
             if (j2 >= 0 && (bj < 0 || w2 < bw || (w2 == bw && j2 < bj))) { bw = w2; bj = j2; }
         }
-        mw[i] = bw;
-        mj[i] = bj;
-        if (d.comp[i] == i) {
-            d.cw[i] = ~0ull;
-            d.cidx[i] = ~0ull;
-        }
     }
-    __threadfence_block();
+    rw[threadIdx.x] = bw;
+    rj[threadIdx.x] = bj;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kTreeWG)
-        if (mj[i] >= 0) atomicMin(&d.cw[d.comp[i]], (unsigned long long)__double_as_longlong(mw[i]));
-    __threadfence_block();
-    __syncthreads();
+    if (part != 0 || i >= n) return;
+    for (int k = 1; k < 4; ++k) {
+        const double w2 = rw[threadIdx.x + k];
+        const int j2 = rj[threadIdx.x + k];
+        if (j2 >= 0 && (bj < 0 || w2 < bw || (w2 == bw && j2 < bj))) { bw = w2; bj = j2; }
+    }
+    d.scr[i] = bw;
+    d.ecomp_tmp[i] = bj;
+    if (bj >= 0) {
+        const unsigned long long key = (unsigned long long)__double_as_longlong(bw);
+        unsigned long long *slot = &d.cw[d.comp[i]];
+        if (key < __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMin(slot, key);   // skip hopeless atomics
+    }
+}
+
+// Component minimum (tie-break on packed (min, max) indices), hooking with
+// mutual pairs broken toward the smaller representative, contraction, and the
+// count of components (one workgroup; component ids, hook pointers and the
+// parent pointers in LDS when they fit).
+//
+// Parent pointers are maintained as the components grow: every component's
+// edges point toward one of its bodies (its tree root).  When component c
+// hooks onto another through the edge (a in c, b outside c), the parent
+// pointers on the path from a to c's tree root are reversed and a points to
+// b; the paths of different hooking components are disjoint, so all hooks of a
+// round are applied in parallel.
+template <bool LDS>
+__global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d) {
+    extern __shared__ int lds[];
+    __shared__ int cnt;
+    if (*d.done) return;
+    const int n = d.n;
+    int *comp = LDS ? lds : d.comp;
+    int *hook = LDS ? lds + n : d.fill;
+    int *tgt = LDS ? lds + 2 * n : d.tgt;
+    int *par = LDS ? lds + 3 * n : d.parent_new;
+    if (LDS) {
+        for (int v = threadIdx.x; v < n; v += kTreeWG) {
+            comp[v] = d.comp[v];
+            par[v] = d.parent_new[v];
+        }
+        __syncthreads();
+    }
+    const double *mw = d.scr;
+    const int32_t *mj = d.ecomp_tmp;
     for (int i = threadIdx.x; i < n; i += kTreeWG) {
         const int j = mj[i];
-        if (j >= 0 && (unsigned long long)__double_as_longlong(mw[i]) == d.cw[d.comp[i]]) {
+        const int c = comp[i];
+        if (j >= 0 && (unsigned long long)__double_as_longlong(mw[i]) == d.cw[c]) {
             const unsigned long long lo = (unsigned)min(i, j), hi = (unsigned)max(i, j);
-            atomicMin(&d.cidx[d.comp[i]], (lo << 32) | hi);
+            atomicMin(&d.cidx[c], (lo << 32) | hi);
         }
     }
     __threadfence_block();
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += kTreeWG) {
-        if (d.comp[c] != c) continue;
+        if (comp[c] != c) continue;
         const unsigned long long k = d.cidx[c];
-        if (k == ~0ull) { d.tgt[c] = c; continue; }
+        if (k == ~0ull) { tgt[c] = c; continue; }
         const int lo = (int)(k >> 32), hi = (int)(k & 0xffffffffull);
-        const int other = (d.comp[lo] == c) ? hi : lo;
-        d.tgt[c] = d.comp[other];
-        d.elo[c] = lo;
-        d.ehi[c] = hi;
+        const bool lo_in = (comp[lo] == c);
+        tgt[c] = comp[lo_in ? hi : lo];
+        d.elo[c] = lo_in ? lo : hi;   // endpoint inside c
+        d.ehi[c] = lo_in ? hi : lo;   // endpoint outside c
     }
     __threadfence_block();
     __syncthreads();
-    // hook: a mutual pair keeps the smaller id as representative; every hook
-    // records its edge at the index of the hooking representative
+    // hook: every representative moves under its target except the smaller
+    // member of a mutual pair; the hooking component re-roots at its end of
+    // the edge and hangs from the other end
     for (int c = threadIdx.x; c < n; c += kTreeWG) {
-        if (d.comp[c] != c) continue;
-        const int t = d.tgt[c];
-        if (t == c) continue;
-        if (d.tgt[t] == c && c < t) continue;
+        if (comp[c] != c) continue;
+        const int t = tgt[c];
+        if (t == c || (tgt[t] == c && c < t)) { hook[c] = c; continue; }
         d.hooked[c] = 1;
-        d.ecomp_tmp[c] = t;   // new representative (mj no longer needed for roots)
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int c = threadIdx.x; c < n; c += kTreeWG)
-        if (d.comp[c] == c && d.hooked[c] && d.tgt[c] != c && !(d.tgt[d.tgt[c]] == c && c < d.tgt[c]))
-            d.comp[c] = d.ecomp_tmp[c];
-    __threadfence_block();
-    __syncthreads();
-    for (int it = 0; it < 64; ++it) {   // 2^64 exceeds any list: bounded
-        if (threadIdx.x == 0) changed = 0;
-        __syncthreads();
-        for (int v = threadIdx.x; v < n; v += kTreeWG) {
-            const int c = d.comp[v];
-            const int cc = d.comp[c];
-            if (cc != c) { d.comp[v] = cc; changed = 1; }
+        hook[c] = t;
+        int prev = d.ehi[c], x = d.elo[c];
+        for (int it = 0; it < n && x >= 0; ++it) {
+            const int nx = par[x];
+            par[x] = prev;
+            prev = x;
+            x = nx;
         }
-        __threadfence_block();
-        __syncthreads();
-        const int ch = changed;
-        __syncthreads();
-        if (!ch) break;
     }
+    __threadfence_block();
+    __syncthreads();
+    // contraction: follow the hook pointers of representatives to the root
+    for (int v = threadIdx.x; v < n; v += kTreeWG) {
+        int c = comp[v];
+        for (int it = 0; it < n && hook[c] != c; ++it) c = hook[c];
+        tgt[v] = c;   // tgt is free again
+    }
+    __threadfence_block();
+    __syncthreads();
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     int local = 0;
-    for (int v = threadIdx.x; v < n; v += kTreeWG) local += (d.comp[v] == v);
+    for (int v = threadIdx.x; v < n; v += kTreeWG) {
+        const int c = tgt[v];
+        d.comp[v] = c;
+        if (LDS) d.parent_new[v] = par[v];
+        if (c == v) {
+            ++local;
+            d.cw[v] = ~0ull;
+            d.cidx[v] = ~0ull;
+        }
+    }
     atomicAdd(&cnt, local);
     __syncthreads();
     if (threadIdx.x == 0) {
         *d.ncomp = cnt;
+        *d.rounds += 1;
         if (cnt <= 1) *d.done = 1;
     }
 }
@@ -358,115 +408,189 @@ __device__ void levels_and_children(Dev &d, const int32_t *par, int32_t *lev, in
     __syncthreads();
 }
 
-// Root the MST at *d.root with an Euler tour: arc 2c = lo->hi, 2c+1 = hi->lo
-// for every hooked c; the successor of arc u->v is the arc after v->u in v's
-// cyclic adjacency list; ranks by pointer jumping; an edge's first-traversed
-// arc points from the parent to the child.  Writes parent_new, level_new and
-// the children lists.
-__global__ __launch_bounds__(kTreeWG) void k_root_tree(Dev d) {
-    __shared__ int sh[kTreeWG];
+// Final rooting (Sec. 3.2: the body nearest the centre of mass): reverse the
+// parent pointers on the path from the chosen root to the current tree root,
+// then levels by pointer jumping (parent, grandparent, ...) and the children
+// lists (ascending index) by counting, one workgroup with LDS when it fits.
+constexpr int kFinWG = 1024;
+
+template <bool LDS>
+__global__ __launch_bounds__(kFinWG) void k_mst_finish(Dev d) {
+    extern __shared__ int lds[];
+    __shared__ int sh[kFinWG];
     __shared__ int any;
-    __shared__ int last;
     const int n = d.n;
     const int root = *d.root;
-    for (int v = threadIdx.x; v < n; v += kTreeWG) {
-        d.deg[v] = 0;
-        d.fill[v] = 0;
+    int *par = LDS ? lds : d.parent_new;          // n
+    int *lev = LDS ? lds + n : d.level_new;       // n
+    int *anc = LDS ? lds + 2 * n : d.deg;         // n
+    int *cnt = LDS ? lds + 3 * n : d.off;         // n + 1
+    if (LDS) {
+        for (int v = threadIdx.x; v < n; v += kFinWG) par[v] = d.parent_new[v];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int prev = -1, x = root;
+        for (int it = 0; it < n && x >= 0; ++it) {
+            const int nx = par[x];
+            par[x] = prev;
+            prev = x;
+            x = nx;
+        }
     }
     __threadfence_block();
     __syncthreads();
-    for (int c = threadIdx.x; c < n; c += kTreeWG)
-        if (d.hooked[c]) {
-            atomicAdd(&d.deg[d.elo[c]], 1);
-            atomicAdd(&d.deg[d.ehi[c]], 1);
-        }
-    __threadfence_block();
-    __syncthreads();
-    block_scan_excl(d.deg, d.off, n, sh);
-    for (int c = threadIdx.x; c < n; c += kTreeWG)
-        if (d.hooked[c]) {
-            const int lo = d.elo[c], hi = d.ehi[c];
-            const int s0 = d.off[lo] + atomicAdd(&d.fill[lo], 1);
-            d.adj[s0] = 2 * c;
-            d.arcpos[2 * c] = s0;
-            const int s1 = d.off[hi] + atomicAdd(&d.fill[hi], 1);
-            d.adj[s1] = 2 * c + 1;
-            d.arcpos[2 * c + 1] = s1;
-        }
-    __threadfence_block();
-    __syncthreads();
-    const int first = d.adj[d.off[root]];
-    if (threadIdx.x == 0) last = -1;
-    for (int a = threadIdx.x; a < 2 * n; a += kTreeWG) {
-        const int c = a >> 1;
-        if (!d.hooked[c]) { d.nxtA[a] = -2; continue; }
-        const int v = (a & 1) ? d.elo[c] : d.ehi[c];     // destination of arc a
-        const int p = d.arcpos[a ^ 1];
-        int q = p + 1;
-        if (q == d.off[v + 1]) q = d.off[v];
-        d.nxtA[a] = d.adj[q];
+    for (int v = threadIdx.x; v < n; v += kFinWG) {
+        lev[v] = par[v] < 0 ? 0 : 1;
+        anc[v] = par[v];
+        cnt[v] = 0;
     }
+    if (threadIdx.x == 0) cnt[n] = 0;
     __threadfence_block();
     __syncthreads();
-    for (int a = threadIdx.x; a < 2 * n; a += kTreeWG)
-        if (d.nxtA[a] == first) last = a;
-    __syncthreads();
-    if (threadIdx.x == 0 && last >= 0) d.nxtA[last] = -1;
-    __threadfence_block();
-    __syncthreads();
-    int32_t *R[2] = {d.rkA, d.rkB};
-    int32_t *N[2] = {d.nxtA, d.nxtB};
-    for (int a = threadIdx.x; a < 2 * n; a += kTreeWG) R[0][a] = (N[0][a] >= 0) ? 1 : 0;
-    __threadfence_block();
-    __syncthreads();
-    int cur = 0;
-    for (int it = 0; it < 64; ++it) {   // 2^64 exceeds any list: bounded
+    // pointer jumping in place: read a thread's bodies into registers, barrier, write
+    constexpr int kPer = 16;
+    const bool fits = (n + kFinWG - 1) / kFinWG <= kPer;
+    for (int it = 0; it < 64; ++it) {
         if (threadIdx.x == 0) any = 0;
         __syncthreads();
-        const int nx = cur ^ 1;
-        for (int a = threadIdx.x; a < 2 * n; a += kTreeWG) {
-            const int b = N[cur][a];
-            if (b >= 0) {
-                R[nx][a] = R[cur][a] + R[cur][b];
-                const int bb = N[cur][b];
-                N[nx][a] = bb;
-                if (bb >= 0) any = 1;
-            } else {
-                R[nx][a] = R[cur][a];
-                N[nx][a] = b;
+        if (fits) {
+            int nl[kPer], na[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int v = threadIdx.x + k * kFinWG;
+                nl[k] = 0; na[k] = -1;
+                if (v < n) {
+                    const int a = anc[v];
+                    nl[k] = lev[v];
+                    if (a >= 0) {
+                        nl[k] = lev[v] + lev[a];
+                        na[k] = anc[a];
+                        if (na[k] >= 0) any = 1;
+                    }
+                }
             }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int v = threadIdx.x + k * kFinWG;
+                if (v < n) { lev[v] = nl[k]; anc[v] = na[k]; }
+            }
+        } else {
+            // large N: jump one body at a time through a private copy in global scratch
+            for (int v = threadIdx.x; v < n; v += kFinWG) {
+                const int a = anc[v];
+                d.nxtA[v] = (a >= 0) ? lev[v] + lev[a] : lev[v];
+                d.nxtB[v] = (a >= 0) ? anc[a] : -1;
+                if (a >= 0 && anc[a] >= 0) any = 1;
+            }
+            __threadfence_block();
+            __syncthreads();
+            for (int v = threadIdx.x; v < n; v += kFinWG) { lev[v] = d.nxtA[v]; anc[v] = d.nxtB[v]; }
         }
         __threadfence_block();
         __syncthreads();
-        cur = nx;
         const int a2 = any;
         __syncthreads();
         if (!a2) break;
     }
-    int32_t *rank = R[cur];
-    for (int c = threadIdx.x; c < n; c += kTreeWG) {
-        if (!d.hooked[c]) continue;
-        const int lo = d.elo[c], hi = d.ehi[c];
-        if (rank[2 * c] > rank[2 * c + 1]) d.parent_new[hi] = lo;
-        else d.parent_new[lo] = hi;
-    }
-    if (threadIdx.x == 0) d.parent_new[root] = -1;
+    // children lists: counts, exclusive scan, fill, sort each short list
+    for (int v = threadIdx.x; v < n; v += kFinWG)
+        if (par[v] >= 0) atomicAdd(&cnt[par[v] + 1], 1);
     __threadfence_block();
     __syncthreads();
-    levels_and_children(d, d.parent_new, d.level_new, sh);
+    {
+        const int t = threadIdx.x;
+        const int chunk = (n + kFinWG - 1) / kFinWG;
+        const int b = 1 + min(n, t * chunk), e = 1 + min(n, t * chunk + chunk);
+        int loc = 0;
+        for (int k = b; k < e; ++k) loc += cnt[k];
+        sh[t] = loc;
+        __syncthreads();
+        for (int o = 1; o < kFinWG; o <<= 1) {
+            const int add = (t >= o) ? sh[t - o] : 0;
+            __syncthreads();
+            sh[t] += add;
+            __syncthreads();
+        }
+        int run = sh[t] - loc;
+        __syncthreads();
+        for (int k = b; k < e; ++k) { run += cnt[k]; cnt[k] = run; }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int v = threadIdx.x; v <= n; v += kFinWG) d.child_off[v] = cnt[v];
+    for (int v = threadIdx.x; v < n; v += kFinWG) anc[v] = cnt[v];   // fill cursors
+    __threadfence_block();
+    __syncthreads();
+    for (int v = threadIdx.x; v < n; v += kFinWG)
+        if (par[v] >= 0) d.child_idx[atomicAdd(&anc[par[v]], 1)] = v;
+    __threadfence_block();
+    __syncthreads();
+    for (int v = threadIdx.x; v < n; v += kFinWG) {
+        const int b = cnt[v], e = cnt[v + 1];
+        int *ci = d.child_idx;
+        if (e - b <= 8) {   // odd-even transposition sort of 8 register slots
+            int r[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r[k] = (b + k < e) ? ci[b + k] : 0x7fffffff;
+#pragma unroll
+            for (int pass = 0; pass < 8; ++pass) {
+#pragma unroll
+                for (int k = pass & 1; k + 1 < 8; k += 2) {
+                    const int lo = min(r[k], r[k + 1]), hi = max(r[k], r[k + 1]);
+                    r[k] = lo;
+                    r[k + 1] = hi;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (b + k < e) ci[b + k] = r[k];
+        } else {
+            for (int k = b + 1; k < e; ++k) {
+                const int x = ci[k];
+                int q = k - 1;
+                while (q >= b && ci[q] > x) { ci[q + 1] = ci[q]; --q; }
+                ci[q + 1] = x;
+            }
+        }
+        if (LDS) {
+            d.parent_new[v] = par[v];
+            d.level_new[v] = lev[v];
+        }
+    }
 }
 
-int launch_mst(const Dev &d, hipStream_t s, const d4 *pos, int root_in, int nsplit) {
+void launch_mst_init(const Dev &d, hipStream_t s, const d4 *pos, int root_in) {
     k_mst_init<<<1, kTreeWG, 0, s>>>(d, pos, root_in);
+}
+
+// `rounds` Boruvka rounds (each a no-op once one component is left).
+void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, int nsplit) {
     const int jchunk = (d.n + nsplit - 1) / nsplit;
-    int rounds = 0;
-    for (int m = 1; m < d.n; m <<= 1) ++rounds;   // components at least halve per round
     for (int r = 0; r < rounds; ++r) {
-        k_bor_scan<<<dim3(d.nib, nsplit), 256, 0, s>>>(d, pos, nsplit, jchunk);
-        k_bor_merge<<<1, kTreeWG, 0, s>>>(d, nsplit);
+        k_bor_scan<<<dim3(d.nib, nsplit), 256, 0, s>>>(d, pos, jchunk);
+        k_bor_vreduce<<<(d.n + kWG / 4 - 1) / (kWG / 4), kWG, 0, s>>>(d, nsplit);
+        const size_t lds = sizeof(int) * 4 * (size_t)d.n;
+        if (lds <= 150 * 1024) {
+            (void)hipFuncSetAttribute((const void *)k_bor_merge<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds);
+            k_bor_merge<true><<<1, kTreeWG, lds, s>>>(d);
+        } else {
+            k_bor_merge<false><<<1, kTreeWG, 0, s>>>(d);
+        }
     }
-    k_root_tree<<<1, kTreeWG, 0, s>>>(d);
-    return rounds;
+}
+
+void launch_mst_root(const Dev &d, hipStream_t s) {
+    const size_t lds = sizeof(int) * (4 * (size_t)d.n + 1);
+    if (lds <= 150 * 1024 && d.n <= 16 * kFinWG) {
+        (void)hipFuncSetAttribute((const void *)k_mst_finish<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        k_mst_finish<true><<<1, kFinWG, lds, s>>>(d);
+    } else {
+        k_mst_finish<false><<<1, kFinWG, 0, s>>>(d);
+    }
 }
 
 // Levels and children of the current tree (parent[]), for stage calls that
