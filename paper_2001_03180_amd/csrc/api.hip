@@ -94,6 +94,7 @@ int ensure(mstar_ctx *ctx, int n) {
         ctx->d.nib = (n + 63) / 64;
         ctx->d.nkwg = (n + kWG - 1) / kWG;
         ctx->d.nkwg4 = (n + kWG / 4 - 1) / (kWG / 4);
+        ctx->d.nfb = (n + 64 * kForceIPL - 1) / (64 * kForceIPL);
         return MSTAR_OK;
     }
     HIPCK(hipStreamSynchronize(ctx->stream));
@@ -129,6 +130,7 @@ int ensure(mstar_ctx *ctx, int n) {
     d.nib = (n + 63) / 64;
     d.nkwg = (n + kWG - 1) / kWG;
     d.nkwg4 = (n + kWG / 4 - 1) / (kWG / 4);
+    d.nfb = (n + 64 * kForceIPL - 1) / (64 * kForceIPL);
     return MSTAR_OK;
 }
 
@@ -138,7 +140,7 @@ constexpr int kResyncEvery = 32;     // accepted steps between re-deriving posit
 // Number of workgroups sharing one i-block's j-range: enough waves to fill
 // the chip, at least 16 j-bodies per wave.
 int nsplit_for(const Dev &d, int nact) {
-    const int per = nact * d.nib * kForceWaves;
+    const int per = nact * d.nfb * kForceWaves;
     int ns = (kTargetWaves + per - 1) / per;
     ns = std::max(1, std::min(ns, kNsplitMax));
     ns = std::min(ns, std::max(1, d.n / (16 * kForceWaves)));

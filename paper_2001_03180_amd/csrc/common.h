@@ -18,6 +18,7 @@ constexpr int kMaxDiv = 17;        // k_fix <= 16 divisions plus the start-state
 constexpr int kBaseSlot = kMaxDiv - 1;   // slot holding the start state of a GBS step
 constexpr int kWG = 256;           // threads per workgroup of the O(N) kernels
 constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, split j-range)
+constexpr int kForceIPL = 1;       // i-bodies per lane in the force kernel (2 and 4 measured slower)
 constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
 
 // 1/sqrt(x) for x > 0 to <= 1 ulp: the hardware estimate v_rsq_f64 (relative
@@ -92,6 +93,7 @@ struct DivScal {           // per-division increments of the scalar variables
 // Workspace pointers used by the kernels (device memory).
 struct Dev {
     int n, nib, kfmax;          // bodies, 64-wide i-blocks, division slots allocated
+    int nfb;                    // force-kernel i-blocks (64 * kForceIPL bodies each)
     // tree
     int32_t *parent, *level, *child_off, *child_idx, *root;
     int32_t *parent_new, *level_new;

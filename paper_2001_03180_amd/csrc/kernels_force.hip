@@ -26,7 +26,7 @@ struct ForceArgs {
     double *Upart;         // [slot][nib * nsplit_max] partial sum_i m_i phi_i
     const d4 *X0, *dX;     // MST edge vectors: current = X0 + dX[slot]
     const int32_t *parent, *child_off, *child_idx;
-    int n, nib, nsplit, nsplit_max, jchunk;
+    int n, nib, nib_alloc, nsplit, nsplit_max, jchunk;   // nib: force i-blocks of 64*IPL bodies
     SlotList sl;
 };
 
@@ -87,31 +87,37 @@ __device__ void close_correction(int i, const d4 *P, const d4 *X0, const d4 *dX,
     }
 }
 
-template <bool GUARD>
-__device__ __forceinline__ void j_loop(const d4 *__restrict__ P, int jb, int je, int ii, const d4 &pi,
-                                       double &ax, double &ay, double &az, double &ph) {
+// Inner loop over j in [jb, je) for the IPL i-bodies of each lane; GUARD
+// masks the self pair (only the diagonal block needs it).
+template <bool GUARD, int IPL>
+__device__ __forceinline__ void j_loop(const d4 *__restrict__ P, int jb, int je, const int (&ii)[IPL],
+                                       const d4 (&pi)[IPL], double (&ax)[IPL], double (&ay)[IPL],
+                                       double (&az)[IPL], double (&ph)[IPL]) {
 #pragma unroll 8
     for (int j = jb; j < je; ++j) {
         const d4 pj = P[j];
-        const double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        double mj = pj.w;
-        if (GUARD) {
-            const bool self = (j == ii);
-            r2 = self ? 1.0 : r2;
-            mj = self ? 0.0 : mj;
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const double dx = pj.x - pi[q].x, dy = pj.y - pi[q].y, dz = pj.z - pi[q].z;
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double mj = pj.w;
+            if (GUARD) {
+                const bool self = (j == ii[q]);
+                r2 = self ? 1.0 : r2;
+                mj = self ? 0.0 : mj;
+            }
+            const double y = rsqrt_f64(r2);
+            const double mr = mj * y;
+            const double s = mr * (y * y);
+            ph[q] = ph[q] + mr;
+            ax[q] = fma(s, dx, ax[q]);
+            ay[q] = fma(s, dy, ay[q]);
+            az[q] = fma(s, dz, az[q]);
         }
-        const double y = rsqrt_f64(r2);
-        const double mr = mj * y;
-        const double s = mr * (y * y);
-        ph = ph + mr;
-        ax = fma(s, dx, ax);
-        ay = fma(s, dy, ay);
-        az = fma(s, dz, az);
     }
 }
 
-template <int ND, int NW>
+template <int ND, int NW, int IPL>
 __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -120,44 +126,59 @@ __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
     const int split = blockIdx.y;
     const int n = a.n;
     const d4 *__restrict__ P = a.P + (size_t)slot * n;
-    const int i0 = ib * 64;
-    const int i = i0 + lane;
-    const int ii = i < n ? i : n - 1;
-    const d4 pi = P[ii];
+    const int i0 = ib * 64 * IPL;
+    int ii[IPL];
+    d4 pi[IPL];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = i0 + q * 64 + lane;
+        ii[q] = i < n ? i : n - 1;
+        pi[q] = P[ii[q]];
+    }
     const int j0 = split * a.jchunk;
     const int j1 = min(n, j0 + a.jchunk);
-    const int q = (max(j1 - j0, 0) + NW - 1) / NW;
-    int jb = min(j1, j0 + wv * q);
-    int je = min(j1, jb + q);
+    const int qw = (max(j1 - j0, 0) + NW - 1) / NW;
+    int jb = min(j1, j0 + wv * qw);
+    int je = min(j1, jb + qw);
     jb = __builtin_amdgcn_readfirstlane(jb);
     je = __builtin_amdgcn_readfirstlane(je);
     const int g0 = __builtin_amdgcn_readfirstlane(max(jb, i0));
-    const int g1 = __builtin_amdgcn_readfirstlane(min(je, i0 + 64));
-    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    const int g1 = __builtin_amdgcn_readfirstlane(min(je, i0 + 64 * IPL));
+    double ax[IPL], ay[IPL], az[IPL], ph[IPL];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) ax[q] = ay[q] = az[q] = ph[q] = 0.0;
     if (g0 < g1) {
-        j_loop<false>(P, jb, g0, ii, pi, ax, ay, az, ph);
-        j_loop<true>(P, g0, g1, ii, pi, ax, ay, az, ph);
-        j_loop<false>(P, g1, je, ii, pi, ax, ay, az, ph);
+        j_loop<false, IPL>(P, jb, g0, ii, pi, ax, ay, az, ph);
+        j_loop<true, IPL>(P, g0, g1, ii, pi, ax, ay, az, ph);
+        j_loop<false, IPL>(P, g1, je, ii, pi, ax, ay, az, ph);
     } else {
-        j_loop<false>(P, jb, je, ii, pi, ax, ay, az, ph);
+        j_loop<false, IPL>(P, jb, je, ii, pi, ax, ay, az, ph);
     }
-    __shared__ d4 red[NW][64];
-    red[wv][lane] = d4{ax, ay, az, ph};
+    __shared__ d4 red[NW][IPL][64];
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) red[wv][q][lane] = d4{ax[q], ay[q], az[q], ph[q]};
     __syncthreads();
     if (wv != 0) return;
-    d4 s = red[0][lane];
-    for (int w = 1; w < NW; ++w) {
-        const d4 t = red[w][lane];
-        s.x = s.x + t.x; s.y = s.y + t.y; s.z = s.z + t.z; s.w = s.w + t.w;
+    double u = 0.0;
+#pragma unroll
+    for (int q = 0; q < IPL; ++q) {
+        const int i = i0 + q * 64 + lane;
+        d4 s = red[0][q][lane];
+        for (int w = 1; w < NW; ++w) {
+            const d4 t = red[w][q][lane];
+            s.x = s.x + t.x; s.y = s.y + t.y; s.z = s.z + t.z; s.w = s.w + t.w;
+        }
+        if (ND > 0 && split == 0 && i < n)
+            close_correction<ND>(i, P, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off, a.child_idx, s.x,
+                                 s.y, s.z, s.w);
+        if (i < n) {
+            a.part[((size_t)slot * a.nsplit_max + split) * n + i] = s;
+            u = u + pi[q].w * s.w;
+        }
     }
-    if (ND > 0 && split == 0 && i < n)
-        close_correction<ND>(i, P, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off, a.child_idx, s.x,
-                             s.y, s.z, s.w);
-    if (i < n) a.part[((size_t)slot * a.nsplit_max + split) * n + i] = s;
-    double u = (i < n) ? pi.w * s.w : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) u = u + __shfl_xor(u, off, 64);
-    if (lane == 0) a.Upart[(size_t)slot * a.nib * a.nsplit_max + (size_t)ib * a.nsplit + split] = u;
+    if (lane == 0) a.Upart[(size_t)slot * a.nib_alloc * a.nsplit_max + (size_t)ib * a.nsplit + split] = u;
 }
 
 void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit) {
@@ -171,16 +192,17 @@ void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int n
     a.child_off = d.child_off;
     a.child_idx = d.child_idx;
     a.n = d.n;
-    a.nib = d.nib;
+    a.nib = d.nfb;
+    a.nib_alloc = d.nib;
     a.nsplit = nsplit;
     a.nsplit_max = d.nsplit_max;
     a.jchunk = (d.n + nsplit - 1) / nsplit;
     a.sl = sl;
-    dim3 grid(sl.nact * d.nib, nsplit);
-    constexpr int NW = kForceWaves;
-    if (nd <= 0) k_force<0, NW><<<grid, 64 * NW, 0, s>>>(a);
-    else if (nd == 1) k_force<1, NW><<<grid, 64 * NW, 0, s>>>(a);
-    else k_force<2, NW><<<grid, 64 * NW, 0, s>>>(a);
+    dim3 grid(sl.nact * d.nfb, nsplit);
+    constexpr int NW = kForceWaves, IPL = kForceIPL;
+    if (nd <= 0) k_force<0, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
+    else if (nd == 1) k_force<1, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
+    else k_force<2, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
 }
 
 // Reduce the force partials of one slot: acc = G sum_split part, and the
@@ -209,7 +231,7 @@ void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int ns
                          double *U_out) {
     const int nb = (d.n + kWG - 1) / kWG;
     k_reduce_start<<<nb, kWG, 0, s>>>(d.part + (size_t)slot * d.nsplit_max * d.n,
-                                      d.Upart + (size_t)slot * d.nib * d.nsplit_max, d.n, d.nib, nsplit,
+                                      d.Upart + (size_t)slot * d.nib * d.nsplit_max, d.n, d.nfb, nsplit,
                                       d.nsplit_max, G, acc_out, U_out);
 }
 

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     const int slot = sl.slot[ai];
     const int n = d.n;
     const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
-    const int cnt = d.nib * nsplit;
+    const int cnt = d.nfb * nsplit;
     double u = 0.0;
     for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
     const double U = 0.5 * G * block_sum<kWG>(u, sh);
