@@ -8,6 +8,15 @@ integrator: MST rebuild (after an accepted step), tree transforms, the start
 force evaluation, all 8 substep divisions (72 force evaluations), Neville
 extrapolation, error test and step control -- every row of the hot path.
 
+The second half of the metric, batched small systems: 4096 independent
+systems (N_p uniform in 3..64, central mass 1 + stars of 1e-5, 10% triples;
+seed 401) integrated to t_end = 1e-2 at eta = 1e-12 in one persistent launch
+(captured HIP graph) with the autotuned launch shape.  Reported as systems/s
+with inputs resident in HBM (and with host copies), next to the per-system
+loop of the same library (mstar_integrate, one system per call, a seeded
+random sample of systems timed and scaled to the whole set) and to the CPU
+oracle (one system per host thread, a seeded random sample).
+
 value = (force evaluations x N_p (N_p - 1)) / wall time of the timed steps,
 inputs resident in HBM.  The roofline entry is the force kernel's algorithmic
 FLOP rate (20 FP64 flops per directed pair) from HIP events around every
@@ -26,6 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 pair-interactions/s at N=5000; batched subsystems/s vs per-system"
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 FLOPS_PER_PAIR = 20
+BATCH_T_END = 1e-2
+BATCH_ETA = 1e-12
 
 
 def cpu_baseline(m, x, v, eta, threads):
@@ -49,12 +60,98 @@ def cpu_baseline(m, x, v, eta, threads):
                        f"{dt:.1f} s on {threads} OpenMP threads")
 
 
+def bench_batch(M, ctx, threads, do_cpu, n_single=12, n_cpu=32):
+    """Batched small systems: systems/s of one launch vs the per-system loop."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+    import ics
+    off, m, x, v = ics.batch_subsystems()
+    sizes = np.diff(off)
+    n_sys = len(sizes)
+    p = M.params(eta=BATCH_ETA)
+    res = {
+        "workload": "4096 systems, N_p uniform in 3..64 (central mass 1 + stars 1e-5, radii log-uniform "
+                    "[1e-3, 1]; 10% hierarchical triples), seed 401; eta=1e-12, k_fix=8, t_end=1e-2",
+        "n_sys": int(n_sys), "n_bodies": int(off[-1]), "t_end": BATCH_T_END, "eta": BATCH_ETA,
+    }
+    t0 = time.perf_counter()
+    best = ctx.batch_autotune(off, m, x, v, BATCH_T_END / 10, p=p)
+    res["autotune_s"] = time.perf_counter() - t0
+    res["launch_shape"] = best
+    print(f"[bench] batch autotune: {best}", file=sys.stderr, flush=True)
+    dm = torch.tensor(m, device="cuda")
+    dx = torch.tensor(x, device="cuda")
+    dv = torch.tensor(v, device="cuda")
+    ctx.integrate_batch(off, dm, dx, dv, BATCH_T_END, p=p)       # warm-up: graph capture
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg, vg, st = ctx.integrate_batch(off, dm, dx, dv, BATCH_T_END, p=p)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, kern_ms, pairs = ctx.profile_read()
+    ctx.profile_enable(False)
+    t0 = time.perf_counter()
+    ctx.integrate_batch(off, m, x, v, BATCH_T_END, p=p)          # host arrays: with H2D / D2H
+    wall_host = time.perf_counter() - t0
+    res.update({
+        "systems_per_s": n_sys / wall,
+        "wall_s": wall,
+        "systems_per_s_with_host_copies": n_sys / wall_host,
+        "kernel_ms": kern_ms,
+        "pair_interactions_per_s": pairs / (kern_ms * 1e-3),
+        "status_ok": int((st["status"] == M.OK).sum()),
+        "steps_accepted": int(st["steps_accepted"].sum()),
+        "steps_rejected": int(st["steps_rejected"].sum()),
+        "force_evals": int(st["force_evals"].sum()),
+    })
+    print(f"[bench] batch: {n_sys} systems in {wall:.3f} s", file=sys.stderr, flush=True)
+    # per-system loop of the same library on a seeded random sample
+    rng = np.random.default_rng(7)
+    pick = sorted(rng.choice(n_sys, n_single, replace=False).tolist())
+    t_single = 0.0
+    for s in pick:
+        o, e = int(off[s]), int(off[s + 1])
+        t0 = time.perf_counter()
+        ctx.integrate(m[o:e], x[o:e], v[o:e], 0.0, BATCH_T_END, p)
+        t_single += time.perf_counter() - t0
+    per_sys = n_single / t_single
+    res["per_system_loop"] = {
+        "systems_per_s": per_sys,
+        "sample": f"{n_single} random systems (seed 7, N_p {[int(sizes[s]) for s in pick]}) integrated one "
+                  f"per mstar_integrate call in {t_single:.1f} s",
+    }
+    res["speedup_vs_per_system"] = res["systems_per_s"] / per_sys
+    print(f"[bench] per-system loop: {per_sys:.2f} systems/s", file=sys.stderr, flush=True)
+    if do_cpu:
+        import oracle
+        pick = sorted(np.random.default_rng(11).choice(n_sys, n_cpu, replace=False).tolist())
+        po = oracle.params(eta=BATCH_ETA, nthreads=1)
+
+        def one(s):
+            o, e = int(off[s]), int(off[s + 1])
+            oracle.integrate(m[o:e], x[o:e], v[o:e], 0.0, BATCH_T_END, po)
+
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, pick))
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {
+            "systems_per_s": n_cpu / dt, "cores": threads, "kind": "oracle",
+            "sample": f"{n_cpu} random systems (seed 11), one per host thread, {dt:.1f} s",
+        }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched small-systems measurement")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched small-systems measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -66,10 +163,14 @@ def main():
     import ics
     import paper_2001_03180_amd as M
 
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    ctx = M.Context(0)
+    if args.batch_only:
+        print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)
+        return
     m, x, v, wl = ics.workload("plummer5000_binary")
     n = len(m)
     eta = wl["eta"]
-    ctx = M.Context(0)
     base = dict(eta=eta, k_fix=8, n_d=2)
 
     # warmup: from the initial conditions (absorbs the first-step halvings)
@@ -136,9 +237,10 @@ def main():
             "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
         },
     }
+    if not args.no_batch:
+        out["batch"] = bench_batch(M, ctx, threads, not args.no_cpu)
     ctx.close()
     if not args.no_cpu:
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
         out["cpu_baseline"] = cpu_baseline(m, x, v, eta, threads)
     print(json.dumps(out), flush=True)
 

@@ -157,9 +157,68 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
 
 /* Force-kernel timing for measurement: when enabled, every force-kernel
  * launch is bracketed by HIP events on the context stream; the totals cover
- * all launches since the last reset. */
+ * all launches since the last reset.  A batched call counts as one launch
+ * (the persistent batch kernel) with the pair interactions of all its force
+ * evaluations. */
 int mstar_profile_enable(mstar_ctx *ctx, int enable);
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
+
+/* ---- many independent small systems in one launch ----
+ * The method applied to n_sys independent systems at once (Sec. 4.2 notes the
+ * extension to several independent systems); each system is integrated
+ * exactly as by mstar_integrate (same driver, GBS step, MST rebuilds and
+ * arithmetic), all of them inside one persistent kernel launched through a
+ * captured HIP graph. */
+
+/* Per-system outcome of a batched call. */
+typedef struct {
+    int32_t status;         /* MSTAR_OK, MSTAR_W_TIME_TOL or a negative code, as mstar_integrate returns */
+    int32_t reserved;
+    int64_t steps_accepted, steps_rejected;
+    int64_t force_evals, mst_rebuilds, topo_changes, time_iters;
+    double t_reached, eps_last, h_next, h_last;
+} mstar_batch_stats;
+
+/* Launch shape of the batch kernel (one per k_fix, kept in the context).
+ * Systems with N > wave_max_n are integrated by a whole 256-thread workgroup
+ * (bodies on 64 lanes, one division pair (n, 2 k_fix + 2 - n) per wave);
+ * systems with N <= wave_max_n by a single wave whose lanes form 64/wave_lanes
+ * groups of wave_lanes lanes, each group running division pairs. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t wave_lanes;     /* 0 (no single-wave systems), 16, 32 or 64 */
+    int32_t wave_max_n;     /* 0..wave_lanes */
+    int32_t wgs_per_cu;     /* persistent workgroups per compute unit; 0 = as many as fit */
+    int32_t use_graph;      /* 1: launch through a captured HIP graph (default); 0: plain launch */
+    int32_t reserved;
+    double kernel_ms;       /* mstar_batch_autotune: time of the chosen shape; else 0 */
+} mstar_batch_config;
+
+/* Integrate system s (bodies offsets[s] .. offsets[s+1]-1) from t0[s] (0 if t0
+ * is NULL) to t_end[s], for s < n_sys.  m [N], x, v [N][3] with N =
+ * offsets[n_sys] follow params->flags (host or device) and x, v are
+ * overwritten with each system's end state (where its status is OK,
+ * W_TIME_TOL, NOCONV or MAXSTEPS).  offsets [n_sys+1] (int64, offsets[0] = 0),
+ * t0, t_end [n_sys] and stats [n_sys] are host memory.  Every system has
+ * 2 <= N_s <= 64 bodies; k_fix <= 8.
+ * Returns MSTAR_OK when the launch completed (per-system results in stats),
+ * MSTAR_E_INVAL (bad offsets, times or parameters), MSTAR_E_UNSUPPORTED
+ * (N_s > 64, k_fix > 8, beta != 0, n_d > 2) or a device error. */
+int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                          const double *m, double *x, double *v, const double *t0, const double *t_end,
+                          mstar_batch_stats *stats);
+
+/* Read or replace the launch shape used for k_fix (2..8). */
+int mstar_batch_get_config(mstar_ctx *ctx, int32_t k_fix, mstar_batch_config *cfg);
+int mstar_batch_set_config(mstar_ctx *ctx, int32_t k_fix, const mstar_batch_config *cfg);
+
+/* Autotuner: time every launch shape (wave_lanes, wave_max_n, wgs_per_cu)
+ * on this batch (same arguments as mstar_integrate_batch; x and v are not
+ * modified; pass a shortened t_end to bound the cost), keep the fastest for
+ * params->k_fix in the context and return it in *best. */
+int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                         const double *m, const double *x, const double *v, const double *t0,
+                         const double *t_end, mstar_batch_config *best);
 
 #ifdef __cplusplus
 }

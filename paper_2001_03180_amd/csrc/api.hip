@@ -14,13 +14,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mstar.h"
+#include "batch.h"
 #include "common.h"
 
 using namespace mstar;
@@ -44,6 +47,23 @@ struct mstar_ctx {
     size_t ev_used = 0;
     int64_t prof_launches = 0;
     double prof_pairs = 0.0;
+    double prof_batch_ms = 0.0;        // batched launches (timed with b_ev)
+    // batched small systems (kernels_batch.hip)
+    int num_cu = 0;
+    int64_t b_cap_sys = 0, b_cap_n = 0;
+    std::vector<void *> b_allocs;
+    int64_t *b_off = nullptr;
+    int32_t *b_order = nullptr, *b_queue = nullptr;
+    double *b_m = nullptr, *b_x = nullptr, *b_v = nullptr, *b_x0 = nullptr, *b_v0 = nullptr;
+    double *b_t0 = nullptr, *b_te = nullptr;
+    BatchStat *b_stat = nullptr;
+    BatchStat *h_bstat = nullptr;      // pinned [b_cap_sys]
+    BatchArgs *b_args = nullptr;       // device copy of the kernel arguments
+    BatchArgs *h_bargs = nullptr;      // pinned staging of the same
+    mstar_batch_config bcfg[kBatchMaxKF + 1];
+    hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
+    int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
+    hipEvent_t b_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -475,6 +495,20 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         mstar_destroy(ctx);
         return MSTAR_E_NOMEM;
     }
+    if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
+        ctx->num_cu <= 0 || hipEventCreate(&ctx->b_ev[0]) != hipSuccess ||
+        hipEventCreate(&ctx->b_ev[1]) != hipSuccess) {
+        mstar_destroy(ctx);
+        return MSTAR_E_DEVICE;
+    }
+    for (auto &c : ctx->bcfg) {
+        memset(&c, 0, sizeof c);
+        c.struct_size = sizeof(mstar_batch_config);
+        c.wave_lanes = 16;
+        c.wave_max_n = 16;
+        c.wgs_per_cu = 0;
+        c.use_graph = 1;
+    }
     *out = ctx;
     return MSTAR_OK;
 }
@@ -484,6 +518,12 @@ void mstar_destroy(mstar_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_workspace(ctx);
+    for (void *p : ctx->b_allocs) (void)hipFree(p);
+    if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
+    if (ctx->h_bargs) (void)hipHostFree(ctx->h_bargs);
+    if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
+    for (hipEvent_t e : ctx->b_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
     if (ctx->h_sys) (void)hipHostFree(ctx->h_sys);
@@ -502,6 +542,7 @@ int mstar_profile_enable(mstar_ctx *ctx, int enable) {
     ctx->ev_used = 0;
     ctx->prof_launches = 0;
     ctx->prof_pairs = 0.0;
+    ctx->prof_batch_ms = 0.0;
     return MSTAR_OK;
 }
 
@@ -509,7 +550,7 @@ int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, dou
     if (!ctx) return MSTAR_E_INVAL;
     (void)hipSetDevice(ctx->device);
     HIPCK(hipStreamSynchronize(ctx->stream));
-    double tot = 0.0;
+    double tot = ctx->prof_batch_ms;
     for (size_t k = 0; k < ctx->ev_used; ++k) {
         float ms = 0.f;
         HIPCK(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
@@ -724,6 +765,306 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
     *stats = st;
     if (rc < 0 && ctx->err.empty()) fail(ctx, rc, "%s", mstar_strerror(rc));
     return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batched small systems: validation, device buffers, launch shape, graph.
+
+static_assert(sizeof(BatchStat) == sizeof(mstar_batch_stats), "BatchStat must mirror mstar_batch_stats");
+static_assert(offsetof(BatchStat, t_reached) == offsetof(mstar_batch_stats, t_reached), "layout");
+
+namespace {
+
+int ensure_batch(mstar_ctx *ctx, int64_t n_sys, int64_t n_tot) {
+    if (n_sys <= ctx->b_cap_sys && n_tot <= ctx->b_cap_n) return MSTAR_OK;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    for (void *p : ctx->b_allocs) (void)hipFree(p);
+    ctx->b_allocs.clear();
+    if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
+    ctx->h_bstat = nullptr;
+    if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
+    ctx->b_exec = nullptr;
+    ctx->b_key_wl = -1;
+    ctx->b_cap_sys = ctx->b_cap_n = 0;
+    const int64_t S = std::max<int64_t>(n_sys, 64), N = std::max<int64_t>(n_tot, 256);
+    auto A = [&](auto **p, size_t bytes) -> int {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return fail(ctx, MSTAR_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        ctx->b_allocs.push_back(q);
+        *p = (std::remove_reference_t<decltype(*p)>)q;
+        return MSTAR_OK;
+    };
+    int rc = 0;
+    if ((rc = A(&ctx->b_off, sizeof(int64_t) * (S + 1))) || (rc = A(&ctx->b_order, sizeof(int32_t) * S)) ||
+        (rc = A(&ctx->b_queue, sizeof(int32_t) * 2)) || (rc = A(&ctx->b_m, sizeof(double) * N)) ||
+        (rc = A(&ctx->b_x, sizeof(double) * 3 * N)) || (rc = A(&ctx->b_v, sizeof(double) * 3 * N)) ||
+        (rc = A(&ctx->b_x0, sizeof(double) * 3 * N)) || (rc = A(&ctx->b_v0, sizeof(double) * 3 * N)) ||
+        (rc = A(&ctx->b_t0, sizeof(double) * S)) || (rc = A(&ctx->b_te, sizeof(double) * S)) ||
+        (rc = A(&ctx->b_stat, sizeof(BatchStat) * S)) || (rc = A(&ctx->b_args, sizeof(BatchArgs))))
+        return rc;
+    if (!ctx->h_bargs && hipHostMalloc((void **)&ctx->h_bargs, sizeof(BatchArgs), hipHostMallocDefault) != hipSuccess) {
+        ctx->h_bargs = nullptr;
+        return fail(ctx, MSTAR_E_NOMEM, "pinned allocation failed");
+    }
+    if (hipHostMalloc((void **)&ctx->h_bstat, sizeof(BatchStat) * S, hipHostMallocDefault) != hipSuccess) {
+        ctx->h_bstat = nullptr;
+        return fail(ctx, MSTAR_E_NOMEM, "pinned allocation failed");
+    }
+    ctx->b_cap_sys = S;
+    ctx->b_cap_n = N;
+    return MSTAR_OK;
+}
+
+// Parameters, offsets and times of a batched call; *n_tot = offsets[n_sys].
+int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const int64_t *off, const double *t0,
+                   const double *t_end, int64_t *n_tot) {
+    int rc = check_params(ctx, p);
+    if (rc) return rc;
+    if (p->k_fix > kBatchMaxKF)
+        return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: k_fix > %d is not implemented", kBatchMaxKF);
+    if (n_sys < 1 || !off || !t_end) return fail(ctx, MSTAR_E_INVAL, "batch: need n_sys >= 1, offsets and t_end");
+    if (off[0] != 0) return fail(ctx, MSTAR_E_INVAL, "batch: offsets[0] must be 0");
+    for (int32_t s = 0; s < n_sys; ++s) {
+        const int64_t n = off[s + 1] - off[s];
+        if (n < 2) return fail(ctx, MSTAR_E_INVAL, "batch: system %d has %lld < 2 bodies", s, (long long)n);
+        if (n > kBatchMaxN)
+            return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: system %d has %lld > %d bodies", s, (long long)n, kBatchMaxN);
+        const double a = t0 ? t0[s] : 0.0;
+        if (!std::isfinite(a) || !std::isfinite(t_end[s]) || a == t_end[s])
+            return fail(ctx, MSTAR_E_INVAL, "batch: system %d needs finite t0 != t_end", s);
+    }
+    *n_tot = off[n_sys];
+    return MSTAR_OK;
+}
+
+int check_config(mstar_ctx *ctx, const mstar_batch_config *c) {
+    if (!c || c->struct_size != sizeof(mstar_batch_config)) return fail(ctx, MSTAR_E_INVAL, "batch config: bad struct_size");
+    if (c->wave_lanes != 0 && c->wave_lanes != 16 && c->wave_lanes != 32 && c->wave_lanes != 64)
+        return fail(ctx, MSTAR_E_INVAL, "batch config: wave_lanes must be 0, 16, 32 or 64");
+    if (c->wave_max_n < 0 || c->wave_max_n > c->wave_lanes)
+        return fail(ctx, MSTAR_E_INVAL, "batch config: need 0 <= wave_max_n <= wave_lanes");
+    if (c->wgs_per_cu < 0 || c->wgs_per_cu > 64) return fail(ctx, MSTAR_E_INVAL, "batch config: wgs_per_cu out of range");
+    return MSTAR_OK;
+}
+
+// One batched launch on device arrays md, xd, vd (x, v overwritten); per-
+// system results to ctx->h_bstat; kernel time (reset + persistent kernel).
+int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &cfg, int32_t n_sys,
+              const int64_t *off, const double *md, double *xd, double *vd, const double *t0, const double *t_end,
+              double *kernel_ms) {
+    const int kf = p->k_fix;
+    const int wl = cfg.wave_lanes;
+    const int wmax = wl > 0 ? cfg.wave_max_n : 0;
+    // two queues (whole-workgroup systems, single-wave systems), each by
+    // decreasing cost estimate N^2 (ties by index)
+    std::vector<int32_t> coop, wave;
+    for (int32_t s = 0; s < n_sys; ++s) ((off[s + 1] - off[s] > wmax) ? coop : wave).push_back(s);
+    auto by_cost = [&](int32_t a, int32_t b) {
+        const int64_t na = off[a + 1] - off[a], nb = off[b + 1] - off[b];
+        return na != nb ? na > nb : a < b;
+    };
+    std::sort(coop.begin(), coop.end(), by_cost);
+    std::sort(wave.begin(), wave.end(), by_cost);
+    std::vector<int32_t> order(coop);
+    order.insert(order.end(), wave.begin(), wave.end());
+    std::vector<double> h0;
+    if (t0) h0.assign(t0, t0 + n_sys);
+    HIPCK(hipMemcpyAsync(ctx->b_off, off, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->b_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->b_te, t_end, sizeof(double) * n_sys, hipMemcpyHostToDevice, ctx->stream));
+    if (t0) HIPCK(hipMemcpyAsync(ctx->b_t0, h0.data(), sizeof(double) * n_sys, hipMemcpyHostToDevice, ctx->stream));
+
+    BatchArgs &a = *ctx->h_bargs;
+    memset(&a, 0, sizeof a);
+    a.n_coop = (int32_t)coop.size();
+    a.n_wave = (int32_t)wave.size();
+    a.order = ctx->b_order;
+    a.queue = ctx->b_queue;
+    a.off = ctx->b_off;
+    a.m = md;
+    a.x = xd;
+    a.v = vd;
+    a.t0 = t0 ? ctx->b_t0 : nullptr;
+    a.t_end = ctx->b_te;
+    a.stat = ctx->b_stat;
+    a.p.G = p->G;
+    a.p.eta = p->eta;
+    a.p.alpha = p->alpha;
+    a.p.gamma = p->gamma;
+    a.p.a_gbs = p->a_gbs;
+    a.p.f_min = p->f_min;
+    a.p.f_max = p->f_max;
+    a.p.q_first = p->q_first;
+    a.p.t_tol = p->t_tol;
+    a.p.h_init = p->h_init;
+    a.p.max_steps = p->max_steps;
+    a.p.k_fix = kf;
+    a.p.n_d = p->n_d;
+    a.p.max_halvings = p->max_halvings;
+    a.p.max_time_iter = p->max_time_iter;
+    a.p.rebuild_every = p->rebuild_every;
+
+    const int fit = batch_blocks_per_cu(kf, wl);   // also sets the kernel's LDS limit
+    if (fit < 1) return fail(ctx, MSTAR_E_DEVICE, "batch kernel (k_fix %d, wave_lanes %d) cannot be launched", kf, wl);
+    const int per = cfg.wgs_per_cu > 0 ? std::min(cfg.wgs_per_cu, fit) : fit;
+    const int64_t need = std::max<int64_t>(a.n_coop, (a.n_wave + 3) / 4);
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per * ctx->num_cu, need));
+
+    HIPCK(hipMemcpyAsync(ctx->b_args, &a, sizeof a, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipEventRecord(ctx->b_ev[0], ctx->stream));
+    if (cfg.use_graph) {
+        const bool same = ctx->b_exec && ctx->b_key_kf == kf && ctx->b_key_wl == wl && ctx->b_key_nwg == nwg;
+        if (!same) {
+            if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
+            ctx->b_exec = nullptr;
+            ctx->b_key_wl = -1;
+            hipGraph_t graph = nullptr;
+            HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            const int lrc = launch_batch(ctx->stream, ctx->b_args, ctx->b_queue, kf, wl, nwg);
+            const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+            if (lrc || ec != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(ctx, MSTAR_E_DEVICE, "batch graph capture failed: %s", hipGetErrorString(ec));
+            }
+            const hipError_t ei = hipGraphInstantiate(&ctx->b_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                ctx->b_exec = nullptr;
+                return fail(ctx, MSTAR_E_DEVICE, "batch graph instantiation failed: %s", hipGetErrorString(ei));
+            }
+            ctx->b_key_kf = kf;
+            ctx->b_key_wl = wl;
+            ctx->b_key_nwg = nwg;
+        }
+        HIPCK(hipGraphLaunch(ctx->b_exec, ctx->stream));
+    } else {
+        if (launch_batch(ctx->stream, ctx->b_args, ctx->b_queue, kf, wl, nwg))
+            return fail(ctx, MSTAR_E_DEVICE, "batch launch failed");
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipEventRecord(ctx->b_ev[1], ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->h_bstat, ctx->b_stat, sizeof(BatchStat) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, ctx->b_ev[0], ctx->b_ev[1]));
+    if (kernel_ms) *kernel_ms = ms;
+    return MSTAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                          const double *m, double *x, double *v, const double *t0, const double *t_end,
+                          mstar_batch_stats *stats) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    int64_t n_tot = 0;
+    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot);
+    if (rc) return rc;
+    if (!m || !x || !v || !stats) return fail(ctx, MSTAR_E_INVAL, "batch: null array");
+    (void)hipSetDevice(ctx->device);
+    if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
+    const uint32_t flags = params->flags;
+    const double *md = m;
+    double *xd = x, *vd = v;
+    if (!is_dev(flags)) {
+        HIPCK(hipMemcpyAsync(ctx->b_m, m, sizeof(double) * n_tot, hipMemcpyHostToDevice, ctx->stream));
+        HIPCK(hipMemcpyAsync(ctx->b_x, x, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
+        HIPCK(hipMemcpyAsync(ctx->b_v, v, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
+        md = ctx->b_m;
+        xd = ctx->b_x;
+        vd = ctx->b_v;
+    }
+    double ms = 0.0;
+    if ((rc = batch_run(ctx, params, ctx->bcfg[params->k_fix], n_sys, offsets, md, xd, vd, t0, t_end, &ms))) return rc;
+    if (!is_dev(flags)) {
+        HIPCK(hipMemcpyAsync(x, ctx->b_x, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipMemcpyAsync(v, ctx->b_v, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipStreamSynchronize(ctx->stream));
+    }
+    memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
+    if (ctx->prof) {
+        double pairs = 0.0;
+        for (int32_t s = 0; s < n_sys; ++s) {
+            const double n = (double)(offsets[s + 1] - offsets[s]);
+            pairs += (double)stats[s].force_evals * n * (n - 1.0);
+        }
+        ctx->prof_launches += 1;
+        ctx->prof_pairs += pairs;
+        ctx->prof_batch_ms += ms;
+    }
+    return MSTAR_OK;
+}
+
+int mstar_batch_get_config(mstar_ctx *ctx, int32_t k_fix, mstar_batch_config *cfg) {
+    if (!ctx) return MSTAR_E_INVAL;
+    if (!cfg || k_fix < 2 || k_fix > kBatchMaxKF) return fail(ctx, MSTAR_E_INVAL, "batch config: bad arguments");
+    *cfg = ctx->bcfg[k_fix];
+    return MSTAR_OK;
+}
+
+int mstar_batch_set_config(mstar_ctx *ctx, int32_t k_fix, const mstar_batch_config *cfg) {
+    if (!ctx) return MSTAR_E_INVAL;
+    if (k_fix < 2 || k_fix > kBatchMaxKF) return fail(ctx, MSTAR_E_INVAL, "batch config: k_fix out of range");
+    int rc = check_config(ctx, cfg);
+    if (rc) return rc;
+    ctx->bcfg[k_fix] = *cfg;
+    return MSTAR_OK;
+}
+
+int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                         const double *m, const double *x, const double *v, const double *t0,
+                         const double *t_end, mstar_batch_config *best) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    int64_t n_tot = 0;
+    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot);
+    if (rc) return rc;
+    if (!m || !x || !v || !best) return fail(ctx, MSTAR_E_INVAL, "autotune: null argument");
+    (void)hipSetDevice(ctx->device);
+    if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
+    const hipMemcpyKind k = is_dev(params->flags) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCK(hipMemcpyAsync(ctx->b_m, m, sizeof(double) * n_tot, k, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->b_x0, x, sizeof(double) * 3 * n_tot, k, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->b_v0, v, sizeof(double) * 3 * n_tot, k, ctx->stream));
+    const int kf = params->k_fix;
+    // candidate shapes: tile width for single-wave systems, the N cut between
+    // the two tile kinds, and persistent workgroups per CU
+    const int shapes[][2] = {{0, 0}, {16, 16}, {32, 16}, {32, 32}, {64, 32}, {64, 64}};
+    mstar_batch_config top{};
+    double top_ms = 0.0;
+    bool have = false;
+    for (const auto &sh : shapes) {
+        const int fit = batch_blocks_per_cu(kf, sh[0]);
+        for (int per = 1; per <= fit; ++per) {
+            mstar_batch_config c{};
+            c.struct_size = sizeof c;
+            c.wave_lanes = sh[0];
+            c.wave_max_n = sh[1];
+            c.wgs_per_cu = per;
+            c.use_graph = 0;
+            HIPCK(hipMemcpyAsync(ctx->b_x, ctx->b_x0, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCK(hipMemcpyAsync(ctx->b_v, ctx->b_v0, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToDevice, ctx->stream));
+            double ms = 0.0;
+            if ((rc = batch_run(ctx, params, c, n_sys, offsets, ctx->b_m, ctx->b_x, ctx->b_v, t0, t_end, &ms)))
+                return rc;
+            if (!have || ms < top_ms) {
+                top = c;
+                top_ms = ms;
+                have = true;
+            }
+        }
+    }
+    if (!have) return fail(ctx, MSTAR_E_DEVICE, "autotune: no launchable shape");
+    top.use_graph = 1;
+    top.kernel_ms = top_ms;
+    ctx->bcfg[kf] = top;
+    *best = top;
+    return MSTAR_OK;
 }
 
 }  // extern "C"

@@ -45,6 +45,23 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
 
 
+class BatchConfig(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("wave_lanes", C.c_int32), ("wave_max_n", C.c_int32),
+        ("wgs_per_cu", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32), ("kernel_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
+
+
+# numpy mirror of mstar_batch_stats (one record per system)
+BATCH_STATS_DTYPE = np.dtype([
+    ("status", np.int32), ("reserved", np.int32), ("steps_accepted", np.int64), ("steps_rejected", np.int64),
+    ("force_evals", np.int64), ("mst_rebuilds", np.int64), ("topo_changes", np.int64), ("time_iters", np.int64),
+    ("t_reached", np.float64), ("eps_last", np.float64), ("h_next", np.float64), ("h_last", np.float64),
+])
+
 EXPORTS = {
     "mstar_abi_version": (C.c_int, []),
     "mstar_params_default": (None, [C.POINTER(Params)]),
@@ -65,6 +82,12 @@ EXPORTS = {
     "mstar_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "mstar_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
+    "mstar_integrate_batch": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_batch_get_config": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BatchConfig)]),
+    "mstar_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BatchConfig)]),
+    "mstar_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchConfig)]),
 }
 
 _lib = None
@@ -250,6 +273,61 @@ class Context:
                                    C.byref(st))
         self._check(rc, allow)
         return x, v, rc, st.as_dict()
+
+    # ---------------------------------------------------------------- batch
+    def _batch_args(self, offsets, m, x, v, t_end, t0, copy):
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        n_sys = len(off) - 1
+        ntot = int(off[-1]) if n_sys >= 0 else 0
+        te = np.ascontiguousarray(np.broadcast_to(np.asarray(t_end, dtype=np.float64), (n_sys,)))
+        t0a = None if t0 is None else np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.float64),
+                                                                            (n_sys,)))
+        if copy:
+            x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
+            v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
+        a = [_Arg(m, np.float64, (ntot,)), _Arg(x, np.float64, (ntot, 3), copy),
+             _Arg(v, np.float64, (ntot, 3), copy)]
+        return off, n_sys, te, t0a, x, v, a
+
+    def integrate_batch(self, offsets, m, x, v, t_end, t0=None, p: Params | None = None):
+        """Integrate n_sys independent systems (bodies offsets[s]..offsets[s+1]-1)
+        to t_end[s] in one launch: returns (x, v, stats) with stats a numpy
+        record array of BATCH_STATS_DTYPE (per-system status and counters)."""
+        p = p or params()
+        off, n_sys, te, t0a, x, v, a = self._batch_args(offsets, m, x, v, t_end, t0, True)
+        p.flags = _mode(*a)
+        st = np.zeros(max(n_sys, 0), dtype=BATCH_STATS_DTYPE)
+        self._check(lib().mstar_integrate_batch(
+            self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
+            None if t0a is None else C.c_void_p(t0a.ctypes.data), C.c_void_p(te.ctypes.data),
+            C.c_void_p(st.ctypes.data)))
+        return x, v, st
+
+    def batch_config(self, k_fix=8):
+        c = BatchConfig()
+        self._check(lib().mstar_batch_get_config(self._h, int(k_fix), C.byref(c)))
+        return c.as_dict()
+
+    def set_batch_config(self, k_fix=8, **kw):
+        c = BatchConfig()
+        self._check(lib().mstar_batch_get_config(self._h, int(k_fix), C.byref(c)))
+        for k, val in kw.items():
+            if not hasattr(c, k):
+                raise KeyError(k)
+            setattr(c, k, val)
+        self._check(lib().mstar_batch_set_config(self._h, int(k_fix), C.byref(c)))
+        return c.as_dict()
+
+    def batch_autotune(self, offsets, m, x, v, t_end, t0=None, p: Params | None = None):
+        """Time every launch shape on this batch (x, v untouched), keep and return the fastest."""
+        p = p or params()
+        off, n_sys, te, t0a, x, v, a = self._batch_args(offsets, m, x, v, t_end, t0, False)
+        p.flags = _mode(*a)
+        c = BatchConfig()
+        self._check(lib().mstar_batch_autotune(
+            self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
+            None if t0a is None else C.c_void_p(t0a.ctypes.data), C.c_void_p(te.ctypes.data), C.byref(c)))
+        return c.as_dict()
 
     def profile_enable(self, on=True):
         self._check(lib().mstar_profile_enable(self._h, 1 if on else 0))

@@ -55,6 +55,24 @@ def test_struct_layout_matches_header(tmp_path):
     assert [int(g) for g in got] == want
 
 
+def test_batch_struct_layout_matches_header(tmp_path):
+    import numpy as np
+    import paper_2001_03180_amd as M
+    src = tmp_path / "b.c"
+    src.write_text('#include "mstar.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(mstar_batch_stats),'
+                   ' offsetof(mstar_batch_stats, steps_accepted), offsetof(mstar_batch_stats, t_reached),'
+                   ' sizeof(mstar_batch_config), offsetof(mstar_batch_config, kernel_ms));return 0;}\n')
+    exe = tmp_path / "b"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    d = M.BATCH_STATS_DTYPE
+    want = [d.itemsize, d.fields["steps_accepted"][1], d.fields["t_reached"][1], ctypes.sizeof(M.BatchConfig),
+            M.BatchConfig.kernel_ms.offset]
+    assert [int(g) for g in got] == want
+    assert np.dtype(d).isalignedstruct or d.itemsize == 88
+
+
 def test_no_gpu_reports_device_error():
     """Without a GPU, creating a context fails cleanly (no abort across the ABI)."""
     import torch
