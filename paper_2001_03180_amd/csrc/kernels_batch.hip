@@ -32,21 +32,52 @@ constexpr int kBatchWG = 256;
 template <int L>
 __device__ __forceinline__ int glane() { return (int)(threadIdx.x & (L - 1)); }
 
+// Sums over a lane group without LDS traffic: DPP moves inside 16-lane rows
+// (quad swaps, then the mirrored half-row and row) and the gfx950 row-swap
+// instructions across rows.  Every step pairs lanes that hold equal partial
+// sums, so all lanes end with the same bits; lanes past the group's bodies
+// hold zeros, so the result does not depend on the group width.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double row_swap_sum(double v, bool wide) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    uint32_t a0, a1, b0, b1;
+    if (wide) {   // rows (0,1) <-> rows (2,3)
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a0 = l[0]; b0 = l[1]; a1 = h[0]; b1 = h[1];
+    } else {      // row 0 <-> row 1, row 2 <-> row 3
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a0 = l[0]; b0 = l[1]; a1 = h[0]; b1 = h[1];
+    }
+    const double a = __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0));
+    const double b = __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+    return a + b;
+}
 template <int L>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-    for (int o = 1; o < L; o <<= 1) v = v + __shfl_xor(v, o, L);
+    static_assert(L == 16 || L == 32 || L == 64, "lane groups of 16, 32 or 64");
+    v = v + dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
+    v = v + dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
+    v = v + dpp_f64<0x141>(v);    // row_half_mirror
+    v = v + dpp_f64<0x140>(v);    // row_mirror
+    if (L >= 32) v = row_swap_sum(v, false);
+    if (L >= 64) v = row_swap_sum(v, true);
     return v;
 }
 template <int L>
 __device__ __forceinline__ void gsum3(double &a, double &b, double &c) {
-#pragma unroll
-    for (int o = 1; o < L; o <<= 1) {
-        const double ta = __shfl_xor(a, o, L), tb = __shfl_xor(b, o, L), tc = __shfl_xor(c, o, L);
-        a = a + ta;
-        b = b + tb;
-        c = c + tc;
-    }
+    static_assert(L == 16 || L == 32 || L == 64, "lane groups of 16, 32 or 64");
+    a = a + dpp_f64<0xB1>(a); b = b + dpp_f64<0xB1>(b); c = c + dpp_f64<0xB1>(c);
+    a = a + dpp_f64<0x4E>(a); b = b + dpp_f64<0x4E>(b); c = c + dpp_f64<0x4E>(c);
+    a = a + dpp_f64<0x141>(a); b = b + dpp_f64<0x141>(b); c = c + dpp_f64<0x141>(c);
+    a = a + dpp_f64<0x140>(a); b = b + dpp_f64<0x140>(b); c = c + dpp_f64<0x140>(c);
+    if (L >= 32) { a = row_swap_sum(a, false); b = row_swap_sum(b, false); c = row_swap_sum(c, false); }
+    if (L >= 64) { a = row_swap_sum(a, true); b = row_swap_sum(b, true); c = row_swap_sum(c, true); }
 }
 template <int L>
 __device__ __forceinline__ int gor(int p) {
@@ -141,7 +172,7 @@ struct SysLDS {
     double tau[KF], drcm[KF][3];
     double t, B, H, U0, T0, M, rcm[3], vcm[3], t0, t_end, eps, h_next, h_last, epsw[4];
     int par[L], lev[L], opar[L], olev[L], coff[L + 1], cidx[L];
-    int n, R, fresh, since_rebuild, halvings, approach, done, status, accepted;
+    int n, R, root, fresh, since_rebuild, halvings, approach, done, status, accepted;
     int64_t acc, rej, nforce, nrebuild, ntopo, time_iters;
 };
 
@@ -226,6 +257,7 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
         int R = 0;
         while ((1 << R) < maxlev) ++R;
         S.R = R;
+        S.root = root;
     }
 }
 
@@ -343,11 +375,10 @@ __device__ __forceinline__ void group_force(const SysLDS<KF, L, G> &S, int g, in
     }
 }
 
-// Kinetic energy in the centre-of-mass frame of the velocities given by MST
-// edges V (Sec. 2.2: velocities are transformed back to the original frame).
+// Kinetic energy in the centre-of-mass frame of root-relative velocities u
+// (Sec. 2.2: velocities are transformed back to the original frame).
 template <int L>
-__device__ __forceinline__ double group_T(const Jumps<L> &J, const d4 &V, double mi, double M) {
-    const d4 u = J.sum(V);
+__device__ __forceinline__ double group_T(const d4 &u, double mi, double M) {
     double bx = mi * u.x, by = mi * u.y, bz = mi * u.z;
     gsum3<L>(bx, by, bz);
     bx = bx / M;
@@ -378,7 +409,7 @@ __device__ __forceinline__ void group_start(SysLDS<KF, L, G> &S, const BatchPara
     group_force(S, 0, n, P.n_d, d4{rho.x, rho.y, rho.z, mi}, ax, ay, az, ph);
     const double U = 0.5 * P.G * gsum<L>(live ? mi * ph : 0.0);
     if (live) S.a0[i] = d4{P.G * ax, P.G * ay, P.G * az, 0.0};
-    const double T = group_T(J, V0, mi, S.M);
+    const double T = group_T<L>(J.sum(V0), mi, S.M);
     wsync();
     if (i == 0) {
         S.U0 = U;
@@ -445,16 +476,29 @@ __device__ __forceinline__ int group_kicks(int g) {
 // (Sec. 2.3), as increments; end increments go to E[k], tau[k], drcm[k].
 // The divisions of a group run as one flat loop of kicks so that all groups
 // of a wave stay converged.
+//
+// Positions and velocities relative to the root are carried along with the
+// edge increments instead of being re-summed from the edges at every
+// substep: a drift adds dt V_e to every edge on a body's path, so the body
+// moves by dt u (u = root-relative velocity), and a kick adds
+// dt (a_v - a_parent) along the path, so u changes by dt (a - a_root).  They
+// start each step from tree sums of the start state's edges.
 template <int KF, int L, int G, bool COOP>
 __device__ __forceinline__ void group_divisions(SysLDS<KF, L, G> &S, const BatchParams &P, int g, int n) {
     constexpr int NP = (KF + 1) / 2;
     const int i = glane<L>();
     const bool live = i < n;
     const int par = live ? S.par[i] : -1;
+    const int root = S.root;
     const double mi = live ? S.m[i] : 0.0;
-    Jumps<L> J;
-    J.init(par, S.R);
     const d4 X0 = live ? S.X0[i] : d4{0.0, 0.0, 0.0, 0.0}, V0 = live ? S.V0[i] : d4{0.0, 0.0, 0.0, 0.0};
+    d4 r0, u0;
+    {
+        Jumps<L> J;
+        J.init(par, S.R);
+        r0 = J.sum(X0);
+        u0 = J.sum(V0);
+    }
     const double H = S.H, B = S.B, T0 = S.T0, M = S.M;
     const double vc0 = S.vcm[0], vc1 = S.vcm[1], vc2 = S.vcm[2];
     const double gd0 = P.alpha * (T0 + B) + P.gamma;
@@ -466,13 +510,15 @@ __device__ __forceinline__ void group_divisions(SysLDS<KF, L, G> &S, const Batch
     int p = g, second = 0, k = g;
     int nsub = 2 * (k + 1), s = 0;
     double h = H / (double)nsub;
-    d4 dX{0.0, 0.0, 0.0, 0.0}, dV{0.0, 0.0, 0.0, 0.0};
+    d4 dX{0.0, 0.0, 0.0, 0.0}, dV{0.0, 0.0, 0.0, 0.0}, dr{0.0, 0.0, 0.0, 0.0}, du{0.0, 0.0, 0.0, 0.0};
     double tau = 0.0, dr0 = 0.0, dr1 = 0.0, dr2 = 0.0;
     // first half drift of a division: V = V0, so T = T0
     auto start = [&]() {
         const double dt = (0.5 * h) / gd0;
         dV = d4{0.0, 0.0, 0.0, 0.0};
+        du = d4{0.0, 0.0, 0.0, 0.0};
         dX = par >= 0 ? d4{dt * V0.x, dt * V0.y, dt * V0.z, 0.0} : d4{0.0, 0.0, 0.0, 0.0};
+        dr = d4{dt * u0.x, dt * u0.y, dt * u0.z, 0.0};
         tau = dt;
         dr0 = dt * vc0;
         dr1 = dt * vc1;
@@ -481,9 +527,8 @@ __device__ __forceinline__ void group_divisions(SysLDS<KF, L, G> &S, const Batch
     if (p < NP) start();
     for (int q = 0; q < kloop; ++q) {
         if (q < kg) {
-            // kick K(h): positions from the edges, forces, U, edge-velocity update
-            const d4 X{X0.x + dX.x, X0.y + dX.y, X0.z + dX.z, 0.0};
-            const d4 rho = J.sum(X);
+            // kick K(h): forces at the current positions, U, velocity updates
+            const d4 rho{r0.x + dr.x, r0.y + dr.y, r0.z + dr.z, 0.0};
             if (live) {
                 S.pos[g][i] = d4{rho.x, rho.y, rho.z, mi};
                 S.dXw[g][i] = dX;
@@ -498,15 +543,22 @@ __device__ __forceinline__ void group_divisions(SysLDS<KF, L, G> &S, const Batch
             const double dtk = h / (P.alpha * U + P.gamma);
             const int src = par < 0 ? i : par;
             const double bx = __shfl(ax, src, L), by = __shfl(ay, src, L), bz = __shfl(az, src, L);
-            if (par >= 0) dV = d4{dV.x + dtk * (ax - bx), dV.y + dtk * (ay - by), dV.z + dtk * (az - bz), 0.0};
+            const double cx = __shfl(ax, root, L), cy = __shfl(ay, root, L), cz = __shfl(az, root, L);
+            if (par >= 0) {
+                dV = d4{dV.x + dtk * (ax - bx), dV.y + dtk * (ay - by), dV.z + dtk * (az - bz), 0.0};
+                du = d4{du.x + dtk * (ax - cx), du.y + dtk * (ay - cy), du.z + dtk * (az - cz), 0.0};
+            }
             wsync();
             ++s;
             const bool last = (s == nsub);
             // drift D(h) (D(h/2) at the end of the division)
-            const d4 V{V0.x + dV.x, V0.y + dV.y, V0.z + dV.z, 0.0};
-            const double T = group_T(J, V, mi, M);
+            const d4 u{u0.x + du.x, u0.y + du.y, u0.z + du.z, 0.0};
+            const double T = group_T<L>(live ? u : d4{0.0, 0.0, 0.0, 0.0}, mi, M);
             const double dtd = (last ? 0.5 * h : h) / (P.alpha * (T + B) + P.gamma);
-            if (par >= 0) dX = d4{dX.x + dtd * V.x, dX.y + dtd * V.y, dX.z + dtd * V.z, 0.0};
+            if (par >= 0) {
+                dX = d4{dX.x + dtd * (V0.x + dV.x), dX.y + dtd * (V0.y + dV.y), dX.z + dtd * (V0.z + dV.z), 0.0};
+                dr = d4{dr.x + dtd * u.x, dr.y + dtd * u.y, dr.z + dtd * u.z, 0.0};
+            }
             tau = tau + dtd;
             dr0 = dr0 + dtd * vc0;
             dr1 = dr1 + dtd * vc1;
@@ -567,29 +619,36 @@ __device__ __forceinline__ double gerr(double nx, double ny, double nz, double d
     return isnan(e) ? INFINITY : e;
 }
 
-// Neville-Aitken extrapolation in h^2 of item `it` (X or V of one body, or
-// the scalars t, r_cm); result to row 0 of E; returns its error measure.
+// Neville-Aitken extrapolation in h^2 of row b of E component c (or of the
+// scalars t, r_cm when c < 0): returns T_{k,k} and sets *prev = T_{k-1,k-1}.
+template <int KF>
+__device__ __forceinline__ double extrap_one(const double *src, int stride, double *prev) {
+    double p[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) p[k] = src[k * stride];
+    neville<KF>(p);
+    *prev = p[KF - 2];
+    return p[KF - 1];
+}
+
+// Extrapolation of item `it` (X or V of one body, or the scalars t, r_cm);
+// result to row 0 of E (or tau[0], drcm[0]); returns its error measure.
 template <int KF, int L, int G>
 __device__ __forceinline__ double extrap_item(SysLDS<KF, L, G> &S, int it, int n, double gd, double gk, double hn) {
     if (it < 2 * L) {
         const int b = it % L, c0 = it < L ? 0 : 3;
         if (b >= n) return 0.0;
-        double px[KF], py[KF], pz[KF];
-#pragma unroll
-        for (int k = 0; k < KF; ++k) {
-            px[k] = S.E[k][c0][b];
-            py[k] = S.E[k][c0 + 1][b];
-            pz[k] = S.E[k][c0 + 2][b];
-        }
-        neville<KF>(px);
-        neville<KF>(py);
-        neville<KF>(pz);
-        S.E[0][c0][b] = px[KF - 1];
-        S.E[0][c0 + 1][b] = py[KF - 1];
-        S.E[0][c0 + 2][b] = pz[KF - 1];
+        constexpr int stride = 6 * L;   // E[k][c][b] -> E[k+1][c][b]
+        double qx, qy, qz;
+        const double ex = extrap_one<KF>(&S.E[0][c0][b], stride, &qx);
+        const double ey = extrap_one<KF>(&S.E[0][c0 + 1][b], stride, &qy);
+        const double ez = extrap_one<KF>(&S.E[0][c0 + 2][b], stride, &qz);
+        S.E[0][c0][b] = ex;
+        S.E[0][c0 + 1][b] = ey;
+        S.E[0][c0 + 2][b] = ez;
         const int q = S.par[b];
         if (q < 0) return 0.0;
-        const double nx = px[KF - 1] - px[KF - 2], ny = py[KF - 1] - py[KF - 2], nz = pz[KF - 1] - pz[KF - 2];
+        const double nx = ex - qx, ny = ey - qy, nz = ez - qz;
         if (c0 == 0) {
             const d4 X0 = S.X0[b], V0 = S.V0[b];
             return gerr(nx, ny, nz, X0.x + hn * (V0.x / gd), X0.y + hn * (V0.y / gd), X0.z + hn * (V0.z / gd));
@@ -599,26 +658,18 @@ __device__ __forceinline__ double extrap_item(SysLDS<KF, L, G> &S, int it, int n
                     V0.z + hn * ((av.z - ap.z) / gk));
     }
     if (it == 2 * L) {
-        double pt[KF], r0[KF], r1[KF], r2[KF];
-#pragma unroll
-        for (int k = 0; k < KF; ++k) {
-            pt[k] = S.tau[k];
-            r0[k] = S.drcm[k][0];
-            r1[k] = S.drcm[k][1];
-            r2[k] = S.drcm[k][2];
-        }
-        neville<KF>(pt);
-        neville<KF>(r0);
-        neville<KF>(r1);
-        neville<KF>(r2);
-        const double et = gerr(pt[KF - 1] - pt[KF - 2], 0.0, 0.0, S.t + hn * (1.0 / gd), 0.0, 0.0);
-        const double er = gerr(r0[KF - 1] - r0[KF - 2], r1[KF - 1] - r1[KF - 2], r2[KF - 1] - r2[KF - 2],
-                               S.rcm[0] + hn * (S.vcm[0] / gd), S.rcm[1] + hn * (S.vcm[1] / gd),
-                               S.rcm[2] + hn * (S.vcm[2] / gd));
-        S.tau[0] = pt[KF - 1];
-        S.drcm[0][0] = r0[KF - 1];
-        S.drcm[0][1] = r1[KF - 1];
-        S.drcm[0][2] = r2[KF - 1];
+        double qt, q0, q1, q2;
+        const double et_ = extrap_one<KF>(&S.tau[0], 1, &qt);
+        const double e0 = extrap_one<KF>(&S.drcm[0][0], 3, &q0);
+        const double e1 = extrap_one<KF>(&S.drcm[0][1], 3, &q1);
+        const double e2 = extrap_one<KF>(&S.drcm[0][2], 3, &q2);
+        const double et = gerr(et_ - qt, 0.0, 0.0, S.t + hn * (1.0 / gd), 0.0, 0.0);
+        const double er = gerr(e0 - q0, e1 - q1, e2 - q2, S.rcm[0] + hn * (S.vcm[0] / gd),
+                               S.rcm[1] + hn * (S.vcm[1] / gd), S.rcm[2] + hn * (S.vcm[2] / gd));
+        S.tau[0] = et_;
+        S.drcm[0][0] = e0;
+        S.drcm[0][1] = e1;
+        S.drcm[0][2] = e2;
         return et > er ? et : er;
     }
     return 0.0;
@@ -895,9 +946,12 @@ __global__ void k_batch_reset(int32_t *queue) {
 }
 
 // Persistent kernel: first the cooperative queue (one system per workgroup),
-// then the wave queue (one system per wave).
+// then the wave queue (one system per wave).  Register use is capped for
+// three resident waves per SIMD (three 256-thread workgroups per CU, which
+// is also what the LDS of one cooperative system allows); measured faster
+// than the uncapped two, the few spills sit outside the substep loop.
 template <int KF, int WL>
-__global__ __launch_bounds__(kBatchWG) void k_batch(const BatchArgs *__restrict__ args) {
+__global__ __launch_bounds__(kBatchWG, 3) void k_batch(const BatchArgs *__restrict__ args) {
     const BatchArgs &A = *args;
     extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
     __shared__ int next;
