@@ -220,6 +220,48 @@ int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_s
                          const double *m, const double *x, const double *v, const double *t0,
                          const double *t_end, mstar_batch_config *best);
 
+/* ---- frozen-controller replay and adjoint (gradients of the end state with
+ * respect to the initial conditions; not in the paper) ----
+ * With the accepted fictitious steps H_k recorded, the integrator is a smooth
+ * map from (x0, v0) to the end state (discretise, then differentiate: the
+ * step-size controller is frozen).  In exact arithmetic that map does not
+ * depend on the coordinates it is evaluated in (the MST transforms and
+ * rebuilds of Sec. 2.2 and 3.5 are linear changes of variables), so the
+ * replay and its adjoint evaluate it in Cartesian coordinates: the LogH
+ * leapfrog of Sec. 2.1-2.3 with B = U(x0) - T(v0), and each GBS step the
+ * k_fix divisions combined with the weights of the extrapolation to h = 0 in
+ * h^2 (Sec. 2.3, 4.2).  N <= 1024 (MSTAR_E_UNSUPPORTED above), k_fix <= 16. */
+
+/* mstar_integrate that records the fictitious step H[k] of every accepted
+ * step (H has room for max_accepted values, host memory) and stops after
+ * max_accepted accepted steps if t_end is not reached first (MSTAR_OK in
+ * both cases); *n_accepted = steps recorded. */
+int mstar_integrate_record(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
+                           double *v, double t0, double t_end, int64_t max_accepted, double *H,
+                           int64_t *n_accepted, mstar_stats *stats);
+
+/* Replay n_steps GBS steps of lengths H[k] (host array) from (x, v) at t0
+ * without error test or step control; x, v are overwritten with the end
+ * state and *t_out (nullable) receives its time. */
+int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                 double t0, int64_t n_steps, const double *H, double *t_out);
+
+/* Adjoint of mstar_replay: given the cotangent (gx, gv [n][3], gt) of the end
+ * state (x, v, t), returns gx0, gv0 = the gradient of <gx, x> + <gv, v> + gt t
+ * with respect to the initial x0, v0.  Checkpoints the state every
+ * checkpoint_every steps and recomputes each segment (and each step's
+ * substep states) during the reverse pass. */
+int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
+                         const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
+                         const double *gx, const double *gv, double gt, double *gx0, double *gv0);
+
+/* Transposed Jacobian of the accelerations applied to w [n][3] (the force
+ * Hessian-vector product of the reverse kick): out_i = G sum_{j != i}
+ * M(d_ij) (m_i w_j - m_j w_i), M(d) = (I - 3 d d^T / |d|^2) / |d|^3,
+ * d_ij = x_j - x_i (Cartesian). */
+int mstar_force_hvp(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x,
+                    const double *w, double *out);
+
 #ifdef __cplusplus
 }
 #endif

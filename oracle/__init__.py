@@ -85,6 +85,12 @@ def lib():
             "orc_integrate": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats)]),
             "orc_diagnostics": (None, [C.c_int, D, D, D, C.c_double, D]),
             "orc_sdiv": (C.c_double, [C.c_int, C.c_int, I]),
+            "orc_integrate_rec": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats),
+                                            C.c_int64, D, I, I64]),
+            "orc_replay": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, I, P, D]),
+            "orc_force_tlm": (C.c_int, [C.c_int, D, D, C.c_double, C.c_int, D, D, D, D, D, C.c_int]),
+            "orc_lagrange_weights": (None, [C.c_int, D]),
+            "orc_replay_tlm": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, P, C.c_int, D, D, D, D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -259,3 +265,76 @@ def sdiv(k_fix, n_div):
     g = np.empty(k_fix, dtype=np.int32)
     s = lib().orc_sdiv(int(k_fix), int(n_div), g.ctypes.data_as(C.POINTER(C.c_int32)))
     return s, g
+
+
+# ---------------------------------------------------------------- replay / TLM
+def integrate_rec(m, x, v, t0, t_end, max_accepted, p: Params | None = None):
+    """integrate() that also records its accepted steps (fictitious step H_k and
+    the MST parent array used) and stops after max_accepted of them.
+    Returns (x, v, rc, stats, H[k], parents[k, n])."""
+    p = p or params()
+    m, pm = _d(m)
+    n = len(m)
+    x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
+    H = np.zeros(int(max_accepted))
+    par = np.zeros((int(max_accepted), n), dtype=np.int32)
+    k = C.c_int64()
+    st = Stats()
+    rc = lib().orc_integrate_rec(n, pm, _d(x)[1], _d(v)[1], float(t0), float(t_end), C.byref(p), C.byref(st),
+                                 int(max_accepted), _d(H)[1], par.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 C.byref(k))
+    _check(rc if rc < 0 else 0, "integrate_rec")
+    return x, v, rc, st.as_dict(), H[:k.value].copy(), par[:k.value].copy()
+
+
+def replay(m, x, v, t0, H, parents, p: Params | None = None):
+    """Frozen-controller replay in MST coordinates: (x, v, t) after len(H) steps."""
+    p = p or params()
+    m, pm = _d(m)
+    x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    par = np.ascontiguousarray(parents, dtype=np.int32)
+    assert par.shape == (len(H), len(m))
+    t = C.c_double()
+    _check(lib().orc_replay(len(m), pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1],
+                            par.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(p), C.byref(t)), "replay")
+    return x, v, t.value
+
+
+def force_tlm(m, r, dr, G=1.0, nthreads=0):
+    """Cartesian force, U and their tangents along directions dr [nd, n, 3]:
+    (a, U, da [nd, n, 3], dU [nd])."""
+    m, pm = _d(m)
+    r, pr = _d(r)
+    dr = np.ascontiguousarray(dr, dtype=np.float64).reshape(-1, len(m), 3)
+    nd = dr.shape[0]
+    a = np.empty((len(m), 3)); U = C.c_double()
+    da = np.empty_like(dr); dU = np.empty(nd)
+    _check(lib().orc_force_tlm(len(m), pm, pr, float(G), nd, _d(dr)[1], _d(a)[1], C.byref(U), _d(da)[1],
+                               _d(dU)[1], int(nthreads)), "force_tlm")
+    return a, U.value, da, dU
+
+
+def lagrange_weights(k_fix):
+    c = np.empty(k_fix)
+    lib().orc_lagrange_weights(int(k_fix), _d(c)[1])
+    return c
+
+
+def replay_tlm(m, x, v, t0, H, dx, dv, p: Params | None = None):
+    """Tangent-linear model of the replay (Cartesian form): end state (x, v, t)
+    and its tangents (dx, dv [nd, n, 3], dt [nd]) along (dx, dv)."""
+    p = p or params()
+    m, pm = _d(m)
+    n = len(m)
+    x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
+    dx = np.array(dx, dtype=np.float64, order="C").reshape(-1, n, 3)
+    dv = np.array(dv, dtype=np.float64, order="C").reshape(-1, n, 3)
+    nd = dx.shape[0]
+    assert dv.shape == dx.shape
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    dt = np.zeros(max(nd, 1))
+    t = C.c_double()
+    _check(lib().orc_replay_tlm(n, pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1], C.byref(p), nd,
+                                _d(dx)[1], _d(dv)[1], _d(dt)[1], C.byref(t)), "replay_tlm")
+    return x, v, t.value, dx, dv, dt[:nd]

@@ -855,9 +855,31 @@ static int all_finite(int k, const double *a) {
  * |t_end - tau| <= t_tol |t_end - t0| or max_time_iter extra steps were taken.
  * Unconverged GBS steps are halved (Sec. 2.3).  x, v are replaced by the state
  * at t_reached. */
+static int integrate_impl(int n, const double *m, double *x, double *v, double t0, double t_end,
+                          const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
+                          int32_t *rec_par, int64_t *n_rec);
+
 int orc_integrate(int n, const double *m, double *x, double *v, double t0, double t_end,
                   const orc_params *p, orc_stats *st) {
+    return integrate_impl(n, m, x, v, t0, t_end, p, st, -1, NULL, NULL, NULL);
+}
+
+/* The driver with a record of its accepted steps, for the frozen-controller
+ * replay below: for accepted step k < max_acc, rec_H[k] is its fictitious
+ * step and rec_par[k*n ..] the MST parent array it used.  Stops after max_acc
+ * accepted steps (returning ORC_OK) if t_end is not reached first. */
+int orc_integrate_rec(int n, const double *m, double *x, double *v, double t0, double t_end,
+                      const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
+                      int32_t *rec_par, int64_t *n_rec) {
+    if (max_acc < 1 || !rec_H || !rec_par || !n_rec) return ORC_E_INVAL;
+    return integrate_impl(n, m, x, v, t0, t_end, p, st, max_acc, rec_H, rec_par, n_rec);
+}
+
+static int integrate_impl(int n, const double *m, double *x, double *v, double t0, double t_end,
+                          const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
+                          int32_t *rec_par, int64_t *n_rec) {
     memset(st, 0, sizeof(*st));
+    if (n_rec) *n_rec = 0;
     st->t_reached = t0;
     if (n < 2 || p->k_fix < 2 || p->k_fix > 32 || p->n_d < 0 || p->n_d > 8 || !(p->eta > 0.0) ||
         !(p->G > 0.0) || !(t_end != t0) || !isfinite(t0) || !isfinite(t_end))
@@ -929,6 +951,11 @@ int orc_integrate(int n, const double *m, double *x, double *v, double t0, doubl
                 H = hn;
                 continue;
             }
+            if (rec_H && *n_rec < max_acc) {
+                rec_H[*n_rec] = H;
+                memcpy(rec_par + (size_t)(*n_rec) * (size_t)n, y.parent, sizeof(int32_t) * (size_t)n);
+                ++*n_rec;
+            }
             st->steps_accepted++;
             st->h_last = H;
             halvings = 0;
@@ -939,6 +966,7 @@ int orc_integrate(int n, const double *m, double *x, double *v, double t0, doubl
             st->h_next = hn;
             if (fabs(t_end - y.t) <= p->t_tol * span) { rc = ORC_OK; break; }
             if (iters > p->max_time_iter) { rc = ORC_W_TIME_TOL; break; }
+            if (max_acc > 0 && st->steps_accepted >= max_acc) { rc = ORC_OK; break; }
         }
         free(S0); free(dS0);
         st->time_iters = iters;
@@ -994,4 +1022,381 @@ double orc_sdiv(int kf, int ndiv, int *group) {
     int64_t mx = 0;
     for (int q = 0; q < ndiv; ++q) if (C[q] > mx) mx = C[q];
     return (double)total / (double)mx;
+}
+
+/* ------------------------------------------------------------------ */
+/* Frozen-controller replay and its tangent-linear model (the reference for
+ * the adjoint; not in the paper).  With the accepted steps H_k and the MST
+ * topologies recorded, the integrator is a smooth map from the initial
+ * positions and velocities to the end state: discretise, then differentiate. */
+
+/* Rebuild onto a given parent array (Sec. 3.5 with the topology fixed): the
+ * edge vector of each new edge is the old tree's separation of that pair
+ * under the close-pair rule, as in rebuild(). */
+static int rebuild_to(ostate *y, const orc_params *p, oscratch *s, const int32_t *np) {
+    const int n = y->n;
+    int changed = 0;
+    for (int u = 0; u < n; ++u) if (np[u] != y->parent[u]) { changed = 1; break; }
+    if (!changed) return ORC_OK;
+    int *nl = (int *)malloc(sizeof(int) * (size_t)n), *no = (int *)malloc(sizeof(int) * (size_t)n);
+    double *nX = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *nV = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    int rc = ORC_OK;
+    if (!nl || !no || !nX || !nV) { rc = ORC_E_NOMEM; goto out; }
+    if (orc_tree_levels(n, np, nl, no) < 0) { rc = ORC_E_INVAL; goto out; }
+    orc_deconstruct(n, y->parent, y->order, y->X, s->rho);
+    orc_deconstruct(n, y->parent, y->order, y->V, s->ups);
+    for (int u = 0; u < n; ++u) {
+        int q = np[u];
+        if (q < 0) { for (int c = 0; c < 3; ++c) { nX[3 * u + c] = 0.0; nV[3 * u + c] = 0.0; } continue; }
+        orc_separation(q, u, y->parent, y->level, y->X, s->rho, p->n_d, nX + 3 * u);
+        orc_separation(q, u, y->parent, y->level, y->V, s->ups, p->n_d, nV + 3 * u);
+    }
+    memcpy(y->parent, np, sizeof(int) * (size_t)n);
+    memcpy(y->level, nl, sizeof(int) * (size_t)n);
+    memcpy(y->order, no, sizeof(int) * (size_t)n);
+    memcpy(y->X, nX, sizeof(double) * 3 * (size_t)n);
+    memcpy(y->V, nV, sizeof(double) * 3 * (size_t)n);
+out:
+    free(nl); free(no); free(nX); free(nV);
+    return rc;
+}
+
+/* One GBS step of fixed length H without the error test (Sec. 2.3): the k_fix
+ * divisions, Neville-Aitken, state += T_{k_fix,k_fix} -- the arithmetic of an
+ * accepted gbs_divisions(). */
+static int replay_step(ostate *y, const orc_params *p, oscratch *s, double H, int64_t *nforce) {
+    const int n = y->n, kf = p->k_fix, L = nvars(n);
+    int rc = ORC_OK;
+    double *tab = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    double *diag = (double *)malloc(sizeof(double) * (size_t)L * (size_t)kf);
+    double *Xw = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *Vw = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    int *nk = (int *)malloc(sizeof(int) * (size_t)kf);
+    if (!tab || !diag || !Xw || !Vw || !nk) { rc = ORC_E_NOMEM; goto out; }
+    for (int k = 0; k < kf; ++k) nk[k] = 2 * (k + 1);
+    for (int k = 0; k < kf && !rc; ++k) {
+        odiv d;
+        d.y0 = y; d.dX = Xw; d.dV = Vw;
+        rc = leapfrog(&d, p, s, H, nk[k], nforce);
+        if (!rc) pack_incr(&d, tab + (size_t)k * L);
+    }
+    if (!rc) rc = orc_neville(kf, L, nk, tab, diag);
+    if (!rc) apply_incr(y, diag + (size_t)(kf - 1) * L);
+out:
+    free(tab); free(diag); free(Xw); free(Vw); free(nk);
+    return rc;
+}
+
+/* Replay: initial MST state on parents[0], then for k < nsteps a rebuild onto
+ * parents[k] (k > 0) and a GBS step of length H[k]; x, v are replaced by the
+ * end state and *t_out is its time.  With the record of orc_integrate_rec
+ * this repeats that integration bit for bit. */
+int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t nsteps, const double *H,
+               const int32_t *parents, const orc_params *p, double *t_out) {
+    if (n < 2 || nsteps < 0 || !H || !parents || p->beta != 0.0) return ORC_E_INVAL;
+    int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    double *X = (double *)malloc(sizeof(double) * 3 * (size_t)n), *V = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double scal[9];
+    oscratch s;
+    int rc = scratch_alloc(&s, n);
+    if (!rc && (!parent || !level || !order || !X || !V)) rc = ORC_E_NOMEM;
+    if (rc) goto out;
+    memcpy(parent, parents, sizeof(int) * (size_t)n);
+    if (orc_tree_levels(n, parent, level, order) < 0) { rc = ORC_E_INVAL; goto out; }
+    for (int u = 0; u < n; ++u) {
+        int q = parent[u];
+        for (int c = 0; c < 3; ++c) {
+            X[3 * u + c] = q < 0 ? 0.0 : x[3 * u + c] - x[3 * q + c];
+            V[3 * u + c] = q < 0 ? 0.0 : v[3 * u + c] - v[3 * q + c];
+        }
+    }
+    {
+        double rc3[3], vc3[3];
+        com3(n, m, x, rc3);
+        com3(n, m, v, vc3);
+        scal[0] = t0; scal[1] = 0.0; scal[2] = 0.0;
+        for (int c = 0; c < 3; ++c) { scal[3 + c] = rc3[c]; scal[6 + c] = vc3[c]; }
+    }
+    ostate y;
+    make_state(&y, n, m, parent, level, order, X, V, scal);
+    {
+        double U0, Om0;
+        int64_t nf = 0;
+        rc = eval_force(&y, y.X, p, &s, &U0, &Om0);
+        if (rc) goto out;
+        double T0 = com_frame_velocities(&y, y.V, s.ups, s.vt_old);
+        y.B = U0 - T0;
+        for (int64_t k = 0; k < nsteps && !rc; ++k) {
+            if (k > 0) rc = rebuild_to(&y, p, &s, parents + (size_t)k * (size_t)n);
+            if (!rc) rc = replay_step(&y, p, &s, H[k], &nf);
+        }
+    }
+    if (!rc) {
+        store_scal(&y, scal);
+        orc_state_to_cartesian(n, m, parent, X, V, scal, x, v);
+        if (t_out) *t_out = y.t;
+    }
+out:
+    scratch_free(&s);
+    free(parent); free(level); free(order); free(X); free(V);
+    return rc;
+}
+
+/* Tangent of the Newtonian force (Sec. 2.1) in Cartesian coordinates r [n][3]:
+ * a_i = G sum_j m_j d_ij/|d_ij|^3 with d_ij = r_j - r_i, U = G sum_{i<j} m_i m_j/|d_ij|,
+ * and for each of nd directions dr [nd][n][3]:
+ *   da_i = G sum_j m_j (I/r^3 - 3 d d^T/r^5)(dr_j - dr_i),  dU = sum_i m_i a_i . dr_i
+ * (the derivative of d/|d|^3 and of 1/|d|).  OpenMP over i only.  a, U, da,
+ * dU may be NULL. */
+int orc_force_tlm(int n, const double *m, const double *r, double G, int nd, const double *dr,
+                  double *a, double *U, double *da, double *dU, int nthreads) {
+    double *acc = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!acc || !phi) { free(acc); free(phi); return ORC_E_NOMEM; }
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+    for (int i = 0; i < n; ++i) {
+        double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d0 = r[3 * j] - r[3 * i], d1 = r[3 * j + 1] - r[3 * i + 1], d2 = r[3 * j + 2] - r[3 * i + 2];
+            double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+            double ri = 1.0 / sqrt(r2);
+            double s3 = m[j] * ((ri * ri) * ri);
+            ax = ax + s3 * d0; ay = ay + s3 * d1; az = az + s3 * d2;
+            ph = ph + m[j] * ri;
+        }
+        acc[3 * i] = G * ax; acc[3 * i + 1] = G * ay; acc[3 * i + 2] = G * az;
+        phi[i] = ph;
+    }
+    if (a) memcpy(a, acc, sizeof(double) * 3 * (size_t)n);
+    if (U) {
+        nsum su;
+        ns_init(&su);
+        for (int i = 0; i < n; ++i) ns_add(&su, m[i] * phi[i]);
+        *U = 0.5 * G * ns_get(&su);
+    }
+    for (int q = 0; q < nd && da; ++q) {
+        const double *t = dr + (size_t)q * 3 * (size_t)n;
+        double *o = da + (size_t)q * 3 * (size_t)n;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+        for (int i = 0; i < n; ++i) {
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double d0 = r[3 * j] - r[3 * i], d1 = r[3 * j + 1] - r[3 * i + 1], d2 = r[3 * j + 2] - r[3 * i + 2];
+                double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
+                double ri = 1.0 / sqrt(r2);
+                double r3 = (ri * ri) * ri, r5 = r3 * (ri * ri);
+                double e0 = t[3 * j] - t[3 * i], e1 = t[3 * j + 1] - t[3 * i + 1], e2 = t[3 * j + 2] - t[3 * i + 2];
+                double de = (d0 * e0 + d1 * e1) + d2 * e2;
+                gx = gx + m[j] * (e0 * r3 - 3.0 * d0 * de * r5);
+                gy = gy + m[j] * (e1 * r3 - 3.0 * d1 * de * r5);
+                gz = gz + m[j] * (e2 * r3 - 3.0 * d2 * de * r5);
+            }
+            o[3 * i] = G * gx; o[3 * i + 1] = G * gy; o[3 * i + 2] = G * gz;
+        }
+        if (dU) {
+            nsum du;
+            ns_init(&du);
+            for (int i = 0; i < n; ++i)
+                for (int c = 0; c < 3; ++c) ns_add(&du, m[i] * (acc[3 * i + c] * t[3 * i + c]));
+            dU[q] = ns_get(&du);
+        }
+    }
+    free(acc); free(phi);
+    return ORC_OK;
+}
+
+/* The frozen-controller map in exact arithmetic does not depend on the
+ * coordinates it is evaluated in: the MST transforms and rebuilds are linear
+ * changes of variables (Sec. 2.2, 3.5), a drift moves every body by dt v_i
+ * and a kick changes every velocity by dt a_i (the MST form is the same
+ * update on edge differences; sum_i m_i a_i = 0).  The tangent-linear model
+ * is therefore written in Cartesian coordinates: state (r, v, t), constant
+ * B = U(r0) - T(v0) (Sec. 2.1, B = -H), and nd tangent directions carried
+ * along with it. */
+typedef struct {
+    int n, nd, nthreads;
+    const double *m;
+    double G, alpha, gamma, B, t;
+    double *r, *v;          /* [n][3] */
+    double *dr, *dv;        /* [nd][n][3] */
+    double *dt, *dB;        /* [nd] */
+} tstate;
+
+typedef struct { double *vc, *a, *da, *dU; } tscratch;
+
+/* T = 1/2 sum m |v - v_cm|^2 and the COM-frame velocities (as com_frame_velocities). */
+static double t_kinetic(const tstate *z, double *vc) {
+    double vb[3];
+    com3(z->n, z->m, z->v, vb);
+    nsum T;
+    ns_init(&T);
+    for (int i = 0; i < z->n; ++i) {
+        for (int c = 0; c < 3; ++c) vc[3 * i + c] = z->v[3 * i + c] - vb[c];
+        ns_add(&T, z->m[i] * ((vc[3 * i] * vc[3 * i] + vc[3 * i + 1] * vc[3 * i + 1]) + vc[3 * i + 2] * vc[3 * i + 2]));
+    }
+    return 0.5 * ns_get(&T);
+}
+
+/* Drift D(ds): dt = ds/(alpha (T + B) + gamma); r += dt v; t += dt.
+ * Tangent: dT = sum m vc . dv; d(dt) = -(dt/g) alpha (dT + dB). */
+static void t_drift(tstate *z, tscratch *w, double ds) {
+    const int n = z->n;
+    double T = t_kinetic(z, w->vc);
+    double g = z->alpha * (T + z->B) + z->gamma;
+    double dt = ds / g;
+    for (int q = 0; q < z->nd; ++q) {
+        double *dr = z->dr + (size_t)q * 3 * n, *dv = z->dv + (size_t)q * 3 * n;
+        nsum s;
+        ns_init(&s);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) ns_add(&s, z->m[i] * (w->vc[3 * i + c] * dv[3 * i + c]));
+        double ddt = -(dt / g) * (z->alpha * (ns_get(&s) + z->dB[q]));
+        for (int k = 0; k < 3 * n; ++k) dr[k] = dr[k] + (ddt * z->v[k] + dt * dv[k]);
+        z->dt[q] = z->dt[q] + ddt;
+    }
+    for (int k = 0; k < 3 * n; ++k) z->r[k] = z->r[k] + dt * z->v[k];
+    z->t = z->t + dt;
+}
+
+/* Kick K(ds): dt = ds/(alpha U + gamma); v += dt a.  Tangent: d(dt) = -(dt/g) alpha dU. */
+static int t_kick(tstate *z, tscratch *w, double ds) {
+    const int n = z->n;
+    double U;
+    int rc = orc_force_tlm(n, z->m, z->r, z->G, z->nd, z->dr, w->a, &U, w->da, w->dU, z->nthreads);
+    if (rc) return rc;
+    double g = z->alpha * U + z->gamma;
+    double dt = ds / g;
+    for (int q = 0; q < z->nd; ++q) {
+        double *dv = z->dv + (size_t)q * 3 * n, *da = w->da + (size_t)q * 3 * n;
+        double ddt = -(dt / g) * (z->alpha * w->dU[q]);
+        for (int k = 0; k < 3 * n; ++k) dv[k] = dv[k] + (ddt * w->a[k] + dt * da[k]);
+    }
+    for (int k = 0; k < 3 * n; ++k) z->v[k] = z->v[k] + dt * w->a[k];
+    return ORC_OK;
+}
+
+/* Lagrange weights of the extrapolation to h = 0 in the variable h^2 with
+ * nodes h_k = H/n_k, n_k = 2k (Sec. 2.3, 4.2): T_{k_fix,k_fix} = sum_k c_k T_{k,1},
+ * c_k = prod_{j != k} n_k^2 / (n_k^2 - n_j^2). */
+void orc_lagrange_weights(int kf, double *c) {
+    for (int k = 0; k < kf; ++k) {
+        double nk2 = (double)(2 * (k + 1)) * (double)(2 * (k + 1));
+        double w = 1.0;
+        for (int j = 0; j < kf; ++j) {
+            if (j == k) continue;
+            double nj2 = (double)(2 * (j + 1)) * (double)(2 * (j + 1));
+            w = w * (nk2 / (nk2 - nj2));
+        }
+        c[k] = w;
+    }
+}
+
+/* Tangent-linear model of the replay: from (x0, v0) at t0 and directions
+ * (dx0, dv0) [nd][n][3], nsteps GBS steps of lengths H[k] (each: the k_fix
+ * leapfrog divisions from the step's start state combined with the Lagrange
+ * weights).  Returns the end state in x, v, *t_out and its tangents in
+ * dx, dv [nd][n][3], dt [nd]. */
+int orc_replay_tlm(int n, const double *m, double *x, double *v, double t0, int64_t nsteps, const double *H,
+                   const orc_params *p, int nd, double *dx, double *dv, double *dt, double *t_out) {
+    if (n < 2 || nd < 0 || nsteps < 0 || !H || p->beta != 0.0 || p->k_fix < 2 || p->k_fix > 32) return ORC_E_INVAL;
+    const int kf = p->k_fix;
+    const size_t S3 = 3 * (size_t)n, SD = (size_t)nd * S3;
+    double c[32];
+    orc_lagrange_weights(kf, c);
+    /* start-of-step state (r0, v0, t) with tangents, one division's state,
+     * and the weighted increments of the new state */
+    double *r0 = (double *)calloc(S3, sizeof(double)), *v0 = (double *)calloc(S3, sizeof(double));
+    double *r = (double *)calloc(S3, sizeof(double)), *vv = (double *)calloc(S3, sizeof(double));
+    double *ar = (double *)calloc(S3, sizeof(double)), *av = (double *)calloc(S3, sizeof(double));
+    double *vc = (double *)calloc(S3, sizeof(double)), *acc = (double *)calloc(S3, sizeof(double));
+    double *dr0 = (double *)calloc(SD + 1, sizeof(double)), *dv0 = (double *)calloc(SD + 1, sizeof(double));
+    double *drr = (double *)calloc(SD + 1, sizeof(double)), *dvv = (double *)calloc(SD + 1, sizeof(double));
+    double *adr = (double *)calloc(SD + 1, sizeof(double)), *adv = (double *)calloc(SD + 1, sizeof(double));
+    double *da = (double *)calloc(SD + 1, sizeof(double));
+    double *dt0 = (double *)calloc((size_t)nd + 1, sizeof(double)), *dtt = (double *)calloc((size_t)nd + 1, sizeof(double));
+    double *adt = (double *)calloc((size_t)nd + 1, sizeof(double)), *dU = (double *)calloc((size_t)nd + 1, sizeof(double));
+    double *dBv = (double *)calloc((size_t)nd + 1, sizeof(double));
+    int rc = ORC_OK;
+    if (!r0 || !v0 || !r || !vv || !ar || !av || !vc || !acc || !dr0 || !dv0 || !drr || !dvv || !adr || !adv ||
+        !da || !dt0 || !dtt || !adt || !dU || !dBv) {
+        rc = ORC_E_NOMEM;
+        goto out;
+    }
+    tscratch w = {vc, acc, da, dU};
+    memcpy(r0, x, sizeof(double) * S3);
+    memcpy(v0, v, sizeof(double) * S3);
+    memcpy(dr0, dx, sizeof(double) * SD);
+    memcpy(dv0, dv, sizeof(double) * SD);
+    double tt0 = t0, B;
+    {   /* B = U(r0) - T(v0) and its tangent */
+        tstate z = {n, nd, p->nthreads, m, p->G, p->alpha, p->gamma, 0.0, t0, r0, v0, dr0, dv0, dt0, dBv};
+        double U;
+        rc = orc_force_tlm(n, m, r0, p->G, nd, dr0, acc, &U, NULL, NULL, p->nthreads);
+        if (rc) goto out;
+        double T = t_kinetic(&z, vc);
+        B = U - T;
+        for (int q = 0; q < nd; ++q) {
+            nsum s;
+            ns_init(&s);
+            const double *e = dr0 + (size_t)q * S3, *f = dv0 + (size_t)q * S3;
+            for (int i = 0; i < n; ++i)
+                for (int cc = 0; cc < 3; ++cc) {
+                    ns_add(&s, m[i] * (acc[3 * i + cc] * e[3 * i + cc]));
+                    ns_add(&s, -(m[i] * (vc[3 * i + cc] * f[3 * i + cc])));
+                }
+            dBv[q] = ns_get(&s);
+        }
+    }
+    for (int64_t st = 0; st < nsteps; ++st) {
+        /* accumulated increments of the new state */
+        memset(ar, 0, sizeof(double) * S3); memset(av, 0, sizeof(double) * S3);
+        memset(adr, 0, sizeof(double) * SD); memset(adv, 0, sizeof(double) * SD);
+        double at = 0.0;
+        for (int q = 0; q < nd; ++q) adt[q] = 0.0;
+        for (int k = 0; k < kf; ++k) {
+            memcpy(r, r0, sizeof(double) * S3); memcpy(vv, v0, sizeof(double) * S3);
+            memcpy(drr, dr0, sizeof(double) * SD); memcpy(dvv, dv0, sizeof(double) * SD);
+            memcpy(dtt, dt0, sizeof(double) * (size_t)nd);
+            tstate z = {n, nd, p->nthreads, m, p->G, p->alpha, p->gamma, B, tt0, r, vv, drr, dvv, dtt, dBv};
+            const int ns = 2 * (k + 1);
+            const double h = H[st] / (double)ns;
+            t_drift(&z, &w, 0.5 * h);
+            for (int j = 0; j < ns - 1; ++j) {
+                if ((rc = t_kick(&z, &w, h))) goto out;
+                t_drift(&z, &w, h);
+            }
+            if ((rc = t_kick(&z, &w, h))) goto out;
+            t_drift(&z, &w, 0.5 * h);
+            /* increments from the start state, weighted */
+            for (size_t i = 0; i < S3; ++i) { ar[i] += c[k] * (r[i] - r0[i]); av[i] += c[k] * (vv[i] - v0[i]); }
+            for (size_t i = 0; i < SD; ++i) { adr[i] += c[k] * (drr[i] - dr0[i]); adv[i] += c[k] * (dvv[i] - dv0[i]); }
+            at += c[k] * (z.t - tt0);
+            for (int q = 0; q < nd; ++q) adt[q] += c[k] * (dtt[q] - dt0[q]);
+        }
+        for (size_t i = 0; i < S3; ++i) { r0[i] += ar[i]; v0[i] += av[i]; }
+        for (size_t i = 0; i < SD; ++i) { dr0[i] += adr[i]; dv0[i] += adv[i]; }
+        tt0 += at;
+        for (int q = 0; q < nd; ++q) dt0[q] += adt[q];
+    }
+    memcpy(x, r0, sizeof(double) * S3);
+    memcpy(v, v0, sizeof(double) * S3);
+    memcpy(dx, dr0, sizeof(double) * SD);
+    memcpy(dv, dv0, sizeof(double) * SD);
+    for (int q = 0; q < nd; ++q) dt[q] = dt0[q];
+    if (t_out) *t_out = tt0;
+    rc = ORC_OK;
+out:
+    free(r0); free(v0); free(r); free(vv); free(ar); free(av); free(vc); free(acc);
+    free(dr0); free(dv0); free(drr); free(dvv); free(adr); free(adv); free(da);
+    free(dt0); free(dtt); free(adt); free(dU); free(dBv);
+    return rc;
 }

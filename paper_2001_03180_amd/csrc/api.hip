@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/mstar.h"
+#include "adjoint.h"
 #include "batch.h"
 #include "common.h"
 
@@ -64,6 +65,18 @@ struct mstar_ctx {
     hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
+    // frozen-controller replay and adjoint (kernels_adjoint.hip)
+    std::vector<void *> a_allocs;
+    int a_n = 0, a_kf = 0;
+    int64_t a_ncp = 0, a_seg = 0;
+    AdjDev ad{};
+    d4 *Yr = nullptr, *Yv = nullptr;      // current state
+    double *Yt = nullptr;
+    d4 *cpr = nullptr, *cpv = nullptr;    // checkpoints
+    double *cpt = nullptr;
+    d4 *sgr = nullptr, *sgv = nullptr;    // states of one checkpoint segment
+    double *sgt = nullptr;
+    double *a_m = nullptr, *a_c = nullptr, *a_io[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -518,6 +531,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_workspace(ctx);
+    for (void *p : ctx->a_allocs) (void)hipFree(p);
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
     if (ctx->h_bargs) (void)hipHostFree(ctx->h_bargs);
@@ -669,9 +683,15 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     return MSTAR_OK;
 }
 
-int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
-                    double t0, double t_end, mstar_stats *stats) {
+}  // extern "C"
+
+// The driver (Sec. 2.4); with rec_H, the fictitious step of every accepted
+// step is recorded and the run stops after max_acc accepted steps.
+static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
+                          double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
+                          int64_t *n_rec) {
     if (!ctx) return MSTAR_E_INVAL;
+    if (n_rec) *n_rec = 0;
     int rc = check_params(ctx, params);
     if (rc) return rc;
     if (n < 2 || n > (1 << 24) || !m || !x || !v || !stats || stats->struct_size != sizeof(mstar_stats))
@@ -740,6 +760,7 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
             H = c.h_next;
             continue;
         }
+        if (rec_H && *n_rec < max_acc) rec_H[(*n_rec)++] = H;
         st.steps_accepted++;
         st.h_last = H;
         halvings = 0;
@@ -752,6 +773,7 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
         t_now = ctx->h_sys->t;
         if (std::fabs(t_end - t_now) <= p.t_tol * span) { rc = MSTAR_OK; break; }
         if (st.time_iters > p.max_time_iter) { rc = MSTAR_W_TIME_TOL; break; }
+        if (rec_H && st.steps_accepted >= max_acc) { rc = MSTAR_OK; break; }
     }
     st.t_reached = ctx->h_sys->t;
     if (rc == MSTAR_OK || rc == MSTAR_W_TIME_TOL || rc == MSTAR_E_NOCONV || rc == MSTAR_E_MAXSTEPS) {
@@ -765,6 +787,21 @@ int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
     *stats = st;
     if (rc < 0 && ctx->err.empty()) fail(ctx, rc, "%s", mstar_strerror(rc));
     return rc;
+}
+
+extern "C" {
+
+int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                    double t0, double t_end, mstar_stats *stats) {
+    return integrate_impl(ctx, params, n, m, x, v, t0, t_end, stats, -1, nullptr, nullptr);
+}
+
+int mstar_integrate_record(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
+                           double *v, double t0, double t_end, int64_t max_accepted, double *H,
+                           int64_t *n_accepted, mstar_stats *stats) {
+    if (!ctx) return MSTAR_E_INVAL;
+    if (max_accepted < 1 || !H || !n_accepted) return fail(ctx, MSTAR_E_INVAL, "integrate_record: bad arguments");
+    return integrate_impl(ctx, params, n, m, x, v, t0, t_end, stats, max_accepted, H, n_accepted);
 }
 
 }  // extern "C"
@@ -1064,6 +1101,221 @@ int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_s
     top.kernel_ms = top_ms;
     ctx->bcfg[kf] = top;
     *best = top;
+    return MSTAR_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// Frozen-controller replay and its adjoint.
+
+namespace {
+
+int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
+    if (n <= ctx->a_n && kf <= ctx->a_kf && ncp <= ctx->a_ncp && seg <= ctx->a_seg) {
+        ctx->ad.n = n;
+        ctx->ad.kf = kf;
+        return MSTAR_OK;
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    const size_t N = (size_t)std::max(n, ctx->a_n), K = (size_t)std::max(std::max(kf, 2), ctx->a_kf);
+    const size_t CP = (size_t)std::max<int64_t>(std::max<int64_t>(ncp, 1), ctx->a_ncp);
+    const size_t SG = (size_t)std::max<int64_t>(std::max<int64_t>(seg, 1), ctx->a_seg);
+    for (void *p : ctx->a_allocs) (void)hipFree(p);
+    ctx->a_allocs.clear();
+    ctx->a_n = ctx->a_kf = 0;
+    ctx->a_ncp = ctx->a_seg = 0;
+    const size_t kicks = K * (K + 1), drifts = K * (K + 1) + K, ops = 2 * K * (K + 1) + K;
+    AdjDev &d = ctx->ad;
+    auto A = [&](auto **p, size_t count) -> int {
+        void *q = nullptr;
+        const size_t bytes = sizeof(**p) * std::max<size_t>(count, 1);
+        if (hipMalloc(&q, bytes) != hipSuccess) return fail(ctx, MSTAR_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        ctx->a_allocs.push_back(q);
+        *p = (std::remove_reference_t<decltype(*p)>)q;
+        return MSTAR_OK;
+    };
+    double *m_ = nullptr, *c_ = nullptr;
+    int rc = 0;
+    if ((rc = A(&m_, N)) || (rc = A(&c_, K)) || (rc = A(&d.B, 1)) || (rc = A(&d.Er, K * N)) || (rc = A(&d.Ev, K * N)) ||
+        (rc = A(&d.Et, K)) || (rc = A(&d.Lr, N)) || (rc = A(&d.Lv, N)) || (rc = A(&d.Lt, 1)) || (rc = A(&d.LB, 1)) ||
+        (rc = A(&d.Sr, K * N)) || (rc = A(&d.Sv, K * N)) || (rc = A(&d.St, K)) || (rc = A(&d.SB, K)) ||
+        (rc = A(&d.rst, kicks * N)) || (rc = A(&d.vst, drifts * N)) || (rc = A(&d.sc, ops * kAdjOpScal)) ||
+        (rc = A(&ctx->Yr, N)) || (rc = A(&ctx->Yv, N)) || (rc = A(&ctx->Yt, 1)) || (rc = A(&ctx->cpr, CP * N)) ||
+        (rc = A(&ctx->cpv, CP * N)) || (rc = A(&ctx->cpt, CP)) || (rc = A(&ctx->sgr, SG * N)) ||
+        (rc = A(&ctx->sgv, SG * N)) || (rc = A(&ctx->sgt, SG)))
+        return rc;
+    for (auto &io : ctx->a_io)
+        if ((rc = A(&io, 3 * N))) return rc;
+    ctx->a_m = m_;
+    ctx->a_c = c_;
+    d.m = m_;
+    d.c = c_;
+    ctx->a_n = (int)N;
+    ctx->a_kf = (int)K;
+    ctx->a_ncp = (int64_t)CP;
+    ctx->a_seg = (int64_t)SG;
+    d.n = n;
+    d.kf = kf;
+    return MSTAR_OK;
+}
+
+// Common set-up of a replay: parameters, sizes, steps; masses, extrapolation
+// weights and the initial state (r0, v0, t0) on the device.
+int adj_setup(mstar_ctx *ctx, const mstar_params *p, int64_t n, const double *m, const double *x, const double *v,
+              double t0, int64_t nsteps, const double *H, int64_t ncp, int64_t seg) {
+    int rc = check_params(ctx, p);
+    if (rc) return rc;
+    if (n < 2 || !m || !x || !v || nsteps < 0 || (nsteps > 0 && !H) || !std::isfinite(t0))
+        return fail(ctx, MSTAR_E_INVAL, "replay: bad arguments");
+    if (n > kAdjMaxN) return fail(ctx, MSTAR_E_UNSUPPORTED, "replay: n > %d is not implemented", kAdjMaxN);
+    for (int64_t k = 0; k < nsteps; ++k)
+        if (!std::isfinite(H[k]) || H[k] == 0.0) return fail(ctx, MSTAR_E_INVAL, "replay: H[%lld] invalid", (long long)k);
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = p->flags;
+    std::vector<double> hm((size_t)n), hx(3 * (size_t)n), hv(3 * (size_t)n);
+    const hipMemcpyKind k = is_dev(flags) ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCK(hipMemcpy(hm.data(), m, sizeof(double) * n, k));
+    HIPCK(hipMemcpy(hx.data(), x, sizeof(double) * 3 * n, k));
+    HIPCK(hipMemcpy(hv.data(), v, sizeof(double) * 3 * n, k));
+    for (int64_t i = 0; i < n; ++i)
+        if (!(hm[i] > 0.0) || !std::isfinite(hm[i])) return fail(ctx, MSTAR_E_INVAL, "mass %lld is not > 0", (long long)i);
+    if (!finite_host(hx.data(), hx.size()) || !finite_host(hv.data(), hv.size()))
+        return fail(ctx, MSTAR_E_NONFINITE, "non-finite position or velocity");
+    if ((rc = ensure_adj(ctx, (int)n, p->k_fix, ncp, seg))) return rc;
+    AdjDev &d = ctx->ad;
+    d.G = p->G;
+    d.alpha = p->alpha;
+    d.gamma = p->gamma;
+    // weights of the extrapolation to h = 0 in h^2, nodes h = H/n_k, n_k = 2k
+    double c[kAdjMaxKF];
+    for (int a = 0; a < p->k_fix; ++a) {
+        const double na = (double)(2 * (a + 1)) * (double)(2 * (a + 1));
+        double w = 1.0;
+        for (int b = 0; b < p->k_fix; ++b)
+            if (b != a) {
+                const double nb = (double)(2 * (b + 1)) * (double)(2 * (b + 1));
+                w = w * (na / (na - nb));
+            }
+        c[a] = w;
+    }
+    HIPCK(hipMemcpyAsync(ctx->a_m, hm.data(), sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->a_c, c, sizeof(double) * p->k_fix, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->a_io[0], hx.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->a_io[1], hv.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream));
+    launch_adj_pack(ctx->stream, (int)n, ctx->a_io[0], ctx->Yr, t0, ctx->Yt);
+    launch_adj_pack(ctx->stream, (int)n, ctx->a_io[1], ctx->Yv, 0.0, nullptr);
+    launch_adj_init(d, ctx->stream, ctx->Yr, ctx->Yv);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(ctx->stream));   // host copies above are locals
+    return MSTAR_OK;
+}
+
+// One replayed GBS step from (r, v, t) into (or, ov, ot) (may alias).
+void adj_step(mstar_ctx *ctx, const d4 *r, const d4 *v, const double *t, double H, d4 *or_, d4 *ov, double *ot) {
+    launch_adj_fwd(ctx->ad, ctx->stream, r, v, t, H, false);
+    launch_adj_combine(ctx->ad, ctx->stream, r, v, t, or_, ov, ot);
+}
+
+int adj_out(mstar_ctx *ctx, uint32_t flags, int64_t n, const d4 *a, double *dst, int io) {
+    launch_adj_unpack(ctx->stream, (int)n, a, ctx->a_io[io]);
+    return out_copy(ctx, flags, dst, ctx->a_io[io], sizeof(double) * 3 * n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                 double t0, int64_t n_steps, const double *H, double *t_out) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    int rc = adj_setup(ctx, params, n, m, x, v, t0, n_steps, H, 1, 1);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n_steps; ++k) adj_step(ctx, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
+    HIPCK(hipGetLastError());
+    const uint32_t flags = params->flags;
+    if ((rc = adj_out(ctx, flags, n, ctx->Yr, x, 2))) return rc;
+    if ((rc = adj_out(ctx, flags, n, ctx->Yv, v, 3))) return rc;
+    double t = 0.0;
+    HIPCK(hipMemcpyAsync(&t, ctx->Yt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (t_out) *t_out = t;
+    return MSTAR_OK;
+}
+
+int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
+                         const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
+                         const double *gx, const double *gv, double gt, double *gx0, double *gv0) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    if (checkpoint_every < 1 || !gx || !gv || !gx0 || !gv0 || !std::isfinite(gt))
+        return fail(ctx, MSTAR_E_INVAL, "replay_adjoint: bad arguments");
+    const int64_t C = checkpoint_every;
+    const int64_t ncp = n_steps > 0 ? (n_steps + C - 1) / C : 1;
+    int rc = adj_setup(ctx, params, n, m, x0, v0, t0, n_steps, H, ncp, C);
+    if (rc) return rc;
+    const AdjDev &d = ctx->ad;
+    const size_t N = (size_t)n;
+    hipStream_t s = ctx->stream;
+    // forward pass, keeping the state at every C-th step
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (k % C == 0)
+            launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr + (size_t)(k / C) * N,
+                            ctx->cpv + (size_t)(k / C) * N, ctx->cpt + k / C);
+        adj_step(ctx, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
+    }
+    if (n_steps == 0) launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr, ctx->cpv, ctx->cpt);
+    // seeds: cotangent of the end state
+    const uint32_t flags = params->flags;
+    const void *gxd, *gvd;
+    if ((rc = in_dev(ctx, flags, gx, ctx->a_io[0], sizeof(double) * 3 * n, &gxd))) return rc;
+    if ((rc = in_dev(ctx, flags, gv, ctx->a_io[1], sizeof(double) * 3 * n, &gvd))) return rc;
+    launch_adj_pack(s, (int)n, (const double *)gxd, d.Lr, gt, d.Lt);
+    launch_adj_pack(s, (int)n, (const double *)gvd, d.Lv, 0.0, nullptr);
+    launch_adj_zero(s, d.LB);
+    // reverse pass, one checkpoint segment at a time
+    for (int64_t seg = ncp - 1; seg >= 0 && n_steps > 0; --seg) {
+        const int64_t j0 = seg * C, j1 = std::min(n_steps, j0 + C);
+        launch_adj_copy(s, (int)n, ctx->cpr + (size_t)seg * N, ctx->cpv + (size_t)seg * N, ctx->cpt + seg, ctx->sgr,
+                        ctx->sgv, ctx->sgt);
+        for (int64_t j = j0; j + 1 < j1; ++j) {
+            const size_t a = (size_t)(j - j0), b = a + 1;
+            adj_step(ctx, ctx->sgr + a * N, ctx->sgv + a * N, ctx->sgt + a, H[j], ctx->sgr + b * N, ctx->sgv + b * N,
+                     ctx->sgt + b);
+        }
+        for (int64_t j = j1 - 1; j >= j0; --j) {
+            const size_t a = (size_t)(j - j0);
+            launch_adj_fwd(d, s, ctx->sgr + a * N, ctx->sgv + a * N, ctx->sgt + a, H[j], true);
+            launch_adj_rev(d, s);
+            launch_adj_combine_rev(d, s);
+        }
+    }
+    launch_adj_finish(d, s, ctx->cpr, ctx->cpv, ctx->a_io[2], ctx->a_io[3]);
+    HIPCK(hipGetLastError());
+    if ((rc = out_copy(ctx, flags, gx0, ctx->a_io[2], sizeof(double) * 3 * n))) return rc;
+    if ((rc = out_copy(ctx, flags, gv0, ctx->a_io[3], sizeof(double) * 3 * n))) return rc;
+    HIPCK(hipStreamSynchronize(s));
+    return MSTAR_OK;
+}
+
+int mstar_force_hvp(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x,
+                    const double *w, double *out) {
+    if (!ctx) return MSTAR_E_INVAL;
+    int rc = check_params(ctx, params);
+    if (rc) return rc;
+    if (n < 2 || n > (1 << 24) || !m || !x || !w || !out) return fail(ctx, MSTAR_E_INVAL, "force_hvp: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    const uint32_t flags = params->flags;
+    if ((rc = ensure(ctx, (int)n))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr))) return rc;
+    const void *xd, *wd;
+    if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
+    if ((rc = in_dev(ctx, flags, w, ctx->vin, sizeof(double) * 3 * n, &wd))) return rc;
+    launch_force_hvp(ctx->stream, (int)n, params->G, ctx->d.m, (const double *)xd, (const double *)wd, ctx->xout);
+    HIPCK(hipGetLastError());
+    if ((rc = out_copy(ctx, flags, out, ctx->xout, sizeof(double) * 3 * n))) return rc;
+    HIPCK(hipStreamSynchronize(ctx->stream));
     return MSTAR_OK;
 }
 

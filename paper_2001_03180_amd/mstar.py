@@ -88,6 +88,16 @@ EXPORTS = {
     "mstar_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BatchConfig)]),
     "mstar_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchConfig)]),
+    "mstar_integrate_record": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_double, C.c_double, C.c_int64, C.c_void_p,
+                                         C.POINTER(C.c_int64), C.POINTER(Stats)]),
+    "mstar_replay": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_double, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
+    "mstar_replay_adjoint": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "mstar_force_hvp": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
 }
 
 _lib = None
@@ -328,6 +338,76 @@ class Context:
             self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
             None if t0a is None else C.c_void_p(t0a.ctypes.data), C.c_void_p(te.ctypes.data), C.byref(c)))
         return c.as_dict()
+
+    # ---------------------------------------------------------------- replay / adjoint
+    def integrate_record(self, m, x, v, t0, t_end, max_accepted, p: Params | None = None):
+        """integrate() that records the fictitious step of every accepted step and
+        stops after max_accepted of them: (x, v, rc, stats, H)."""
+        p = p or params()
+        n = len(m)
+        x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
+        v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
+        p.flags = _mode(*a)
+        H = np.zeros(int(max_accepted))
+        k = C.c_int64()
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().mstar_integrate_record(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0),
+                                          float(t_end), int(max_accepted), C.c_void_p(H.ctypes.data),
+                                          C.byref(k), C.byref(st))
+        self._check(rc, (OK, W_TIME_TOL))
+        return x, v, rc, st.as_dict(), H[:k.value].copy()
+
+    def replay(self, m, x, v, t0, H, p: Params | None = None):
+        """Frozen-controller replay of the recorded steps H: (x, v, t)."""
+        p = p or params()
+        n = len(m)
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
+        v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
+        p.flags = _mode(*a)
+        t = C.c_double()
+        self._check(lib().mstar_replay(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), len(H),
+                                       C.c_void_p(H.ctypes.data), C.byref(t)))
+        return x, v, t.value
+
+    def replay_adjoint(self, m, x0, v0, t0, H, gx, gv, gt=0.0, checkpoint_every=50, p: Params | None = None):
+        """Gradient of <gx, x> + <gv, v> + gt t (end state of the replay) with
+        respect to x0, v0: (gx0, gv0)."""
+        p = p or params()
+        n = len(m)
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        a = [_Arg(m, np.float64, (n,)), _Arg(x0, np.float64, (n, 3)), _Arg(v0, np.float64, (n, 3)),
+             _Arg(gx, np.float64, (n, 3)), _Arg(gv, np.float64, (n, 3))]
+        p.flags = _mode(*a)
+        if p.flags:
+            import torch
+            gx0 = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
+            gv0 = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
+        else:
+            gx0, gv0 = np.empty((n, 3)), np.empty((n, 3))
+        o = [_Arg(gx0, np.float64, writable=True), _Arg(gv0, np.float64, writable=True)]
+        self._check(lib().mstar_replay_adjoint(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0),
+                                               len(H), C.c_void_p(H.ctypes.data), int(checkpoint_every),
+                                               a[3].ptr, a[4].ptr, float(gt), o[0].ptr, o[1].ptr))
+        return gx0, gv0
+
+    def force_hvp(self, m, x, w, p: Params | None = None):
+        """out_i = G sum_j M(d_ij)(m_i w_j - m_j w_i): the transposed Jacobian of the accelerations times w."""
+        p = p or params()
+        n = len(m)
+        a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3)), _Arg(w, np.float64, (n, 3))]
+        p.flags = _mode(*a)
+        if p.flags:
+            import torch
+            out = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
+        else:
+            out = np.empty((n, 3))
+        o = _Arg(out, np.float64, writable=True)
+        self._check(lib().mstar_force_hvp(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, o.ptr))
+        return out
 
     def profile_enable(self, on=True):
         self._check(lib().mstar_profile_enable(self._h, 1 if on else 0))
