@@ -17,6 +17,12 @@ loop of the same library (mstar_integrate, one system per call, a seeded
 random sample of systems timed and scaled to the whole set) and to the CPU
 oracle (one system per host thread, a seeded random sample).
 
+The `adjoint` object: N=256 Plummer + central mass 0.01 (seed 501), 1000
+accepted GBS steps at eta = 1e-12 recorded by the integrator; the gradient
+of the central mass's end position (one component) with respect to all 6N
+initial coordinates by the checkpointed adjoint (every 50 steps), timed
+against the forward integration.
+
 value = (force evaluations x N_p (N_p - 1)) / wall time of the timed steps,
 inputs resident in HBM.  The roofline entry is the force kernel's algorithmic
 FLOP rate (20 FP64 flops per directed pair) from HIP events around every
@@ -144,6 +150,41 @@ def bench_batch(M, ctx, threads, do_cpu, n_single=12, n_cpu=32):
     return res
 
 
+def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
+    """Cost of one gradient (adjoint pass) against the forward integration."""
+    import numpy as np
+    import ics
+    m, x, v, _ = ics.workload("plummer256_bh")
+    n = len(m)
+    p = M.params(eta=1e-12)
+    ctx.integrate_record(m, x, v, 0.0, 1e9, 20, p)                  # warm-up
+    t0 = time.perf_counter()
+    xs, vs, rc, st, H = ctx.integrate_record(m, x, v, 0.0, 1e9, steps, p)
+    t_fwd = time.perf_counter() - t0
+    seed = np.zeros((n, 3))
+    seed[n - 1, 0] = 1.0
+    t0 = time.perf_counter()
+    gx, gv = ctx.replay_adjoint(m, x, v, 0.0, H, seed, np.zeros((n, 3)), 0.0, checkpoint_every)
+    t_adj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.replay(m, x, v, 0.0, H)
+    t_rep = time.perf_counter() - t0
+    kf = 8
+    ops = 2 * kf * (kf + 1) + kf
+    dev_bytes = 32 * n * (2 * ((steps + checkpoint_every - 1) // checkpoint_every) + 2 * checkpoint_every +
+                          ops + 4 * kf + 4) + 8 * ops * 8
+    return {
+        "workload": "plummer256_bh: Plummer N=256 (seed 501) + central mass 0.01 (N_p=257); eta=1e-12, "
+                    f"{steps} accepted GBS steps; gradient of the central mass's end x-position w.r.t. all 6N "
+                    "initial coordinates",
+        "steps": steps, "rejected_steps": st["steps_rejected"], "t_reached": st["t_reached"],
+        "forward_s": t_fwd, "adjoint_s": t_adj, "replay_s": t_rep,
+        "fwd_plus_bwd_over_fwd": (t_fwd + t_adj) / t_fwd,
+        "checkpoint_every": checkpoint_every, "adjoint_device_bytes": dev_bytes,
+        "grad_norm": float(np.sqrt(np.sum(gx * gx) + np.sum(gv * gv))),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +193,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-systems measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the batched small-systems measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -239,6 +281,8 @@ def main():
     }
     if not args.no_batch:
         out["batch"] = bench_batch(M, ctx, threads, not args.no_cpu)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(M, ctx)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x, v, eta, threads)
