@@ -43,6 +43,23 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2
 FLOPS_PER_PAIR = 20
 BATCH_T_END = 1e-2
 BATCH_ETA = 1e-12
+# HBM bytes per k_force launch on this workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
+# valid only for the force-kernel sources with this hash.
+FORCE_TRAFFIC = {"sha256": "94a0731b1302c8432905caa0b20d2b904afca22a1f32be7e9741ab01dbd33c4a",
+                 "fetch_bytes": 13979625.0, "write_bytes": 4593910.0}
+
+
+def force_traffic():
+    """Measured HBM bytes per force launch if the kernel is the one measured, else None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_force.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2001_03180_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != FORCE_TRAFFIC["sha256"]:
+        return None
+    return FORCE_TRAFFIC["fetch_bytes"] + FORCE_TRAFFIC["write_bytes"]
 
 
 def cpu_baseline(m, x, v, eta, threads):
@@ -194,6 +211,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-systems measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the batched small-systems measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -205,8 +225,20 @@ def main():
     import ics
     import paper_2001_03180_amd as M
 
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3}), flush=True)
+        return
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     ctx = M.Context(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": bench_adjoint(M, ctx)}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)
         return
@@ -272,11 +304,12 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": force_traffic(),
             "kernel": "k_force (FP64 pair loop)",
             "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         },
     }
     if not args.no_batch:
