@@ -65,6 +65,7 @@ struct mstar_ctx {
     hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
+    int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by N_d kind
     // frozen-controller replay and adjoint (kernels_adjoint.hip)
     std::vector<void *> a_allocs;
     int a_n = 0, a_kf = 0;
@@ -82,7 +83,6 @@ struct mstar_ctx {
 namespace {
 
 constexpr int kNsplitMax = 32;
-constexpr int kTargetWaves = 8192;   // ~8 waves per SIMD over 256 CUs
 
 int fail(mstar_ctx *c, int code, const char *fmt, ...) {
     if (c) {
@@ -170,14 +170,32 @@ int ensure(mstar_ctx *ctx, int n) {
 constexpr int kBase = kBaseSlot;     // slot of the start state
 constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
 
-// Number of workgroups sharing one i-block's j-range: enough waves to fill
-// the chip, at least 16 j-bodies per wave.
-int nsplit_for(const Dev &d, int nact) {
-    const int per = nact * d.nfb * kForceWaves;
-    int ns = (kTargetWaves + per - 1) / per;
-    ns = std::max(1, std::min(ns, kNsplitMax));
-    ns = std::min(ns, std::max(1, d.n / (16 * kForceWaves)));
-    return ns;
+// Resident force workgroups on the whole chip (queried once per N_d kind).
+int force_cap(mstar_ctx *ctx, int nd) {
+    const int k = nd <= 0 ? 0 : (nd == 1 ? 1 : 2);
+    if (ctx->force_cap[k] <= 0) ctx->force_cap[k] = force_blocks_per_cu(nd) * ctx->num_cu;
+    return ctx->force_cap[k];
+}
+
+// Number of j-splits of one force launch over `nact` divisions.  The
+// workgroups of a launch all take about the same time, so they run in rounds
+// of `cap` (resident workgroups of the whole chip); the split count is the
+// smallest whose last round is nearly full (within 1% of the best fill over
+// all admissible counts), with at least 16 j-bodies per wave.
+int nsplit_for(const Dev &d, int nact, int cap) {
+    const int per = nact * d.nfb;
+    const int hi = std::max(1, std::min(kNsplitMax - 1, d.n / (16 * kForceWaves)));
+    double best = 0.0;
+    std::vector<double> eff((size_t)hi + 1, 0.0);
+    for (int ns = 1; ns <= hi; ++ns) {
+        const long w = (long)per * ns;
+        const long rounds = (w + cap - 1) / cap;
+        eff[ns] = (double)w / (double)(rounds * cap);
+        best = std::max(best, eff[ns]);
+    }
+    for (int ns = 1; ns <= hi; ++ns)
+        if (eff[ns] >= best - 0.01) return ns;
+    return hi;
 }
 
 int check_params(mstar_ctx *ctx, const mstar_params *p) {
@@ -314,10 +332,10 @@ int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool wi
         SlotList sl{};
         sl.nact = 1;
         sl.slot[0] = kBase;
-        const int ns = nsplit_for(d, 1);
+        const int ns = nsplit_for(d, 1, force_cap(ctx, p->n_d));
         int rc = prof_force(ctx, sl, p->n_d, ns);
         if (rc) return rc;
-        launch_reduce_start(d, ctx->stream, kBase, p->G, ns, d.a0, &d.ctl->U0);
+        launch_reduce_start(d, ctx->stream, kBase, p->G, force_parts(ns, p->n_d), d.a0, &d.ctl->U0);
         if (nforce) ++*nforce;
     }
     HIPCK(hipGetLastError());
@@ -349,10 +367,10 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
         SlotList fk{};
         for (int k = 0; k < ndiv; ++k)
             if (nlist[k] >= s) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nlist[k]; fk.nact++; }
-        const int ns = nsplit_for(d, fk.nact);
+        const int ns = nsplit_for(d, fk.nact, force_cap(ctx, p->n_d));
         int rc = prof_force(ctx, fk, p->n_d, ns);
         if (rc) return rc;
-        launch_kick(d, ctx->stream, fk, ns, p->G, p->alpha, p->gamma);
+        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, p->alpha, p->gamma);
         if (nforce) *nforce += fk.nact;
     }
     HIPCK(hipGetLastError());
@@ -622,9 +640,9 @@ int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const dou
     SlotList sl{};
     sl.nact = 1;
     sl.slot[0] = kBase;
-    const int ns = nsplit_for(d, 1);
+    const int ns = nsplit_for(d, 1, force_cap(ctx, params->n_d));
     if ((rc = prof_force(ctx, sl, params->n_d, ns))) return rc;
-    launch_reduce_start(d, ctx->stream, kBase, params->G, ns, d.a0, &d.ctl->U0);
+    launch_reduce_start(d, ctx->stream, kBase, params->G, force_parts(ns, params->n_d), d.a0, &d.ctl->U0);
     launch_unpack3(ctx->stream, d.a0, ctx->xout, (int)n);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, acc, ctx->xout, sizeof(double) * 3 * n))) return rc;

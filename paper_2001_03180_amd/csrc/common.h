@@ -132,6 +132,12 @@ struct Dev {
 // ---------------------------------------------------------------- launches
 // kernels_force.hip
 void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit);
+// Partial sums per i-block written by launch_force: the nsplit j-splits plus
+// one close-pair correction block when N_d > 0.  Kick and start reduction
+// take this count.
+inline int force_parts(int nsplit, int nd) { return nsplit + (nd > 0 ? 1 : 0); }
+// Resident force workgroups per CU (occupancy of the force kernel).
+int force_blocks_per_cu(int nd);
 void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int nsplit, d4 *acc_out,
                          double *U_out);
 // kernels_step.hip

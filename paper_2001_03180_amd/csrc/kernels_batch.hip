@@ -79,6 +79,72 @@ __device__ __forceinline__ void gsum3(double &a, double &b, double &c) {
     if (L >= 32) { a = row_swap_sum(a, false); b = row_swap_sum(b, false); c = row_swap_sum(c, false); }
     if (L >= 64) { a = row_swap_sum(a, true); b = row_swap_sum(b, true); c = row_swap_sum(c, true); }
 }
+// Value of the butterfly partner at step q (the pairing used by gsum):
+// quad swaps, mirrored half-row and row, then the row swaps.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t swap_partner_u32(uint32_t v, bool wide) {
+    const int lane = __lane_id();
+    if (wide) {
+        const auto l = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return ((lane >> 5) & 1) ? l[0] : l[1];
+    }
+    const auto l = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return ((lane >> 4) & 1) ? l[0] : l[1];
+}
+template <int Q>
+__device__ __forceinline__ double partner_f64(double v) {
+    if constexpr (Q == 0) return dpp_f64<0xB1>(v);
+    else if constexpr (Q == 1) return dpp_f64<0x4E>(v);
+    else if constexpr (Q == 2) return dpp_f64<0x141>(v);
+    else if constexpr (Q == 3) return dpp_f64<0x140>(v);
+    else {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        const uint32_t lo = swap_partner_u32((uint32_t)u, Q == 5), hi = swap_partner_u32((uint32_t)(u >> 32), Q == 5);
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    }
+}
+template <int Q>
+__device__ __forceinline__ int partner_i32(int v) {
+    if constexpr (Q == 0) return dpp_i32<0xB1>(v);
+    else if constexpr (Q == 1) return dpp_i32<0x4E>(v);
+    else if constexpr (Q == 2) return dpp_i32<0x141>(v);
+    else if constexpr (Q == 3) return dpp_i32<0x140>(v);
+    else return (int)swap_partner_u32((uint32_t)v, Q == 5);
+}
+// Minimum over a lane group of the key (w, a, b, c), lexicographic; every
+// lane ends with the group minimum (keys are distinct or equal in full).
+template <int Q>
+__device__ __forceinline__ void argmin_step(double &w, int &a, int &b, int &c) {
+    const double w2 = partner_f64<Q>(w);
+    const int a2 = partner_i32<Q>(a), b2 = partner_i32<Q>(b), c2 = partner_i32<Q>(c);
+    const bool take = (w2 < w) || (w2 == w && (a2 < a || (a2 == a && (b2 < b || (b2 == b && c2 < c)))));
+    if (take) { w = w2; a = a2; b = b2; c = c2; }
+}
+template <int L>
+__device__ __forceinline__ void gargmin(double &w, int &a, int &b, int &c) {
+    static_assert(L == 16 || L == 32 || L == 64, "lane groups of 16, 32 or 64");
+    argmin_step<0>(w, a, b, c);
+    argmin_step<1>(w, a, b, c);
+    argmin_step<2>(w, a, b, c);
+    argmin_step<3>(w, a, b, c);
+    if constexpr (L >= 32) argmin_step<4>(w, a, b, c);
+    if constexpr (L >= 64) argmin_step<5>(w, a, b, c);
+}
+// Lane k's value in every lane (k uniform; group 0 starts at lane 0).
+__device__ __forceinline__ int lane_i32(int v, int k) {
+    return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(k));
+}
+__device__ __forceinline__ double lane_f64(double v, int k) {
+    const int kk = __builtin_amdgcn_readfirstlane(k);
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, kk);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), kk);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 template <int L>
 __device__ __forceinline__ int gor(int p) {
 #pragma unroll
@@ -183,6 +249,7 @@ struct SysLDS {
 // Writes par, lev, the children lists and the jump-round count R.
 template <int KF, int L, int G>
 __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int n) {
+    // Runs in group 0 (lanes 0 .. L-1 of the first wave) only.
     const int i = glane<L>();
     const bool live = i < n;
     const double mi = live ? S.m[i] : 0.0;
@@ -193,16 +260,11 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
     cy = cy / M;
     cz = cz / M;
     double wr = live ? w3(cx, cy, cz, p.x, p.y, p.z) : INFINITY;
-    int root = live ? i : 0x7fffffff;
-#pragma unroll
-    for (int o = 1; o < L; o <<= 1) {
-        const double w2 = __shfl_xor(wr, o, L);
-        const int r2 = __shfl_xor(root, o, L);
-        if (w2 < wr || (w2 == wr && r2 < root)) { wr = w2; root = r2; }
-    }
+    int root = live ? i : 0x7fffffff, z0 = 0, z1 = 0;
+    gargmin<L>(wr, root, z0, z1);
     bool in = (i == root);
     int mypar = -1, mylev = 0;
-    const double rx = __shfl(p.x, root, L), ry = __shfl(p.y, root, L), rz = __shfl(p.z, root, L);
+    const double rx = lane_f64(p.x, root), ry = lane_f64(p.y, root), rz = lane_f64(p.z, root);
     double bw = (live && !in) ? w3(rx, ry, rz, p.x, p.y, p.z) : INFINITY;
     int bu = root;
     for (int step = 1; step < n; ++step) {
@@ -210,23 +272,16 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
         double kw = cand ? bw : INFINITY;
         int klo = cand ? min(bu, i) : 0x7fffffff, khi = cand ? max(bu, i) : 0x7fffffff;
         int kv = cand ? i : 0x7fffffff;
-#pragma unroll
-        for (int o = 1; o < L; o <<= 1) {
-            const double w2 = __shfl_xor(kw, o, L);
-            const int lo2 = __shfl_xor(klo, o, L), hi2 = __shfl_xor(khi, o, L), v2 = __shfl_xor(kv, o, L);
-            const bool take =
-                (w2 < kw) || (w2 == kw && (lo2 < klo || (lo2 == klo && (hi2 < khi || (hi2 == khi && v2 < kv)))));
-            if (take) { kw = w2; klo = lo2; khi = hi2; kv = v2; }
-        }
+        gargmin<L>(kw, klo, khi, kv);
         const int pick = kv;
-        const int pu = __shfl(bu, pick, L);
-        const int plev = __shfl(mylev, pu, L);
+        const int pu = lane_i32(bu, pick);
+        const int plev = lane_i32(mylev, pu);
         if (i == pick) {
             in = true;
             mypar = pu;
             mylev = plev + 1;
         }
-        const double qx = __shfl(p.x, pick, L), qy = __shfl(p.y, pick, L), qz = __shfl(p.z, pick, L);
+        const double qx = lane_f64(p.x, pick), qy = lane_f64(p.y, pick), qz = lane_f64(p.z, pick);
         if (live && !in) {
             const double w = w3(qx, qy, qz, p.x, p.y, p.z);
             if (key_less(w, pick, i, bw, bu, i)) { bw = w; bu = pick; }
@@ -234,7 +289,7 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
     }
     // children lists in ascending order
     int nchild = 0;
-    for (int k = 0; k < n; ++k) nchild += (__shfl(mypar, k, L) == i) ? 1 : 0;
+    for (int k = 0; k < n; ++k) nchild += (lane_i32(mypar, k) == i) ? 1 : 0;
     int incl = live ? nchild : 0;
 #pragma unroll
     for (int o = 1; o < L; o <<= 1) {
@@ -243,7 +298,7 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
     }
     int w = incl - nchild;
     for (int k = 0; k < n; ++k) {
-        const bool mine = live && __shfl(mypar, k, L) == i;
+        const bool mine = live && lane_i32(mypar, k) == i;
         if (mine) S.cidx[w++] = k;
     }
     const int maxlev = gmaxi<L>(live ? mylev : 0);

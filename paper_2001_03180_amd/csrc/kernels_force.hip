@@ -12,10 +12,12 @@
 // order, so results are bitwise reproducible.
 //
 // Close pairs (tree distance <= N_d): the main loop uses Cartesian
-// differences for every pair; the split-0 workgroup of each i-block then
-// replaces the Cartesian term of each close pair by the term built from the
-// MST path sum (same operation sequence, so the subtracted term is the one
-// that was added).
+// differences for every pair; one extra workgroup per i-block (grid row
+// y = 0, dispatched first) computes, for each close pair, the term built from
+// the MST path sum minus the Cartesian term (same operation sequence as the
+// main loop, so the subtracted term is the one that was added) into a partial
+// of its own.  These correction blocks are short and run beside the j-loop
+// blocks instead of lengthening one of them.
 #include "common.h"
 
 namespace mstar {
@@ -27,6 +29,7 @@ struct ForceArgs {
     const d4 *X0, *dX;     // MST edge vectors: current = X0 + dX[slot]
     const int32_t *parent, *child_off, *child_idx;
     int n, nib, nib_alloc, nsplit, nsplit_max, jchunk;   // nib: force i-blocks of 64*IPL bodies
+    int nparts;            // partials per i-block: nsplit j-splits (+1 correction block when N_d > 0)
     SlotList sl;
 };
 
@@ -123,7 +126,8 @@ __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ib = blockIdx.x % a.nib;
     const int slot = a.sl.slot[blockIdx.x / a.nib];
-    const int split = blockIdx.y;
+    const int part = blockIdx.y;                          // partial index
+    const int split = ND > 0 ? part - 1 : part;            // j-split index (-1: correction block)
     const int n = a.n;
     const d4 *__restrict__ P = a.P + (size_t)slot * n;
     const int i0 = ib * 64 * IPL;
@@ -134,6 +138,25 @@ __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
         const int i = i0 + q * 64 + lane;
         ii[q] = i < n ? i : n - 1;
         pi[q] = P[ii[q]];
+    }
+    if (ND > 0 && split < 0) {   // close-pair correction block (wave 0)
+        if (wv != 0) return;
+        double u = 0.0;
+#pragma unroll
+        for (int q = 0; q < IPL; ++q) {
+            const int i = i0 + q * 64 + lane;
+            if (i < n) {
+                double cx = 0.0, cy = 0.0, cz = 0.0, cp = 0.0;
+                close_correction<ND>(i, P, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off, a.child_idx, cx,
+                                     cy, cz, cp);
+                a.part[((size_t)slot * a.nsplit_max + part) * n + i] = d4{cx, cy, cz, cp};
+                u = u + pi[q].w * cp;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) u = u + __shfl_xor(u, off, 64);
+        if (lane == 0) a.Upart[(size_t)slot * a.nib_alloc * a.nsplit_max + (size_t)ib * a.nparts + part] = u;
+        return;
     }
     const int j0 = split * a.jchunk;
     const int j1 = min(n, j0 + a.jchunk);
@@ -168,17 +191,24 @@ __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
             const d4 t = red[w][q][lane];
             s.x = s.x + t.x; s.y = s.y + t.y; s.z = s.z + t.z; s.w = s.w + t.w;
         }
-        if (ND > 0 && split == 0 && i < n)
-            close_correction<ND>(i, P, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off, a.child_idx, s.x,
-                                 s.y, s.z, s.w);
         if (i < n) {
-            a.part[((size_t)slot * a.nsplit_max + split) * n + i] = s;
+            a.part[((size_t)slot * a.nsplit_max + part) * n + i] = s;
             u = u + pi[q].w * s.w;
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) u = u + __shfl_xor(u, off, 64);
-    if (lane == 0) a.Upart[(size_t)slot * a.nib_alloc * a.nsplit_max + (size_t)ib * a.nsplit + split] = u;
+    if (lane == 0) a.Upart[(size_t)slot * a.nib_alloc * a.nsplit_max + (size_t)ib * a.nparts + part] = u;
+}
+
+int force_blocks_per_cu(int nd) {
+    constexpr int NW = kForceWaves, IPL = kForceIPL;
+    int nb = 0;
+    hipError_t e;
+    if (nd <= 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<0, NW, IPL>, 64 * NW, 0);
+    else if (nd == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<1, NW, IPL>, 64 * NW, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<2, NW, IPL>, 64 * NW, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit) {
@@ -197,15 +227,17 @@ void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int n
     a.nsplit = nsplit;
     a.nsplit_max = d.nsplit_max;
     a.jchunk = (d.n + nsplit - 1) / nsplit;
+    a.nparts = force_parts(nsplit, nd);
     a.sl = sl;
-    dim3 grid(sl.nact * d.nfb, nsplit);
+    dim3 grid(sl.nact * d.nfb, a.nparts);
     constexpr int NW = kForceWaves, IPL = kForceIPL;
     if (nd <= 0) k_force<0, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
     else if (nd == 1) k_force<1, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
     else k_force<2, NW, IPL><<<grid, 64 * NW, 0, s>>>(a);
 }
 
-// Reduce the force partials of one slot: acc = G sum_split part, and the
+// Reduce the force partials of one slot (nparts of them per i-block, see
+// force_parts): acc = G sum_part part, and the
 // force function U = G/2 sum_i m_i phi_i (every workgroup reduces the same
 // partials in the same order; block 0 stores U).
 __global__ __launch_bounds__(kWG) void k_reduce_start(const d4 *part, const double *Upart, int n, int nib,
