@@ -1133,6 +1133,7 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     if (n <= ctx->a_n && kf <= ctx->a_kf && ncp <= ctx->a_ncp && seg <= ctx->a_seg) {
         ctx->ad.n = n;
         ctx->ad.kf = kf;
+        ctx->ad.tpb = std::max(1, std::min(4, kAdjMaxN / n));
         return MSTAR_OK;
     }
     HIPCK(hipStreamSynchronize(ctx->stream));
@@ -1175,6 +1176,7 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     ctx->a_seg = (int64_t)SG;
     d.n = n;
     d.kf = kf;
+    d.tpb = std::max(1, std::min(4, kAdjMaxN / n));
     return MSTAR_OK;
 }
 

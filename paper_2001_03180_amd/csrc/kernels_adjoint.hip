@@ -18,9 +18,11 @@
 // Hessian-vector product).
 //
 // One workgroup integrates (or reverses) one substep division of one GBS
-// step with one body per thread (N <= 1024): positions and the adjoint
-// weights of the j-bodies are broadcast from LDS, and U, T, the COM velocity
-// and the d(dt) sums are workgroup sums in a fixed order.
+// step with up to 1024 threads: min(4, 1024/N) threads per body, each summing
+// a contiguous chunk of the j-range, the chunks added in order through LDS.
+// Positions and the adjoint weights of the j-bodies are broadcast from LDS,
+// and U, T, the COM velocity and the d(dt) sums are workgroup sums in a
+// fixed order.
 #include "../../include/mstar.h"
 #include "adjoint.h"
 
@@ -60,24 +62,37 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kMaxWaves = kAdjMaxN / 64;
 
-// Sums of K values over the workgroup: wave sums, then the wave partials
-// added in wave order by every thread.  Two barriers; `sh` holds K * 16.
+// Sums of K values over the workgroup with one barrier: wave sums written to
+// one of two alternating buffers, then every thread adds the wave partials in
+// wave order.  A buffer is rewritten only two calls later, after the barrier
+// of the call in between, which every thread reaches after its reads.
 template <int K>
-__device__ __forceinline__ void block_sums(double (&v)[K], double *sh) {
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__device__ __forceinline__ void wave_partials(const double (&v)[K], double *red, int buf) {
+    const int w = threadIdx.x >> 6;
+    double *sh = red + buf * (4 * kMaxWaves);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const double s = wave_sum(v[c]);
         if ((threadIdx.x & 63) == 0) sh[c * kMaxWaves + w] = s;
     }
-    __syncthreads();
+}
+template <int K>
+__device__ __forceinline__ void read_partials(double (&v)[K], const double *red, int &buf) {
+    const int nw = blockDim.x >> 6;
+    const double *sh = red + buf * (4 * kMaxWaves);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         double s = 0.0;
         for (int q = 0; q < nw; ++q) s = s + sh[c * kMaxWaves + q];
         v[c] = s;
     }
+    buf ^= 1;
+}
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double *red, int &buf) {
+    wave_partials<K>(v, red, buf);
     __syncthreads();
+    read_partials<K>(v, red, buf);
 }
 
 __device__ __forceinline__ double rsqrt_refined(double x) {
@@ -88,17 +103,42 @@ struct LamA {
     double x, y, z;
 };
 
+// LDS of one division workgroup.  Between kicks, pos / la hold the j-bodies
+// (positions + mass, adjoint weights); right after a j-loop they are reused
+// for the per-thread partial sums of that loop.
 struct AdjShared {
-    d4 pos[kAdjMaxN];      // r_j and m_j
-    LamA la[kAdjMaxN];     // adjoint weights w_j = dt * lambda_v,j of a reverse kick
-    double red[4 * kMaxWaves];
+    d4 pos[kAdjMaxN];
+    LamA la[kAdjMaxN];
+    double red[2 * 4 * kMaxWaves];
 };
 
-// Acceleration (with G) and phi of body i at r from the positions in LDS.
-__device__ __forceinline__ void accel(const AdjShared &S, int n, int i, const d4 &r, double G, double &ax,
-                                      double &ay, double &az, double &ph) {
+// Thread layout: T = d.tpb threads per body; thread (b, q) owns body b and the
+// q-th of T contiguous chunks of the j-range.  Per-body state is replicated in
+// the T threads (they compute identical values); sums over bodies take the
+// q = 0 threads only.
+struct Lay {
+    int b, q, T;
+    bool live, lead;
+    int jb, je;
+};
+__device__ __forceinline__ Lay layout(const AdjDev &d) {
+    Lay L;
+    L.T = d.tpb;
+    L.b = (int)threadIdx.x / L.T;
+    L.q = (int)threadIdx.x - L.b * L.T;
+    L.live = L.b < d.n;
+    L.lead = L.live && L.q == 0;
+    const int c = (d.n + L.T - 1) / L.T;
+    L.jb = min(d.n, L.q * c);
+    L.je = min(d.n, L.jb + c);
+    return L;
+}
+
+// Partial acceleration (without G) and phi of body i over j in [jb, je).
+__device__ __forceinline__ void accel_part(const AdjShared &S, int jb, int je, int i, const d4 &r, double &ax,
+                                           double &ay, double &az, double &ph) {
     ax = ay = az = ph = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = jb; j < je; ++j) {
         const d4 pj = S.pos[j];
         const double dx = pj.x - r.x, dy = pj.y - r.y, dz = pj.z - r.z;
         double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
@@ -113,18 +153,15 @@ __device__ __forceinline__ void accel(const AdjShared &S, int n, int i, const d4
         ay = fma(s, dy, ay);
         az = fma(s, dz, az);
     }
-    ax = G * ax;
-    ay = G * ay;
-    az = G * az;
 }
 
-// Forward acceleration and the transposed-Jacobian product of body i in one
-// pass over j: a_i and h_i = G sum_j M(d_ij) (m_i w_j - m_j w_i).
-__device__ __forceinline__ void accel_hvp(const AdjShared &S, int n, int i, const d4 &r, double mi, const LamA &wi,
-                                          double G, double &ax, double &ay, double &az, double &hx, double &hy,
-                                          double &hz) {
+// Partial acceleration (without G) and transposed-Jacobian product
+// sum_j M(d_ij) (m_i w_j - m_j w_i) (without G) of body i over j in [jb, je).
+__device__ __forceinline__ void accel_hvp_part(const AdjShared &S, int jb, int je, int i, const d4 &r, double mi,
+                                               const LamA &wi, double &ax, double &ay, double &az, double &hx,
+                                               double &hy, double &hz) {
     ax = ay = az = hx = hy = hz = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = jb; j < je; ++j) {
         const d4 pj = S.pos[j];
         const LamA wj = S.la[j];
         const double dx = pj.x - r.x, dy = pj.y - r.y, dz = pj.z - r.z;
@@ -139,8 +176,7 @@ __device__ __forceinline__ void accel_hvp(const AdjShared &S, int n, int i, cons
         ax = fma(s, dx, ax);
         ay = fma(s, dy, ay);
         az = fma(s, dz, az);
-        // q = m_i w_j - m_j w_i (zero for the self pair since mj = 0 and w_i enters only with mj)
-        const double m_i = self ? 0.0 : mi;
+        const double m_i = self ? 0.0 : mi;   // the self pair contributes nothing
         const double qx = m_i * wj.x - mj * wi.x, qy = m_i * wj.y - mj * wi.y, qz = m_i * wj.z - mj * wi.z;
         const double dq = fma(dz, qz, fma(dy, qy, dx * qx));
         const double c = 3.0 * dq * y2;   // 3 (d . q) / |d|^2
@@ -148,32 +184,44 @@ __device__ __forceinline__ void accel_hvp(const AdjShared &S, int n, int i, cons
         hy = fma(y3, qy - c * dy, hy);
         hz = fma(y3, qz - c * dz, hz);
     }
-    ax = G * ax;
-    ay = G * ay;
-    az = G * az;
-    hx = G * hx;
-    hy = G * hy;
-    hz = G * hz;
 }
 
+// Sum the T partials of each body in chunk order (identical in the T threads).
+// The barrier before the writes ends every thread's reads of pos / la.
+__device__ __forceinline__ void sum_parts(AdjShared &S, const Lay &L, int n, double &ax, double &ay, double &az,
+                                          double &ph) {
+    if (L.T == 1) return;
+    __syncthreads();
+    if (L.live) S.pos[L.q * n + L.b] = d4{ax, ay, az, ph};
+    __syncthreads();
+    if (L.live) {
+        d4 t = S.pos[L.b];
+        for (int q = 1; q < L.T; ++q) {
+            const d4 u = S.pos[q * n + L.b];
+            t = d4{t.x + u.x, t.y + u.y, t.z + u.z, t.w + u.w};
+        }
+        ax = t.x; ay = t.y; az = t.z; ph = t.w;
+    }
+}
 // B = U(r0) - T(v0) for the state in (Yr, Yv); one workgroup.
 __global__ __launch_bounds__(kAdjMaxN) void k_adj_init(AdjDev d, const d4 *Yr, const d4 *Yv, double *B) {
     __shared__ AdjShared S;
-    const int i = threadIdx.x, n = d.n;
-    const bool live = i < n;
-    const double mi = live ? d.m[i] : 0.0;
-    const d4 r = live ? Yr[i] : d4{0.0, 0.0, 0.0, 0.0}, v = live ? Yv[i] : d4{0.0, 0.0, 0.0, 0.0};
-    if (live) S.pos[i] = d4{r.x, r.y, r.z, mi};
-    double s4[4] = {mi, mi * v.x, mi * v.y, mi * v.z};
-    block_sums<4>(s4, S.red);   // barrier also publishes pos
+    const Lay L = layout(d);
+    const double mi = L.live ? d.m[L.b] : 0.0;
+    const double ml = L.lead ? mi : 0.0;
+    const d4 r = L.live ? Yr[L.b] : d4{0.0, 0.0, 0.0, 0.0}, v = L.live ? Yv[L.b] : d4{0.0, 0.0, 0.0, 0.0};
+    int rb = 0;
+    if (L.lead) S.pos[L.b] = d4{r.x, r.y, r.z, mi};
+    double s4[4] = {ml, ml * v.x, ml * v.y, ml * v.z};
+    block_sums<4>(s4, S.red, rb);   // the barrier also publishes pos
     const double M = s4[0];
     const double bx = s4[1] / M, by = s4[2] / M, bz = s4[3] / M;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-    if (live) accel(S, n, i, r, d.G, ax, ay, az, ph);
+    if (L.live) accel_part(S, L.jb, L.je, L.b, r, ax, ay, az, ph);
     const double cx = v.x - bx, cy = v.y - by, cz = v.z - bz;
-    double s2[2] = {mi * ph, mi * ((cx * cx + cy * cy) + cz * cz)};
-    block_sums<2>(s2, S.red);
-    if (i == 0) *B = 0.5 * d.G * s2[0] - 0.5 * s2[1];
+    double s2[2] = {L.live ? mi * ph : 0.0, ml * ((cx * cx + cy * cy) + cz * cz)};
+    block_sums<2>(s2, S.red, rb);
+    if (threadIdx.x == 0) *B = 0.5 * d.G * s2[0] - 0.5 * s2[1];
 }
 
 // One division per workgroup (blockIdx.x = k): the leapfrog with n_k = 2(k+1)
@@ -184,33 +232,35 @@ template <bool STORE>
 __global__ __launch_bounds__(kAdjMaxN) void k_adj_fwd(AdjDev d, const d4 *Yr, const d4 *Yv, const double *Yt,
                                                       double H) {
     __shared__ AdjShared S;
-    const int k = blockIdx.x, i = threadIdx.x, n = d.n;
-    const bool live = i < n;
+    const Lay L = layout(d);
+    const int k = blockIdx.x, n = d.n;
     const int nsub = 2 * (k + 1);
     const int kb = k * (k + 1), db = k * (k + 1) + k, ob = 2 * k * (k + 1) + k;
     const double h = H / (double)nsub;
-    const double mi = live ? d.m[i] : 0.0;
-    d4 r = live ? Yr[i] : d4{0.0, 0.0, 0.0, 0.0}, v = live ? Yv[i] : d4{0.0, 0.0, 0.0, 0.0};
+    const double mi = L.live ? d.m[L.b] : 0.0;
+    const double ml = L.lead ? mi : 0.0;
+    d4 r = L.live ? Yr[L.b] : d4{0.0, 0.0, 0.0, 0.0}, v = L.live ? Yv[L.b] : d4{0.0, 0.0, 0.0, 0.0};
     double t = *Yt;
     const double B = *d.B;
-    double sm[1] = {mi};
-    block_sums<1>(sm, S.red);
-    const double M = sm[0];
+    int rb = 0;
+    // total mass and COM velocity of the start state: kicks conserve momentum
+    // exactly in the map being evaluated, so v_cm is constant over the division
+    double s4[4] = {ml, ml * v.x, ml * v.y, ml * v.z};
+    block_sums<4>(s4, S.red, rb);
+    const double M = s4[0];
+    const double bx = s4[1] / M, by = s4[2] / M, bz = s4[3] / M;
     for (int s = 0; s <= nsub; ++s) {
         // drift
         {
             const double ds = (s == 0 || s == nsub) ? 0.5 * h : h;
-            if (STORE && live) d.vst[(size_t)(db + s) * n + i] = v;
-            double s3[3] = {mi * v.x, mi * v.y, mi * v.z};
-            block_sums<3>(s3, S.red);
-            const double bx = s3[0] / M, by = s3[1] / M, bz = s3[2] / M;
+            if (STORE && L.lead) d.vst[(size_t)(db + s) * n + L.b] = v;
             const double cx = v.x - bx, cy = v.y - by, cz = v.z - bz;
-            double s1[1] = {mi * ((cx * cx + cy * cy) + cz * cz)};
-            block_sums<1>(s1, S.red);
+            double s1[1] = {ml * ((cx * cx + cy * cy) + cz * cz)};
+            block_sums<1>(s1, S.red, rb);
             const double T = 0.5 * s1[0];
             const double g = d.alpha * (T + B) + d.gamma;
             const double dt = ds / g;
-            if (STORE && i == 0) {
+            if (STORE && threadIdx.x == 0) {
                 double *o = d.sc + (size_t)(ob + 2 * s) * kAdjOpScal;
                 o[0] = dt; o[1] = g; o[2] = T; o[3] = bx; o[4] = by; o[5] = bz;
             }
@@ -218,30 +268,43 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_fwd(AdjDev d, const d4 *Yr, co
             t = t + dt;
         }
         if (s == nsub) break;
-        // kick
+        // kick: publish positions; j-loop; U from the per-thread partials of
+        // m_i phi_i; the acceleration partials of the T threads of a body
+        // meet in la (unused by the forward pass)
         {
-            if (STORE && live) d.rst[(size_t)(kb + s) * n + i] = r;
-            if (live) S.pos[i] = d4{r.x, r.y, r.z, mi};
+            if (STORE && L.lead) d.rst[(size_t)(kb + s) * n + L.b] = r;
+            if (L.lead) S.pos[L.b] = d4{r.x, r.y, r.z, mi};
             __syncthreads();
             double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-            if (live) accel(S, n, i, r, d.G, ax, ay, az, ph);
-            double su[1] = {mi * ph};
-            block_sums<1>(su, S.red);   // its barriers also end the reads of pos
+            if (L.live) accel_part(S, L.jb, L.je, L.b, r, ax, ay, az, ph);
+            double su[1] = {L.live ? mi * ph : 0.0};
+            wave_partials<1>(su, S.red, rb);
+            if (L.T > 1 && L.live) S.la[L.q * n + L.b] = LamA{ax, ay, az};
+            __syncthreads();
+            read_partials<1>(su, S.red, rb);
+            if (L.T > 1 && L.live) {
+                LamA a = S.la[L.b];
+                for (int q = 1; q < L.T; ++q) {
+                    const LamA u = S.la[q * n + L.b];
+                    a = LamA{a.x + u.x, a.y + u.y, a.z + u.z};
+                }
+                ax = a.x; ay = a.y; az = a.z;
+            }
             const double U = 0.5 * d.G * su[0];
             const double g = d.alpha * U + d.gamma;
             const double dt = h / g;
-            if (STORE && i == 0) {
+            if (STORE && threadIdx.x == 0) {
                 double *o = d.sc + (size_t)(ob + 2 * s + 1) * kAdjOpScal;
                 o[0] = dt; o[1] = g; o[2] = U;
             }
-            v = d4{v.x + dt * ax, v.y + dt * ay, v.z + dt * az, 0.0};
+            v = d4{v.x + dt * (d.G * ax), v.y + dt * (d.G * ay), v.z + dt * (d.G * az), 0.0};
         }
     }
-    if (live) {
-        d.Er[(size_t)k * n + i] = r;
-        d.Ev[(size_t)k * n + i] = v;
+    if (L.lead) {
+        d.Er[(size_t)k * n + L.b] = r;
+        d.Ev[(size_t)k * n + L.b] = v;
     }
-    if (i == 0) d.Et[k] = t;
+    if (threadIdx.x == 0) d.Et[k] = t;
 }
 
 // Y' = Y + sum_k c_k (L_k - Y) into (Or, Ov, Ot) (may alias Y).
@@ -272,34 +335,35 @@ __global__ void k_adj_combine(AdjDev d, const d4 *Yr, const d4 *Yv, const double
 // start state goes to Sr[k], Sv[k], St[k] and the B part to SB[k].
 __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
     __shared__ AdjShared S;
-    const int k = blockIdx.x, i = threadIdx.x, n = d.n;
-    const bool live = i < n;
+    const Lay L = layout(d);
+    const int k = blockIdx.x, n = d.n;
     const int nsub = 2 * (k + 1);
     const int kb = k * (k + 1), db = k * (k + 1) + k, ob = 2 * k * (k + 1) + k;
-    const double mi = live ? d.m[i] : 0.0;
+    const double mi = L.live ? d.m[L.b] : 0.0;
     const double ck = d.c[k];
     const double al = d.alpha;
     d4 lr{0.0, 0.0, 0.0, 0.0}, lv{0.0, 0.0, 0.0, 0.0};
-    if (live) {
-        const d4 a = d.Lr[i], b = d.Lv[i];
+    if (L.live) {
+        const d4 a = d.Lr[L.b], b = d.Lv[L.b];
         lr = d4{ck * a.x, ck * a.y, ck * a.z, 0.0};
         lv = d4{ck * b.x, ck * b.y, ck * b.z, 0.0};
     }
     const double lt = ck * *d.Lt;
     double lB = 0.0;
+    int rb = 0;
     for (int s = nsub; s >= 0; --s) {
         // reverse drift s: r' = r + dt v, t' = t + dt, dt = ds / (alpha (T(v) + B) + gamma)
         {
             const double *o = d.sc + (size_t)(ob + 2 * s) * kAdjOpScal;
             const double dt = o[0], g = o[1];
             const double bx = o[3], by = o[4], bz = o[5];
-            const d4 v = live ? d.vst[(size_t)(db + s) * n + i] : d4{0.0, 0.0, 0.0, 0.0};
-            double s1[1] = {(lr.x * v.x + lr.y * v.y) + lr.z * v.z};
-            block_sums<1>(s1, S.red);
+            const d4 v = L.live ? d.vst[(size_t)(db + s) * n + L.b] : d4{0.0, 0.0, 0.0, 0.0};
+            double s1[1] = {L.lead ? (lr.x * v.x + lr.y * v.y) + lr.z * v.z : 0.0};
+            block_sums<1>(s1, S.red, rb);
             const double ldt = s1[0] + lt;
             const double lT = ldt * (-(dt / g) * al);
             lB = lB + lT;
-            if (live) {
+            if (L.live) {
                 lv = d4{lv.x + dt * lr.x + lT * (mi * (v.x - bx)), lv.y + dt * lr.y + lT * (mi * (v.y - by)),
                         lv.z + dt * lr.z + lT * (mi * (v.z - bz)), 0.0};
             }
@@ -309,28 +373,52 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
         {
             const double *o = d.sc + (size_t)(ob + 2 * (s - 1) + 1) * kAdjOpScal;
             const double dt = o[0], g = o[1];
-            const d4 r = live ? d.rst[(size_t)(kb + s - 1) * n + i] : d4{0.0, 0.0, 0.0, 0.0};
+            const d4 r = L.live ? d.rst[(size_t)(kb + s - 1) * n + L.b] : d4{0.0, 0.0, 0.0, 0.0};
             const LamA wi{dt * lv.x, dt * lv.y, dt * lv.z};
-            if (live) {
-                S.pos[i] = d4{r.x, r.y, r.z, mi};
-                S.la[i] = wi;
+            if (L.lead) {
+                S.pos[L.b] = d4{r.x, r.y, r.z, mi};
+                S.la[L.b] = wi;
             }
             __syncthreads();
             double ax = 0.0, ay = 0.0, az = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
-            if (live) accel_hvp(S, n, i, r, mi, wi, d.G, ax, ay, az, hx, hy, hz);
-            double s1[1] = {(lv.x * ax + lv.y * ay) + lv.z * az};
-            block_sums<1>(s1, S.red);   // its barriers also end the reads of pos / la
+            if (L.live) accel_hvp_part(S, L.jb, L.je, L.b, r, mi, wi, ax, ay, az, hx, hy, hz);
+            // lambda_dt = sum_i lambda_v,i . a_i, from the per-thread partials
+            double s1[1] = {L.live ? (lv.x * (d.G * ax) + lv.y * (d.G * ay)) + lv.z * (d.G * az) : 0.0};
+            wave_partials<1>(s1, S.red, rb);
+            if (L.T > 1) {
+                __syncthreads();   // every j-loop has finished reading pos / la
+                if (L.live) {
+                    S.pos[L.q * n + L.b] = d4{ax, ay, az, 0.0};
+                    S.la[L.q * n + L.b] = LamA{hx, hy, hz};
+                }
+            }
+            __syncthreads();
+            read_partials<1>(s1, S.red, rb);
+            if (L.T > 1 && L.live) {
+                d4 a = S.pos[L.b];
+                LamA hh = S.la[L.b];
+                for (int q = 1; q < L.T; ++q) {
+                    const d4 u = S.pos[q * n + L.b];
+                    const LamA w = S.la[q * n + L.b];
+                    a = d4{a.x + u.x, a.y + u.y, a.z + u.z, 0.0};
+                    hh = LamA{hh.x + w.x, hh.y + w.y, hh.z + w.z};
+                }
+                ax = a.x; ay = a.y; az = a.z;
+                hx = hh.x; hy = hh.y; hz = hh.z;
+            }
+            ax = d.G * ax; ay = d.G * ay; az = d.G * az;
+            hx = d.G * hx; hy = d.G * hy; hz = d.G * hz;
             const double lU = s1[0] * (-(dt / g) * al);
-            if (live) {
+            if (L.live) {
                 lr = d4{lr.x + lU * (mi * ax) + hx, lr.y + lU * (mi * ay) + hy, lr.z + lU * (mi * az) + hz, 0.0};
             }
         }
     }
-    if (live) {
-        d.Sr[(size_t)k * n + i] = lr;
-        d.Sv[(size_t)k * n + i] = lv;
+    if (L.lead) {
+        d.Sr[(size_t)k * n + L.b] = lr;
+        d.Sv[(size_t)k * n + L.b] = lv;
     }
-    if (i == 0) {
+    if (threadIdx.x == 0) {
         d.St[k] = lt;
         d.SB[k] = lB;
     }
@@ -370,26 +458,30 @@ __global__ void k_adj_combine_rev(AdjDev d) {
 __global__ __launch_bounds__(kAdjMaxN) void k_adj_finish(AdjDev d, const d4 *Yr, const d4 *Yv, double *gx,
                                                          double *gv) {
     __shared__ AdjShared S;
-    const int i = threadIdx.x, n = d.n;
-    const bool live = i < n;
-    const double mi = live ? d.m[i] : 0.0;
-    const d4 r = live ? Yr[i] : d4{0.0, 0.0, 0.0, 0.0}, v = live ? Yv[i] : d4{0.0, 0.0, 0.0, 0.0};
-    if (live) S.pos[i] = d4{r.x, r.y, r.z, mi};
-    double s4[4] = {mi, mi * v.x, mi * v.y, mi * v.z};
-    block_sums<4>(s4, S.red);
+    const Lay L = layout(d);
+    const int n = d.n;
+    const double mi = L.live ? d.m[L.b] : 0.0;
+    const double ml = L.lead ? mi : 0.0;
+    const d4 r = L.live ? Yr[L.b] : d4{0.0, 0.0, 0.0, 0.0}, v = L.live ? Yv[L.b] : d4{0.0, 0.0, 0.0, 0.0};
+    int rb = 0;
+    if (L.lead) S.pos[L.b] = d4{r.x, r.y, r.z, mi};
+    double s4[4] = {ml, ml * v.x, ml * v.y, ml * v.z};
+    block_sums<4>(s4, S.red, rb);   // the barrier also publishes pos
     const double M = s4[0];
     const double bx = s4[1] / M, by = s4[2] / M, bz = s4[3] / M;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
-    if (live) accel(S, n, i, r, d.G, ax, ay, az, ph);
+    if (L.live) accel_part(S, L.jb, L.je, L.b, r, ax, ay, az, ph);
+    sum_parts(S, L, n, ax, ay, az, ph);
+    ax = d.G * ax; ay = d.G * ay; az = d.G * az;
     const double lB = *d.LB;
-    if (live) {
-        const d4 a = d.Lr[i], b = d.Lv[i];
-        gx[3 * i] = a.x + lB * (mi * ax);
-        gx[3 * i + 1] = a.y + lB * (mi * ay);
-        gx[3 * i + 2] = a.z + lB * (mi * az);
-        gv[3 * i] = b.x - lB * (mi * (v.x - bx));
-        gv[3 * i + 1] = b.y - lB * (mi * (v.y - by));
-        gv[3 * i + 2] = b.z - lB * (mi * (v.z - bz));
+    if (L.lead) {
+        const d4 a = d.Lr[L.b], b = d.Lv[L.b];
+        gx[3 * L.b] = a.x + lB * (mi * ax);
+        gx[3 * L.b + 1] = a.y + lB * (mi * ay);
+        gx[3 * L.b + 2] = a.z + lB * (mi * az);
+        gv[3 * L.b] = b.x - lB * (mi * (v.x - bx));
+        gv[3 * L.b + 1] = b.y - lB * (mi * (v.y - by));
+        gv[3 * L.b + 2] = b.z - lB * (mi * (v.z - bz));
     }
 }
 
@@ -445,28 +537,28 @@ __global__ void k_adj_copy(int n, const d4 *a, const d4 *b, const double *t, d4 
     if (i == 0) *ot = *t;
 }
 
-int threads_for(int n) { return ((n + 63) / 64) * 64; }
+int threads_for(const AdjDev &d) { return ((d.n * d.tpb + 63) / 64) * 64; }
 
 }  // namespace
 
 void launch_adj_init(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv) {
-    k_adj_init<<<1, threads_for(d.n), 0, s>>>(d, Yr, Yv, d.B);
+    k_adj_init<<<1, threads_for(d), 0, s>>>(d, Yr, Yv, d.B);
 }
 void launch_adj_fwd(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, const double *Yt, double H,
                     bool store) {
-    if (store) k_adj_fwd<true><<<d.kf, threads_for(d.n), 0, s>>>(d, Yr, Yv, Yt, H);
-    else k_adj_fwd<false><<<d.kf, threads_for(d.n), 0, s>>>(d, Yr, Yv, Yt, H);
+    if (store) k_adj_fwd<true><<<d.kf, threads_for(d), 0, s>>>(d, Yr, Yv, Yt, H);
+    else k_adj_fwd<false><<<d.kf, threads_for(d), 0, s>>>(d, Yr, Yv, Yt, H);
 }
 void launch_adj_combine(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, const double *Yt, d4 *Or,
                         d4 *Ov, double *Ot) {
     k_adj_combine<<<(d.n + 255) / 256, 256, 0, s>>>(d, Yr, Yv, Yt, Or, Ov, Ot);
 }
-void launch_adj_rev(const AdjDev &d, hipStream_t s) { k_adj_rev<<<d.kf, threads_for(d.n), 0, s>>>(d); }
+void launch_adj_rev(const AdjDev &d, hipStream_t s) { k_adj_rev<<<d.kf, threads_for(d), 0, s>>>(d); }
 void launch_adj_combine_rev(const AdjDev &d, hipStream_t s) {
     k_adj_combine_rev<<<(d.n + 255) / 256, 256, 0, s>>>(d);
 }
 void launch_adj_finish(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, double *gx, double *gv) {
-    k_adj_finish<<<1, threads_for(d.n), 0, s>>>(d, Yr, Yv, gx, gv);
+    k_adj_finish<<<1, threads_for(d), 0, s>>>(d, Yr, Yv, gx, gv);
 }
 void launch_force_hvp(hipStream_t s, int n, double G, const double *m, const double *x, const double *w,
                       double *out) {

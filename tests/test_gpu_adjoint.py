@@ -92,7 +92,10 @@ def test_replay_matches_oracle_replay(ctx, orc, M, case):
     R = np.abs(xo - (m[:, None] * xo).sum(0) / m.sum()).max()
     Vs = np.abs(vo - (m[:, None] * vo).sum(0) / m.sum()).max()
     assert np.abs(xg - xo).max() <= 1e-10 * R and np.abs(vg - vo).max() <= 1e-10 * Vs
-    assert abs(tg - to) <= 1e-13 * abs(to)
+    # t sums the extrapolated time increments; the extrapolation weights add
+    # up to |c| ~ 1.2e2 in magnitude, so each step's rounding (~1e-16 of dt)
+    # reaches ~1e-14 of it: 1e-12 of t over these records
+    assert abs(tg - to) <= 1e-12 * abs(to)
 
 
 def _adjoint_vs_tlm(ctx, orc, m, x, v, H, nd, seed, ce=50):
@@ -199,7 +202,7 @@ def test_autograd_function(ctx, orc, M):
     rng = np.random.default_rng(8)
     h = 1e-6
     gE0 = torch.autograd.grad(energy(x0, v0), (x0, v0))
-    scale = float(torch.cat([gE0[0].flatten(), gE0[1].flatten()]).norm()) / abs(float(energy(x0, v0)))
+    scale = float(torch.cat([gE0[0].flatten(), gE0[1].flatten()]).norm()) / abs(float(energy(x0, v0).detach()))
     for q in range(3):
         dx, dv = rng.standard_normal((2, n, 3))
 
