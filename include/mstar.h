@@ -114,7 +114,11 @@ const char *mstar_last_error(const mstar_ctx *ctx);
  * at t0 and overwritten with the state at stats->t_reached.  m [n] > 0.
  * Errors: MSTAR_E_INVAL (n < 2, bad masses or parameters), MSTAR_E_NONFINITE,
  * MSTAR_E_COINCIDENT, MSTAR_E_NOCONV, MSTAR_E_MAXSTEPS, MSTAR_E_UNSUPPORTED
- * (beta != 0 or n_d > 2), device errors; warning MSTAR_W_TIME_TOL. */
+ * (n_d > 2), device errors; warning MSTAR_W_TIME_TOL.  With beta != 0 the
+ * time transformation includes the TTL function Omega of Sec. 2.1 over the
+ * bodies with m <= omega_mass_max, and its auxiliary variable w starts at
+ * Omega(t0); alpha = gamma = 0 then needs at least two such bodies
+ * (MSTAR_E_INVAL otherwise). */
 int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
                     double *x, double *v, double t0, double t_end, mstar_stats *stats);
 
@@ -135,9 +139,14 @@ int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, 
  * close-pair rule of Sec. 3.4): acc[n][3] = G sum_j m_j d_ij/|d_ij|^3 and
  * *U = G sum_{i<j} m_i m_j/|d_ij|, where d_ij is the MST path sum of the edge
  * vectors X for pairs within params->n_d tree edges and rho_j - rho_i
- * otherwise.  rho [n][3] are positions in any frame consistent with X. */
+ * otherwise.  rho [n][3] are positions in any frame consistent with X.
+ * Omega and dOmega may be NULL.  With params->beta != 0 they receive the TTL
+ * function Omega = G sum_{i<j} mo_i mo_j/|d_ij| and its gradient
+ * dOmega[i] = G mo_i sum_j mo_j d_ij/|d_ij|^3, where mo_i = m_i if
+ * m_i <= omega_mass_max, else 0.  With beta == 0 they receive zeros. */
 int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
-                const double *rho, const int32_t *parent, const double *X, double *acc, double *U);
+                const double *rho, const int32_t *parent, const double *X, double *acc, double *U,
+                double *Omega, double *dOmega);
 
 /* One leapfrog division over the fictitious interval H with nsub substeps,
  * D(H/2n)[K(H/n)D(H/n)]^(n-1)K(H/n)D(H/2n) (Sec. 2.3), on the MST state

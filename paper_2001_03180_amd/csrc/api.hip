@@ -149,7 +149,7 @@ int ensure(mstar_ctx *ctx, int n) {
     A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.rounds, 1) A(d.comp, N) A(d.ecomp_tmp, N)
     A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.done, 1) A(d.ncomp, 1)
     A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
-    A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N)
+    A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N) A(d.mo, N) A(d.dOm0, N)
     A(ctx->xin, 3 * N) A(ctx->vin, 3 * N) A(ctx->xout, 3 * N)
 #undef A
     HIPCK(hipMemsetAsync(d.dX, 0, sizeof(d4) * kMaxDiv * N, ctx->stream));
@@ -166,6 +166,26 @@ int ensure(mstar_ctx *ctx, int n) {
     d.nfb = (n + 64 * kForceIPL - 1) / (64 * kForceIPL);
     return MSTAR_OK;
 }
+
+// Buffers of the TTL function Omega, allocated on the first call with
+// beta != 0 (they double the force-partial memory) at the current capacity.
+int ensure_ttl(mstar_ctx *ctx) {
+    Dev &d = ctx->d;
+    if (d.opart) return MSTAR_OK;
+    const size_t N = (size_t)ctx->cap_n;
+    const size_t nib = (N + 63) / 64, nkwg4 = (N + kWG / 4 - 1) / (kWG / 4);
+    int rc;
+    if ((rc = dalloc(ctx, &d.opart, (size_t)kMaxDiv * kNsplitMax * N)) ||
+        (rc = dalloc(ctx, &d.Opart, (size_t)kMaxDiv * nib * kNsplitMax)) ||
+        (rc = dalloc(ctx, &d.wpart, (size_t)kMaxDiv * nkwg4))) {
+        d.opart = nullptr; d.Opart = nullptr; d.wpart = nullptr;
+        return rc;
+    }
+    return MSTAR_OK;
+}
+
+Ttl ttl_of(const mstar_params *p) { return Ttl{p->alpha, p->beta, p->gamma}; }
+bool ttl_on(const mstar_params *p) { return p->beta != 0.0; }
 
 constexpr int kBase = kBaseSlot;     // slot of the start state
 constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
@@ -205,10 +225,11 @@ int check_params(mstar_ctx *ctx, const mstar_params *p) {
     if (p->k_fix < 2 || p->k_fix > 16) return fail(ctx, MSTAR_E_INVAL, "params: k_fix must be in [2, 16]");
     if (p->n_d < 0) return fail(ctx, MSTAR_E_INVAL, "params: n_d must be >= 0");
     if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: n_d > 2 is not implemented on the GPU");
-    if (p->beta != 0.0) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: beta != 0 (TTL Omega) is not implemented on the GPU");
-    if (!std::isfinite(p->alpha) || !std::isfinite(p->gamma) || p->alpha < 0.0 || p->gamma < 0.0 ||
-        (p->alpha == 0.0 && p->gamma == 0.0))
-        return fail(ctx, MSTAR_E_INVAL, "params: need alpha, gamma >= 0, not both zero");
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || !std::isfinite(p->gamma) || p->alpha < 0.0 ||
+        p->beta < 0.0 || p->gamma < 0.0 || (p->alpha == 0.0 && p->beta == 0.0 && p->gamma == 0.0))
+        return fail(ctx, MSTAR_E_INVAL, "params: need alpha, beta, gamma >= 0, not all zero");
+    if (p->beta != 0.0 && !std::isfinite(p->omega_mass_max))
+        return fail(ctx, MSTAR_E_INVAL, "params: omega_mass_max must be finite");
     if (!(p->a_gbs > 0.0) || !(p->f_min > 0.0) || !(p->f_max >= p->f_min) || !(p->q_first > 0.0) ||
         !(p->t_tol >= 0.0) || p->max_steps < 1 || p->max_halvings < 0 || p->max_time_iter < 0 ||
         p->rebuild_every < 0 || !(p->h_init >= 0.0))
@@ -243,7 +264,11 @@ bool finite_host(const double *a, size_t k) {
 }
 
 // Validate masses / positions / velocities (host copies) and copy masses.
-int load_bodies(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x, const double *v) {
+// With TTL (p->beta != 0) also the Omega masses mo_i = m_i if m_i <=
+// omega_mass_max else 0; a time transformation that rests on Omega alone
+// needs at least two such bodies.
+int load_bodies(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x, const double *v,
+                const mstar_params *p) {
     std::vector<double> hm((size_t)n), hx, hv;
     if (is_dev(flags)) {
         HIPCK(hipMemcpy(hm.data(), m, sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -259,6 +284,19 @@ int load_bodies(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, cons
     if ((x && !finite_host(hx.data(), hx.size())) || (v && !finite_host(hv.data(), hv.size())))
         return fail(ctx, MSTAR_E_NONFINITE, "non-finite position or velocity");
     HIPCK(hipMemcpyAsync(ctx->d.m, hm.data(), sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    if (p && ttl_on(p)) {
+        std::vector<double> mo((size_t)n);
+        int64_t light = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            mo[i] = hm[i] <= p->omega_mass_max ? hm[i] : 0.0;
+            light += mo[i] > 0.0;
+        }
+        if (light < 2 && p->alpha == 0.0 && p->gamma == 0.0)
+            return fail(ctx, MSTAR_E_INVAL, "TTL with alpha = gamma = 0 needs two bodies with m <= omega_mass_max");
+        int rc = ensure_ttl(ctx);
+        if (rc) return rc;
+        HIPCK(hipMemcpyAsync(ctx->d.mo, mo.data(), sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    }
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MSTAR_OK;
 }
@@ -287,7 +325,7 @@ int load_tree(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent) 
     return MSTAR_OK;
 }
 
-int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit) {
+int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit, bool om) {
     if (ctx->prof) {
         if (ctx->ev_used == ctx->ev.size()) {
             hipEvent_t a, b;
@@ -297,12 +335,12 @@ int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit) {
         }
         auto &e = ctx->ev[ctx->ev_used++];
         HIPCK(hipEventRecord(e.first, ctx->stream));
-        launch_force(ctx->d, ctx->stream, sl, nd, nsplit);
+        launch_force(ctx->d, ctx->stream, sl, nd, nsplit, om);
         HIPCK(hipEventRecord(e.second, ctx->stream));
         ctx->prof_launches++;
         ctx->prof_pairs += (double)sl.nact * (double)ctx->d.n * (double)(ctx->d.n - 1);
     } else {
-        launch_force(ctx->d, ctx->stream, sl, nd, nsplit);
+        launch_force(ctx->d, ctx->stream, sl, nd, nsplit, om);
     }
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -333,9 +371,10 @@ int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool wi
         sl.nact = 1;
         sl.slot[0] = kBase;
         const int ns = nsplit_for(d, 1, force_cap(ctx, p->n_d));
-        int rc = prof_force(ctx, sl, p->n_d, ns);
+        int rc = prof_force(ctx, sl, p->n_d, ns, ttl_on(p));
         if (rc) return rc;
-        launch_reduce_start(d, ctx->stream, kBase, p->G, force_parts(ns, p->n_d), d.a0, &d.ctl->U0);
+        launch_reduce_start(d, ctx->stream, kBase, p->G, force_parts(ns, p->n_d), d.a0, &d.ctl->U0, ttl_on(p),
+                            ttl_on(p));
         if (nforce) ++*nforce;
     }
     HIPCK(hipGetLastError());
@@ -362,15 +401,15 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
                 dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 1; dr.first[dr.nact] = 0; dr.nact++;
             }
         }
-        if (dr.nact) launch_drift(d, ctx->stream, dr, p->alpha, p->gamma);
+        if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p));
         if (s > nmax) break;
         SlotList fk{};
         for (int k = 0; k < ndiv; ++k)
             if (nlist[k] >= s) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nlist[k]; fk.nact++; }
         const int ns = nsplit_for(d, fk.nact, force_cap(ctx, p->n_d));
-        int rc = prof_force(ctx, fk, p->n_d, ns);
+        int rc = prof_force(ctx, fk, p->n_d, ns, ttl_on(p));
         if (rc) return rc;
-        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, p->alpha, p->gamma);
+        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, ttl_of(p));
         if (nforce) *nforce += fk.nact;
     }
     HIPCK(hipGetLastError());
@@ -423,8 +462,9 @@ int rebuild(mstar_ctx *ctx, const mstar_params *p) {
     return MSTAR_OK;
 }
 
-int load_state(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent, const double *X, const double *V,
-               const double *scal) {
+int load_state(mstar_ctx *ctx, const mstar_params *p, int64_t n, const int32_t *parent, const double *X,
+               const double *V, const double *scal) {
+    const uint32_t flags = p->flags;
     int rc = load_tree(ctx, flags, n, parent);
     if (rc) return rc;
     const void *xd, *vd;
@@ -436,8 +476,8 @@ int load_state(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent,
     if (is_dev(flags)) HIPCK(hipMemcpy(hs, scal, sizeof hs, hipMemcpyDeviceToHost));
     else memcpy(hs, scal, sizeof hs);
     if (!finite_host(hs, 9)) return fail(ctx, MSTAR_E_NONFINITE, "non-finite scalars");
-    if (hs[2] != 0.0) return fail(ctx, MSTAR_E_UNSUPPORTED, "w != 0 needs beta != 0 (not implemented)");
-    launch_set_sys(ctx->d, ctx->stream, hs[0], hs[1], hs + 3, hs + 6, 1);
+    if (hs[2] != 0.0 && !ttl_on(p)) return fail(ctx, MSTAR_E_INVAL, "scal: w != 0 needs beta != 0");
+    launch_set_sys(ctx->d, ctx->stream, hs[0], hs[1], hs[2], hs + 3, hs + 6, 1);
     launch_levels_children(ctx->d, ctx->stream);
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -602,7 +642,7 @@ int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, 
     (void)hipSetDevice(ctx->device);
     int rc = ensure(ctx, (int)n);
     if (rc) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr, nullptr))) return rc;
     const void *xd;
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
     const Dev &d = ctx->d;
@@ -618,7 +658,7 @@ int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, 
 }
 
 int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *rho,
-                const int32_t *parent, const double *X, double *acc, double *U) {
+                const int32_t *parent, const double *X, double *acc, double *U, double *Omega, double *dOmega) {
     if (!ctx) return MSTAR_E_INVAL;
     int rc = check_params(ctx, params);
     if (rc) return rc;
@@ -627,7 +667,7 @@ int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const dou
     (void)hipSetDevice(ctx->device);
     const uint32_t flags = params->flags;
     if ((rc = ensure(ctx, (int)n))) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, rho, nullptr))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, rho, nullptr, params))) return rc;
     if ((rc = load_tree(ctx, flags, n, parent))) return rc;
     const Dev &d = ctx->d;
     const void *rd, *xd;
@@ -641,12 +681,21 @@ int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const dou
     sl.nact = 1;
     sl.slot[0] = kBase;
     const int ns = nsplit_for(d, 1, force_cap(ctx, params->n_d));
-    if ((rc = prof_force(ctx, sl, params->n_d, ns))) return rc;
-    launch_reduce_start(d, ctx->stream, kBase, params->G, force_parts(ns, params->n_d), d.a0, &d.ctl->U0);
+    const bool om = ttl_on(params);
+    if ((rc = prof_force(ctx, sl, params->n_d, ns, om))) return rc;
+    launch_reduce_start(d, ctx->stream, kBase, params->G, force_parts(ns, params->n_d), d.a0, &d.ctl->U0, om,
+                        false);
     launch_unpack3(ctx->stream, d.a0, ctx->xout, (int)n);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, acc, ctx->xout, sizeof(double) * 3 * n))) return rc;
     if ((rc = out_copy(ctx, flags, U, &d.ctl->U0, sizeof(double)))) return rc;
+    if (Omega && (rc = out_copy(ctx, flags, Omega, &d.ctl->Om0, sizeof(double)))) return rc;
+    if (dOmega) {
+        HIPCK(hipStreamSynchronize(ctx->stream));   // xin is reused below
+        if (om) launch_unpack3(ctx->stream, d.dOm0, ctx->xin, (int)n);
+        else HIPCK(hipMemsetAsync(ctx->xin, 0, sizeof(double) * 3 * n, ctx->stream));
+        if ((rc = out_copy(ctx, flags, dOmega, ctx->xin, sizeof(double) * 3 * n))) return rc;
+    }
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MSTAR_OK;
 }
@@ -662,10 +711,10 @@ int mstar_leapfrog(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     (void)hipSetDevice(ctx->device);
     const uint32_t flags = params->flags;
     if ((rc = ensure(ctx, (int)n))) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
-    if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr, params))) return rc;
+    if ((rc = load_state(ctx, params, n, parent, X, V, scal))) return rc;
     if ((rc = prepare_start(ctx, params, true, false, nullptr))) return rc;
-    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params));
     const int nl[1] = {nsub};
     if ((rc = run_divisions(ctx, params, nl, 1, nullptr))) return rc;
     launch_commit(ctx->d, ctx->stream, 0, 0);
@@ -683,14 +732,14 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     (void)hipSetDevice(ctx->device);
     const uint32_t flags = params->flags;
     if ((rc = ensure(ctx, (int)n))) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr))) return rc;
-    if ((rc = load_state(ctx, flags, n, parent, X, V, scal))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr, params))) return rc;
+    if ((rc = load_state(ctx, params, n, parent, X, V, scal))) return rc;
     if ((rc = prepare_start(ctx, params, true, true, nullptr))) return rc;
-    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, params->alpha, params->gamma);
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params));
     int nl[16];
     for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
     if ((rc = run_divisions(ctx, params, nl, params->k_fix, nullptr))) return rc;
-    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, params->alpha, params->gamma, kBase);
+    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, ttl_of(params), kBase);
     launch_control(ctx->d, ctx->stream, params->k_fix, params->eta, params->a_gbs, params->f_min, params->f_max);
     launch_commit(ctx->d, ctx->stream, 1, 0);
     HIPCK(hipGetLastError());
@@ -723,7 +772,7 @@ static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n,
     const uint32_t flags = params->flags;
     const mstar_params &p = *params;
     if ((rc = ensure(ctx, (int)n))) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, x, v))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, v, params))) return rc;
     const Dev &d = ctx->d;
     const void *xd, *vd;
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
@@ -732,14 +781,14 @@ static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n,
     launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
     if ((rc = build_mst(ctx, d.tsA, -1))) return rc;
     launch_tree_finish(d, ctx->stream);
-    launch_set_sys(d, ctx->stream, t0, 0.0, nullptr, nullptr, 0);
+    launch_set_sys(d, ctx->stream, t0, 0.0, 0.0, nullptr, nullptr, 0);
     launch_state_from_cartesian(d, ctx->stream, (const double *)xd, (const double *)vd);
     launch_check_coincident(d, ctx->stream);
     if ((rc = prepare_start(ctx, &p, true, true, &st.force_evals))) return rc;
     launch_set_B(d, ctx->stream);
     if ((rc = read_ctl(ctx))) return rc;
     if (ctx->h_ctl->coincident) return fail(ctx, MSTAR_E_COINCIDENT, "two bodies share a position");
-    const double gk0 = p.alpha * ctx->h_ctl->U0 + p.gamma;
+    const double gk0 = (p.alpha * ctx->h_ctl->U0 + p.beta * ctx->h_ctl->Om0) + p.gamma;
     double H = p.h_init > 0.0 ? p.h_init : p.q_first * gk0 * (t_end - t0);
     const double span = std::fabs(t_end - t0);
     int halvings = 0, since_rebuild = 0, since_resync = 0;
@@ -762,9 +811,9 @@ static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n,
             if ((rc = prepare_start(ctx, &p, resync, true, &st.force_evals))) break;
             fresh = false;
         }
-        launch_set_h(d, ctx->stream, H, t_end, 1, p.alpha, p.gamma);
+        launch_set_h(d, ctx->stream, H, t_end, 1, ttl_of(&p));
         if ((rc = run_divisions(ctx, &p, nl, p.k_fix, &st.force_evals))) break;
-        launch_extrapolate(d, ctx->stream, p.k_fix, p.alpha, p.gamma, kBase);
+        launch_extrapolate(d, ctx->stream, p.k_fix, ttl_of(&p), kBase);
         launch_control(d, ctx->stream, p.k_fix, p.eta, p.a_gbs, p.f_min, p.f_max);
         launch_commit(d, ctx->stream, 1, 0);
         if ((rc = read_ctl(ctx))) break;
@@ -877,6 +926,7 @@ int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const i
                    const double *t_end, int64_t *n_tot) {
     int rc = check_params(ctx, p);
     if (rc) return rc;
+    if (ttl_on(p)) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: beta != 0 (TTL) is not implemented");
     if (p->k_fix > kBatchMaxKF)
         return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: k_fix > %d is not implemented", kBatchMaxKF);
     if (n_sys < 1 || !off || !t_end) return fail(ctx, MSTAR_E_INVAL, "batch: need n_sys >= 1, offsets and t_end");
@@ -1189,6 +1239,7 @@ int adj_setup(mstar_ctx *ctx, const mstar_params *p, int64_t n, const double *m,
     if (n < 2 || !m || !x || !v || nsteps < 0 || (nsteps > 0 && !H) || !std::isfinite(t0))
         return fail(ctx, MSTAR_E_INVAL, "replay: bad arguments");
     if (n > kAdjMaxN) return fail(ctx, MSTAR_E_UNSUPPORTED, "replay: n > %d is not implemented", kAdjMaxN);
+    if (ttl_on(p)) return fail(ctx, MSTAR_E_UNSUPPORTED, "replay: beta != 0 (TTL) is not implemented");
     for (int64_t k = 0; k < nsteps; ++k)
         if (!std::isfinite(H[k]) || H[k] == 0.0) return fail(ctx, MSTAR_E_INVAL, "replay: H[%lld] invalid", (long long)k);
     (void)hipSetDevice(ctx->device);
@@ -1328,7 +1379,7 @@ int mstar_force_hvp(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
     (void)hipSetDevice(ctx->device);
     const uint32_t flags = params->flags;
     if ((rc = ensure(ctx, (int)n))) return rc;
-    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr))) return rc;
+    if ((rc = load_bodies(ctx, flags, n, m, x, nullptr, nullptr))) return rc;
     const void *xd, *wd;
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
     if ((rc = in_dev(ctx, flags, w, ctx->vin, sizeof(double) * 3 * n, &wd))) return rc;

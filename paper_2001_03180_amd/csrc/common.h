@@ -73,7 +73,9 @@ struct Ctl {               // device control block, read back once per GBS step
     double H;              // fictitious step of this attempt (after the end-time clip)
     double eps;            // GBS error measure
     double h_next;
-    double U0, T0, gk0;    // start-state force function, kinetic energy, alpha U + gamma
+    double U0, T0, gk0;    // start-state force function, kinetic energy, alpha U + beta Omega + gamma
+    double Om0;            // start-state TTL function Omega (0 when beta = 0)
+    double dw0;            // sum_i grad_i Omega . v_i at the start state (dw/dt, TTL)
     double t_est;          // predicted physical time after the step
     int32_t accepted;
     int32_t clipped;
@@ -87,7 +89,10 @@ struct SysScal {           // start-of-step scalars of the integrated state
 };
 
 struct DivScal {           // per-division increments of the scalar variables
-    double tau, dw, drcm[3], pad[3];
+    double tau, dw, drcm[3];
+    double dtk;            // TTL: time step of the latest kick
+    double dwn;            // TTL: dw including the latest kick (set by the drift after it)
+    double pad;
 };
 
 // Workspace pointers used by the kernels (device memory).
@@ -111,6 +116,12 @@ struct Dev {
     DivScal *dscal, *dscal1;    // [slot], extrapolated
     d4 *part;                   // force partials [slot][nsplit_max][n]
     double *Upart;              // [slot][nib * nsplit_max]
+    // TTL function Omega (beta != 0; allocated on first use)
+    double *mo;                 // [n] Omega masses: m_i if m_i <= omega_mass_max else 0
+    d4 *opart;                  // [slot][nsplit_max][n] partial (sum mo_j d/r^3, sum mo_j/r)
+    double *Opart;              // [slot][nib * nsplit_max] partial sum_i mo_i (sum_j mo_j/r)
+    double *wpart;              // [slot][nkwg4] partial sum_i grad_i Omega . v_i
+    d4 *dOm0;                   // [n] grad Omega at the start state
     double *Tpart;              // [slot][nkwg4] (kick: nkwg4 workgroups; commit: nkwg)
     double *epspart;            // [nkwg + 1]
     int nsplit_max, nkwg, nkwg4;  // nkwg = ceil(n/256), nkwg4 = ceil(n/64)
@@ -131,7 +142,7 @@ struct Dev {
 
 // ---------------------------------------------------------------- launches
 // kernels_force.hip
-void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit);
+void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit, bool om);
 // Partial sums per i-block written by launch_force: the nsplit j-splits plus
 // one close-pair correction block when N_d > 0.  Kick and start reduction
 // take this count.
@@ -139,24 +150,28 @@ inline int force_parts(int nsplit, int nd) { return nsplit + (nd > 0 ? 1 : 0); }
 // Resident force workgroups per CU (occupancy of the force kernel).
 int force_blocks_per_cu(int nd);
 void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int nsplit, d4 *acc_out,
-                         double *U_out);
+                         double *U_out, bool om, bool with_w);
 // kernels_step.hip
 void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot);
-void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, double alpha, double gamma);
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, double alpha,
-                 double gamma);
-void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, double alpha, double gamma);
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, double alpha, double gamma, int base_slot);
+// (alpha, beta, gamma): the time-transformation triplet; beta != 0 switches
+// on the TTL function Omega and its auxiliary variable w.
+struct Ttl {
+    double alpha, beta, gamma;
+};
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr);
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr);
+void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr);
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot);
 void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max);
 void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot);
 void launch_state_from_cartesian(const Dev &d, hipStream_t s, const double *x, const double *v);
 void launch_com_frame(const Dev &d, hipStream_t s, int with_T);
 void launch_output_cartesian(const Dev &d, hipStream_t s, double *x, double *v);
-void launch_set_B(const Dev &d, hipStream_t s);
+void launch_set_B(const Dev &d, hipStream_t s);   // B = U0 - T0 and w = Omega0
 void launch_pack3(hipStream_t s, const double *x, const double *m, d4 *out, int n);
 void launch_unpack3(hipStream_t s, const d4 *in, double *out, int n);
-void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, const double *rcm, const double *vcm,
-                    int set_com);
+void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, double w, const double *rcm,
+                    const double *vcm, int set_com);
 void launch_check_coincident(const Dev &d, hipStream_t s);
 // kernels_tree.hip
 void launch_tree_sums(const Dev &d, hipStream_t s, const d4 *X, const d4 *V, d4 *rho, d4 *ups);

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kWG) void k_div_init(Dev d, int ndiv, int base) {
         d.dP[o] = d4{0.0, 0.0, 0.0, 0.0};
         d.dVt[o] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{0.0, 0.0, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{0.0, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
 }
 
 void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
@@ -35,15 +35,19 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
     k_div_init<<<grid, kWG, 0, s>>>(d, ndiv, base_slot);
 }
 
-// Drift D(ds): dt = ds / (alpha (T + B) + gamma); X += dt V; positions +=
-// dt v (kept as increments dP from the start positions, P = P0 + dP);
-// t += dt; r_cm += dt v_cm.
-__global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha, double gamma) {
+// Drift D(ds): dt = ds / (alpha (T + B) + beta w + gamma); X += dt V;
+// positions += dt v (kept as increments dP from the start positions,
+// P = P0 + dP); t += dt; r_cm += dt v_cm.  With OM (TTL), the w increment of
+// the preceding kick is completed here: dw += dt_kick sum_wg wpart, summed by
+// every workgroup in the same order; block 0 records the result in dwn (the
+// kick copies it to dw before it overwrites dtk and wpart).
+template <bool OM>
+__global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
     __shared__ double sh[kWG];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
-    double T;
+    double T, w = d.sys->w;
     if (sl.first[ai]) {
         T = d.ctl->T0;
     } else {
@@ -51,11 +55,21 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha,
         double t = 0.0;
         for (int k = threadIdx.x; k < d.nkwg4; k += kWG) t = t + tp[k];
         T = 0.5 * block_sum<kWG>(t, sh);
+        if constexpr (OM) {
+            const double *wp = d.wpart + (size_t)slot * d.nkwg4;
+            double a = 0.0;
+            for (int k = threadIdx.x; k < d.nkwg4; k += kWG) a = a + wp[k];
+            const double S = block_sum<kWG>(a, sh);
+            const DivScal &q = d.dscal[slot];
+            const double dw = q.dw + q.dtk * S;
+            w = w + dw;
+            if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot].dwn = dw;
+        }
     }
     const double H = d.ctl->H;
     const double h = H / (double)sl.nsub[ai];
     const double ds = sl.half[ai] ? 0.5 * h : h;
-    const double dt = ds / (alpha * (T + d.sys->B) + gamma);
+    const double dt = ds / ((tr.alpha * (T + d.sys->B) + tr.beta * w) + tr.gamma);
     const int v = blockIdx.x * kWG + threadIdx.x;
     if (v < n) {
         const size_t o = (size_t)slot * n + v;
@@ -83,18 +97,21 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, double alpha,
     }
 }
 
-void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, double alpha, double gamma) {
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr) {
     dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
-    k_drift<<<grid, kWG, 0, s>>>(d, sl, alpha, gamma);
+    if (tr.beta != 0.0) k_drift<true><<<grid, kWG, 0, s>>>(d, sl, tr);
+    else k_drift<false><<<grid, kWG, 0, s>>>(d, sl, tr);
 }
 
-// Kick K(ds): dt = ds / (alpha U + gamma); V_v += dt (a_v - a_parent(v));
-// COM-frame velocities v += dt a (as increments dVt, v = v0 + dVt); partial
-// sums of m |v|^2 for the next drift.
-__global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, double alpha,
-                                             double gamma) {
+// Kick K(ds): dt = ds / (alpha U + beta Omega + gamma); V_v += dt (a_v -
+// a_parent(v)); COM-frame velocities v += dt a (as increments dVt,
+// v = v0 + dVt); partial sums of m |v|^2 for the next drift.  With OM (TTL)
+// also per-workgroup partials of sum_i grad_i Omega . (v_i_old + v_i_new)/2;
+// the next drift scales them by dt (kept in dtk) into w.
+template <bool OM>
+__global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, Ttl tr) {
     __shared__ double sh[kWG];
-    __shared__ d4 ra[kWG], rb[kWG];
+    __shared__ d4 ra[kWG], rb[kWG], rc[OM ? kWG : 1];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
@@ -103,14 +120,22 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     double u = 0.0;
     for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
     const double U = 0.5 * G * block_sum<kWG>(u, sh);
+    double Om = 0.0;
+    if constexpr (OM) {
+        const double *op = d.Opart + (size_t)slot * d.nib * d.nsplit_max;
+        double o = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kWG) o = o + op[k];
+        Om = 0.5 * G * block_sum<kWG>(o, sh);
+    }
     const double H = d.ctl->H;
     const double ds = H / (double)sl.nsub[ai];
-    const double dt = ds / (alpha * U + gamma);
+    const double dt = ds / ((tr.alpha * U + tr.beta * Om) + tr.gamma);
     // four threads per body: fixed quarter of the split partials each
     const int v = blockIdx.x * (kWG / 4) + (threadIdx.x >> 2);
     const int part = threadIdx.x & 3;
-    const d4 *pp = d.part + (size_t)slot * d.nsplit_max * n;
-    d4 sa{0.0, 0.0, 0.0, 0.0}, sb{0.0, 0.0, 0.0, 0.0};
+    const size_t prow = (size_t)slot * d.nsplit_max * n;
+    const d4 *pp = d.part + prow;
+    d4 sa{0.0, 0.0, 0.0, 0.0}, sb{0.0, 0.0, 0.0, 0.0}, so{0.0, 0.0, 0.0, 0.0};
     const int p = v < n ? d.parent[v] : -1;
     if (v < n) {
         for (int sp = part; sp < nsplit; sp += 4) {
@@ -120,18 +145,29 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
                 const d4 t2 = pp[(size_t)sp * n + p];
                 sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
             }
+            if constexpr (OM) {
+                const d4 t3 = d.opart[prow + (size_t)sp * n + v];
+                so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
+            }
         }
     }
     ra[threadIdx.x] = sa;
     rb[threadIdx.x] = sb;
+    if constexpr (OM) rc[threadIdx.x] = so;
     __syncthreads();
-    double tl = 0.0;
+    double tl = 0.0, wl = 0.0;
     if (part == 0 && v < n) {
         for (int k = 1; k < 4; ++k) {
             const d4 t = ra[threadIdx.x + k], t2 = rb[threadIdx.x + k];
             sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
             sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
+            if constexpr (OM) {
+                const d4 t3 = rc[threadIdx.x + k];
+                so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
+            }
         }
+    }
+    if (part == 0 && v < n) {
         const double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
         const size_t o = (size_t)slot * n + v;
         if (p >= 0) {
@@ -149,23 +185,40 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
         d.dVt[o] = dvt;
         const d4 v0 = d.Vt[(size_t)kBaseSlot * n + v];
         const d4 vt{v0.x + dvt.x, v0.y + dvt.y, v0.z + dvt.z, 0.0};
+        if constexpr (OM) {
+            const d4 vo = d.Vt[o];
+            const double gm = G * d.mo[v];
+            const double gx = gm * so.x, gy = gm * so.y, gz = gm * so.z;
+            wl = (gx * (0.5 * (vo.x + vt.x)) + gy * (0.5 * (vo.y + vt.y))) + gz * (0.5 * (vo.z + vt.z));
+        }
         d.Vt[o] = vt;
         tl = d.P[o].w * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
     }
     const double ts = block_sum<kWG>(tl, sh);
     if (threadIdx.x == 0) d.Tpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ts;
+    if constexpr (OM) {
+        const double ws = block_sum<kWG>(wl, sh);
+        if (threadIdx.x == 0) d.wpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ws;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            DivScal &q = d.dscal[slot];
+            q.dw = q.dwn;
+            q.dtk = dt;
+        }
+    }
 }
 
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, double alpha,
-                 double gamma) {
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr) {
     dim3 grid((d.n + kWG / 4 - 1) / (kWG / 4), sl.nact);
-    k_kick<<<grid, kWG, 0, s>>>(d, sl, nsplit, G, alpha, gamma);
+    if (tr.beta != 0.0) k_kick<true><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
+    else k_kick<false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
 }
 
 // Step length of this attempt with the end-time clip of Sec. 2.4: the
-// predicted time after the step, t + H/(alpha U + gamma), must not pass t_end
-// (nor may the step point away from it); otherwise ds = (alpha U + gamma)(t_end - t).
-__global__ void k_set_h(Dev d, double H, double t_end, int clip, double alpha, double gamma) {
+// predicted time after the step, t + H/g with g = alpha U + beta Omega + gamma,
+// must not pass t_end (nor may the step point away from it); otherwise
+// ds = g (t_end - t).  With TTL also dw/dt at the start state from the
+// partials of the start-state force reduction.
+__global__ void k_set_h(Dev d, double H, double t_end, int clip, Ttl tr) {
     Ctl &c = *d.ctl;
     {   // T of the start state from the per-workgroup partials left by the commit
         const double *tp = d.Tpart + (size_t)kBaseSlot * d.nkwg4;
@@ -173,7 +226,13 @@ __global__ void k_set_h(Dev d, double H, double t_end, int clip, double alpha, d
         for (int k = 0; k < d.nkwg; ++k) t = t + tp[k];
         c.T0 = 0.5 * t;
     }
-    const double gk = alpha * c.U0 + gamma;
+    double dw = 0.0;
+    if (tr.beta != 0.0) {
+        const double *wp = d.wpart + (size_t)kBaseSlot * d.nkwg4;
+        for (int k = 0; k < d.nkwg; ++k) dw = dw + wp[k];
+    }
+    c.dw0 = dw;
+    const double gk = (tr.alpha * c.U0 + tr.beta * c.Om0) + tr.gamma;
     c.gk0 = gk;
     c.clipped = 0;
     if (clip) {
@@ -188,8 +247,8 @@ __global__ void k_set_h(Dev d, double H, double t_end, int clip, double alpha, d
     c.t_est = d.sys->t + H / gk;
 }
 
-void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, double alpha, double gamma) {
-    k_set_h<<<1, 1, 0, s>>>(d, H, t_end, clip, alpha, gamma);
+void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr) {
+    k_set_h<<<1, 1, 0, s>>>(d, H, t_end, clip, tr);
 }
 
 // In-place Aitken-Neville tableau over KF divisions n_k = 2(k+1); on return
@@ -248,15 +307,15 @@ __device__ __forceinline__ void extrap3(const d4 *arr, int n, int v, d4 &out, do
 }
 
 template <int KF>
-__global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, double alpha, double gamma, int base) {
+__global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
     __shared__ double sh[kWG];
     const int n = d.n;
     const int v = blockIdx.x * kWG + threadIdx.x;
     const Ctl &c = *d.ctl;
     const double H = c.H;
     const double hn = H / (double)(2 * KF);
-    const double gd = alpha * (c.T0 + d.sys->B) + gamma;
-    const double gk = alpha * c.U0 + gamma;
+    const double gd = (tr.alpha * (c.T0 + d.sys->B) + tr.beta * d.sys->w) + tr.gamma;
+    const double gk = (tr.alpha * c.U0 + tr.beta * c.Om0) + tr.gamma;
     double eps = 0.0;
     if (v < n) {
         d4 ox, ov, op, ow;
@@ -289,29 +348,33 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, double alpha, double
     }
     if (threadIdx.x == 0) d.epspart[blockIdx.x] = sh[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // scalar groups: t (extrapolated through its increment tau) and r_cm
-        double pt[KF], rx[KF], ry[KF], rz[KF];
+        // scalar groups: t (extrapolated through its increment tau), r_cm
+        // and, with TTL, w
+        double pt[KF], rx[KF], ry[KF], rz[KF], pw[KF];
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
             const DivScal q = d.dscal[k];
-            pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2];
+            pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2]; pw[k] = q.dwn;
         }
-        neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz);
-        DivScal out{pt[KF - 1], 0.0, {rx[KF - 1], ry[KF - 1], rz[KF - 1]}, {0.0, 0.0, 0.0}};
+        neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz); neville<KF>(pw);
+        DivScal out{pt[KF - 1], pw[KF - 1], {rx[KF - 1], ry[KF - 1], rz[KF - 1]}, 0.0, 0.0, 0.0};
         *d.dscal1 = out;
         const SysScal &y = *d.sys;
         const double et = group_err(pt[KF - 1] - pt[KF - 2], 0.0, 0.0, y.t + hn * (1.0 / gd), 0.0, 0.0);
         const double er = group_err(rx[KF - 1] - rx[KF - 2], ry[KF - 1] - ry[KF - 2], rz[KF - 1] - rz[KF - 2],
                                     y.rcm[0] + hn * (y.vcm[0] / gd), y.rcm[1] + hn * (y.vcm[1] / gd),
                                     y.rcm[2] + hn * (y.vcm[2] / gd));
-        d.epspart[d.nkwg] = fmax_nan(et, er);
+        double es = fmax_nan(et, er);
+        if (tr.beta != 0.0)
+            es = fmax_nan(es, group_err(pw[KF - 1] - pw[KF - 2], 0.0, 0.0, y.w + hn * (c.dw0 / gk), 0.0, 0.0));
+        d.epspart[d.nkwg] = es;
     }
 }
 
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, double alpha, double gamma, int base) {
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base) {
     const int nb = (d.n + kWG - 1) / kWG;
     switch (kf) {
-#define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, alpha, gamma, base); break;
+#define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, tr, base); break;
         KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
         KFC(15) KFC(16)
 #undef KFC
@@ -380,6 +443,7 @@ __global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot
         const DivScal q = from_extrap ? *d.dscal1 : d.dscal[slot];
         SysScal &y = *d.sys;
         y.t = y.t + q.tau;
+        y.w = y.w + (from_extrap ? q.dw : q.dwn);
         for (int c = 0; c < 3; ++c) y.rcm[c] = y.rcm[c] + q.drcm[c];
     }
 }
@@ -495,8 +559,12 @@ void launch_output_cartesian(const Dev &d, hipStream_t s, double *x, double *v) 
     k_output_cartesian<<<1, kTreeWG, 0, s>>>(d, x, v);
 }
 
-// B = -H = U - T at the start of an integration (Sec. 2.1).
-__global__ void k_set_B(Dev d) { d.sys->B = d.ctl->U0 - d.ctl->T0; }
+// B = -H = U - T at the start of an integration (Sec. 2.1); the TTL
+// variable starts at w = Omega (0 without TTL).
+__global__ void k_set_B(Dev d) {
+    d.sys->B = d.ctl->U0 - d.ctl->T0;
+    d.sys->w = d.ctl->Om0;
+}
 void launch_set_B(const Dev &d, hipStream_t s) { k_set_B<<<1, 1, 0, s>>>(d); }
 
 // [n][3] doubles <-> 32-byte rows (fourth slot = mass or 0).
@@ -518,21 +586,21 @@ void launch_unpack3(hipStream_t s, const d4 *in, double *out, int n) {
     k_unpack3<<<(n + kWG - 1) / kWG, kWG, 0, s>>>(in, out, n);
 }
 
-__global__ void k_set_sys(Dev d, double t, double B, double r0, double r1, double r2, double v0, double v1,
-                          double v2, int set_com) {
+__global__ void k_set_sys(Dev d, double t, double B, double w, double r0, double r1, double r2, double v0,
+                          double v1, double v2, int set_com) {
     SysScal &y = *d.sys;
     y.t = t;
     y.B = B;
-    y.w = 0.0;
+    y.w = w;
     if (set_com) {
         y.rcm[0] = r0; y.rcm[1] = r1; y.rcm[2] = r2;
         y.vcm[0] = v0; y.vcm[1] = v1; y.vcm[2] = v2;
     }
     d.ctl->coincident = 0;
 }
-void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, const double *rcm, const double *vcm,
+void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, double w, const double *rcm, const double *vcm,
                     int set_com) {
-    k_set_sys<<<1, 1, 0, s>>>(d, t, B, set_com ? rcm[0] : 0.0, set_com ? rcm[1] : 0.0, set_com ? rcm[2] : 0.0,
+    k_set_sys<<<1, 1, 0, s>>>(d, t, B, w, set_com ? rcm[0] : 0.0, set_com ? rcm[1] : 0.0, set_com ? rcm[2] : 0.0,
                               set_com ? vcm[0] : 0.0, set_com ? vcm[1] : 0.0, set_com ? vcm[2] : 0.0, set_com);
 }
 

@@ -74,7 +74,7 @@ EXPORTS = {
     "mstar_mst_build": (C.c_int, [C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "mstar_force": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                              C.c_void_p, C.c_void_p, C.c_void_p]),
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mstar_leapfrog": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
     "mstar_gbs_step": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -220,8 +220,10 @@ class Context:
         self._check(lib().mstar_mst_build(self._h, flags, n, M.ptr, X.ptr, int(root_in), P.ptr, L.ptr, R.ptr))
         return parent, level, int(root[0])
 
-    def force(self, m, rho, parent, X, p: Params | None = None):
-        """Accelerations [n,3] and force function U with MST separations."""
+    def force(self, m, rho, parent, X, p: Params | None = None, omega: bool = False):
+        """Accelerations [n,3] and force function U with MST separations; with
+        omega=True also the TTL function Omega and its gradient [n,3] (zeros
+        unless p.beta != 0): (acc, U, Omega, dOmega)."""
         p = p or params()
         n = len(m)
         args = [_Arg(m, np.float64, (n,)), _Arg(rho, np.float64, (n, 3)), _Arg(parent, np.int32, (n,)),
@@ -231,12 +233,18 @@ class Context:
         if flags:
             import torch
             acc = torch.empty((n, 3), dtype=torch.float64, device=rho.device)
-            U = torch.empty(1, dtype=torch.float64, device=rho.device)
+            U = torch.empty(2, dtype=torch.float64, device=rho.device)
+            dOm = torch.empty((n, 3), dtype=torch.float64, device=rho.device) if omega else None
         else:
-            acc, U = np.empty((n, 3)), np.empty(1)
+            acc, U = np.empty((n, 3)), np.empty(2)
+            dOm = np.empty((n, 3)) if omega else None
         A, Ua = _Arg(acc, np.float64, writable=True), _Arg(U, np.float64, writable=True)
+        Oa = _Arg(dOm, np.float64, writable=True) if omega else None
+        om_ptr = C.c_void_p(Ua.ptr.value + 8) if omega else None   # U[1] receives Omega
         self._check(lib().mstar_force(self._h, C.byref(p), n, args[0].ptr, args[1].ptr, args[2].ptr,
-                                      args[3].ptr, A.ptr, Ua.ptr))
+                                      args[3].ptr, A.ptr, Ua.ptr, om_ptr, Oa.ptr if omega else None))
+        if omega:
+            return acc, float(U[0]), float(U[1]), dOm
         return acc, float(U[0])
 
     def leapfrog(self, m, parent, X, V, scal, H, nsub, p: Params | None = None):

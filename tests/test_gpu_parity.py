@@ -250,7 +250,7 @@ def test_error_paths(ctx, M):
         ctx.integrate(m, xb, v, 0.0, 1.0)
     assert e.value.code == M.E_NONFINITE
     with pytest.raises(M.MstarError) as e:
-        ctx.integrate(m, x, v, 0.0, 1.0, M.params(beta=1.0))
+        ctx.integrate(m, x, v, 0.0, 1.0, M.params(n_d=3))
     assert e.value.code == M.E_UNSUPPORTED
     with pytest.raises(M.MstarError) as e:
         ctx.integrate(m, x, v, 0.0, 1.0, M.params(k_fix=1))
