@@ -54,7 +54,7 @@ def force_traffic():
     """Measured HBM bytes per force launch if the kernel is the one measured, else None."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_force.hip", "common.h"):
+    for f in ("kernels_force.hip", "pair.h"):
         with open(os.path.join(ROOT, "paper_2001_03180_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if h.hexdigest() != FORCE_TRAFFIC["sha256"]:

@@ -382,30 +382,47 @@ int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool wi
 }
 
 // All divisions nlist[k] (slot k) from the start state over the step in
-// ctl->H: D(h/2)[K(h)D(h)]^(n-1)K(h)D(h/2) for every division, one stage at a
-// time across divisions.
+// ctl->H: D(h/2)[K(h)D(h)]^(n-1)K(h)D(h/2) for every division.  Divisions
+// are packed into lanes no longer than the longest division (first fit,
+// longest first; for n_k = 2k this pairs n with 2 k_fix - n as in the load
+// balancing of Sec. 4.2); a lane's next division starts when the previous one
+// ends.  Every stage launches the drifts, then one force evaluation and the
+// kicks of all divisions active in it: the step takes as many stages as the
+// longest division has kicks, with the force evaluations spread evenly over
+// them (k_fix = 8: 5 per launch for 8 stages, then 4), which keeps every
+// launch large and its j-split partials few.
 int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int ndiv, int64_t *nforce) {
     const Dev &d = ctx->d;
     launch_div_init(d, ctx->stream, ndiv, kBase);
-    int nmax = 0;
-    for (int k = 0; k < ndiv; ++k) nmax = std::max(nmax, nlist[k]);
-    for (int s = 1; s <= nmax + 1; ++s) {
-        SlotList dr{};
+    int order[kMaxDiv];
+    for (int k = 0; k < ndiv; ++k) order[k] = k;
+    std::sort(order, order + ndiv, [&](int a, int b) { return nlist[a] > nlist[b] || (nlist[a] == nlist[b] && a < b); });
+    const int cap = ndiv > 0 ? nlist[order[0]] : 0;
+    int lane_len[kMaxDiv], nlanes = 0;
+    int start[kMaxDiv];   // stage at which each division's first drift runs
+    for (int q = 0; q < ndiv; ++q) {
+        const int k = order[q];
+        int l = 0;
+        while (l < nlanes && lane_len[l] + nlist[k] > cap) ++l;
+        if (l == nlanes) lane_len[nlanes++] = 0;
+        start[k] = 1 + lane_len[l];
+        lane_len[l] += nlist[k];
+    }
+    const int last = cap;
+    for (int t = 1; t <= last + 1; ++t) {
+        SlotList dr{}, fk{};
         for (int k = 0; k < ndiv; ++k) {
+            const int s = t - start[k] + 1;   // local stage of division k
             const int nk = nlist[k];
-            if (s == 1) {
-                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 1; dr.first[dr.nact] = 1; dr.nact++;
-            } else if (nk >= s) {
-                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 0; dr.first[dr.nact] = 0; dr.nact++;
-            } else if (nk == s - 1) {
-                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk; dr.half[dr.nact] = 1; dr.first[dr.nact] = 0; dr.nact++;
-            }
+            if (s < 1 || s > nk + 1) continue;
+            dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk;
+            dr.half[dr.nact] = (s == 1 || s == nk + 1) ? 1 : 0;
+            dr.first[dr.nact] = (s == 1) ? 1 : 0;
+            dr.nact++;
+            if (s <= nk) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nk; fk.nact++; }
         }
         if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p));
-        if (s > nmax) break;
-        SlotList fk{};
-        for (int k = 0; k < ndiv; ++k)
-            if (nlist[k] >= s) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nlist[k]; fk.nact++; }
+        if (!fk.nact) continue;
         const int ns = nsplit_for(d, fk.nact, force_cap(ctx, p->n_d));
         int rc = prof_force(ctx, fk, p->n_d, ns, ttl_on(p));
         if (rc) return rc;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pair.h"
+
 namespace mstar {
 
 // One 32-byte record per body: xyz plus a fourth slot (mass for positions,
@@ -21,26 +23,6 @@ constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, s
 constexpr int kForceIPL = 1;       // i-bodies per lane in the force kernel (2 and 4 measured slower)
 constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
 
-// 1/sqrt(x) for x > 0 to <= 1 ulp: the hardware estimate v_rsq_f64 (relative
-// error ~5e-8) refined by the second-order expansion of (1 - e)^(-1/2) =
-// 1 + e/2 + 3e^2/8 + O(e^3) with e = 1 - x y0^2 (Newton's method on
-// f(y) = y^-2 - x carried one term further).
-__device__ __forceinline__ double rsqrt_f64(double x) {
-    double y0 = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y0, y0, 1.0);
-    double c = fma(e, 0.375, 0.5);
-    return fma(y0 * e, c, y0);
-}
-
-// The O(N^2) pair term: mr = m_j/r, s = m_j/r^3; accumulate phi and a.
-__device__ __forceinline__ void pair_terms(double dx, double dy, double dz, double mj,
-                                           double &s, double &mr) {
-    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double y = rsqrt_f64(r2);
-    mr = mj * y;
-    s = mr * (y * y);
-}
-
 // Deterministic sum of a block of values held one per thread (fixed tree).
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -55,6 +37,28 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     double r = sh[0];
     __syncthreads();
     return r;
+}
+
+// Sum over a wave; lane 0 holds the sum taken in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a workgroup of NT threads with one barrier: lane 0 of every wave
+// writes its wave's sum to sh[0 .. NT/64), then every thread adds them in
+// wave order (the same value in every thread and workgroup).  A later
+// reduction in the same kernel must use other words of shared memory.
+template <int NT>
+__device__ __forceinline__ double block_sum1(double v, double *sh) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int k = 1; k < NT / 64; ++k) s = s + sh[k];
+    return s;
 }
 
 // ---------------------------------------------------------------- stages

@@ -330,21 +330,8 @@ struct ReduceArgs {
 
 template <bool OM>
 __global__ __launch_bounds__(kWG) void k_reduce_start(ReduceArgs r) {
-    __shared__ double sh[kWG];
+    __shared__ double sh[3][kWG / 64];
     const int n = r.n, cnt = r.nib * r.nsplit;
-    double u = 0.0;
-    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + r.Upart[k];
-    const double U = 0.5 * r.G * block_sum<kWG>(u, sh);
-    double Om = 0.0;
-    if constexpr (OM) {
-        double o = 0.0;
-        for (int k = threadIdx.x; k < cnt; k += kWG) o = o + r.Opart[k];
-        Om = 0.5 * r.G * block_sum<kWG>(o, sh);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *r.Uout = U;
-        *r.Omout = Om;
-    }
     const int v = blockIdx.x * kWG + threadIdx.x;
     double wl = 0.0;
     if (v < n) {
@@ -369,11 +356,22 @@ __global__ __launch_bounds__(kWG) void k_reduce_start(ReduceArgs r) {
             }
         }
     }
+    double u = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + r.Upart[k];
+    const double U = 0.5 * r.G * block_sum1<kWG>(u, sh[0]);
+    double Om = 0.0;
     if constexpr (OM) {
+        double o = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kWG) o = o + r.Opart[k];
+        Om = 0.5 * r.G * block_sum1<kWG>(o, sh[1]);
         if (r.vt) {
-            const double ws = block_sum<kWG>(wl, sh);
+            const double ws = block_sum1<kWG>(wl, sh[2]);
             if (threadIdx.x == 0) r.wpart[blockIdx.x] = ws;
         }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *r.Uout = U;
+        *r.Omout = Om;
     }
 }
 

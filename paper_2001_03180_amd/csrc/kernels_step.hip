@@ -43,10 +43,18 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
 // kick copies it to dw before it overwrites dtk and wpart).
 template <bool OM>
 __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
-    __shared__ double sh[kWG];
+    __shared__ double sh[2][kWG / 64];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
+    // the body's operands first: their loads overlap the reductions below
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const size_t o = (size_t)slot * n + v;
+    const bool live = v < n;
+    const bool edge = live && d.parent[v] >= 0;
+    d4 V0{0.0, 0.0, 0.0, 0.0}, dV = V0, dX = V0, vt = V0, p0 = V0, dp = V0;
+    if (edge) { V0 = d.V0[v]; dV = d.dV[o]; dX = d.dX[o]; }
+    if (live) { vt = d.Vt[o]; p0 = d.P[(size_t)kBaseSlot * n + v]; dp = d.dP[o]; }
     double T, w = d.sys->w;
     if (sl.first[ai]) {
         T = d.ctl->T0;
@@ -54,12 +62,12 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
         const double *tp = d.Tpart + (size_t)slot * d.nkwg4;
         double t = 0.0;
         for (int k = threadIdx.x; k < d.nkwg4; k += kWG) t = t + tp[k];
-        T = 0.5 * block_sum<kWG>(t, sh);
+        T = 0.5 * block_sum1<kWG>(t, sh[0]);
         if constexpr (OM) {
             const double *wp = d.wpart + (size_t)slot * d.nkwg4;
             double a = 0.0;
             for (int k = threadIdx.x; k < d.nkwg4; k += kWG) a = a + wp[k];
-            const double S = block_sum<kWG>(a, sh);
+            const double S = block_sum1<kWG>(a, sh[1]);
             const DivScal &q = d.dscal[slot];
             const double dw = q.dw + q.dtk * S;
             w = w + dw;
@@ -70,20 +78,13 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
     const double h = H / (double)sl.nsub[ai];
     const double ds = sl.half[ai] ? 0.5 * h : h;
     const double dt = ds / ((tr.alpha * (T + d.sys->B) + tr.beta * w) + tr.gamma);
-    const int v = blockIdx.x * kWG + threadIdx.x;
-    if (v < n) {
-        const size_t o = (size_t)slot * n + v;
-        if (d.parent[v] >= 0) {
-            const d4 V0 = d.V0[v], dV = d.dV[o];
-            d4 dX = d.dX[o];
-            dX.x = dX.x + dt * (V0.x + dV.x);
-            dX.y = dX.y + dt * (V0.y + dV.y);
-            dX.z = dX.z + dt * (V0.z + dV.z);
-            d.dX[o] = dX;
-        }
-        const d4 vt = d.Vt[o];
-        const d4 p0 = d.P[(size_t)kBaseSlot * n + v];
-        d4 dp = d.dP[o];
+    if (edge) {
+        dX.x = dX.x + dt * (V0.x + dV.x);
+        dX.y = dX.y + dt * (V0.y + dV.y);
+        dX.z = dX.z + dt * (V0.z + dV.z);
+        d.dX[o] = dX;
+    }
+    if (live) {
         dp.x = dp.x + dt * vt.x;
         dp.y = dp.y + dt * vt.y;
         dp.z = dp.z + dt * vt.z;
@@ -110,34 +111,22 @@ void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr) {
 // the next drift scales them by dt (kept in dtk) into w.
 template <bool OM>
 __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, Ttl tr) {
-    __shared__ double sh[kWG];
+    __shared__ double sh[4][kWG / 64];
     __shared__ d4 ra[kWG], rb[kWG], rc[OM ? kWG : 1];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
-    const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
-    const int cnt = d.nfb * nsplit;
-    double u = 0.0;
-    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
-    const double U = 0.5 * G * block_sum<kWG>(u, sh);
-    double Om = 0.0;
-    if constexpr (OM) {
-        const double *op = d.Opart + (size_t)slot * d.nib * d.nsplit_max;
-        double o = 0.0;
-        for (int k = threadIdx.x; k < cnt; k += kWG) o = o + op[k];
-        Om = 0.5 * G * block_sum<kWG>(o, sh);
-    }
-    const double H = d.ctl->H;
-    const double ds = H / (double)sl.nsub[ai];
-    const double dt = ds / ((tr.alpha * U + tr.beta * Om) + tr.gamma);
-    // four threads per body: fixed quarter of the split partials each
+    // four threads per body, each a fixed quarter of the split partials; all
+    // loads that do not depend on the step length are issued first
     const int v = blockIdx.x * (kWG / 4) + (threadIdx.x >> 2);
     const int part = threadIdx.x & 3;
+    const bool live = v < n, lead = live && part == 0;
     const size_t prow = (size_t)slot * d.nsplit_max * n;
+    const size_t o = (size_t)slot * n + v;
     const d4 *pp = d.part + prow;
-    d4 sa{0.0, 0.0, 0.0, 0.0}, sb{0.0, 0.0, 0.0, 0.0}, so{0.0, 0.0, 0.0, 0.0};
-    const int p = v < n ? d.parent[v] : -1;
-    if (v < n) {
+    d4 sa{0.0, 0.0, 0.0, 0.0}, sb = sa, so = sa;
+    const int p = live ? d.parent[v] : -1;
+    if (live) {
         for (int sp = part; sp < nsplit; sp += 4) {
             const d4 t = pp[(size_t)sp * n + v];
             sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
@@ -151,12 +140,35 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
             }
         }
     }
+    d4 dV = sa, dvt = sa, v0 = sa, vo = sa;
+    double mv = 0.0, mo = 0.0;
+    if (lead) {
+        if (p >= 0) dV = d.dV[o];
+        dvt = d.dVt[o];
+        v0 = d.Vt[(size_t)kBaseSlot * n + v];
+        mv = d.P[o].w;
+        if constexpr (OM) { vo = d.Vt[o]; mo = d.mo[v]; }
+    }
     ra[threadIdx.x] = sa;
     rb[threadIdx.x] = sb;
     if constexpr (OM) rc[threadIdx.x] = so;
-    __syncthreads();
+    const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
+    const int cnt = d.nfb * nsplit;
+    double u = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
+    const double U = 0.5 * G * block_sum1<kWG>(u, sh[0]);   // its barrier also publishes ra, rb, rc
+    double Om = 0.0;
+    if constexpr (OM) {
+        const double *op = d.Opart + (size_t)slot * d.nib * d.nsplit_max;
+        double q = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kWG) q = q + op[k];
+        Om = 0.5 * G * block_sum1<kWG>(q, sh[1]);
+    }
+    const double H = d.ctl->H;
+    const double ds = H / (double)sl.nsub[ai];
+    const double dt = ds / ((tr.alpha * U + tr.beta * Om) + tr.gamma);
     double tl = 0.0, wl = 0.0;
-    if (part == 0 && v < n) {
+    if (lead) {
         for (int k = 1; k < 4; ++k) {
             const d4 t = ra[threadIdx.x + k], t2 = rb[threadIdx.x + k];
             sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
@@ -166,38 +178,31 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
                 so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
             }
         }
-    }
-    if (part == 0 && v < n) {
         const double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
-        const size_t o = (size_t)slot * n + v;
         if (p >= 0) {
             const double bx = G * sb.x, by = G * sb.y, bz = G * sb.z;
-            d4 dV = d.dV[o];
             dV.x = dV.x + dt * (ax - bx);
             dV.y = dV.y + dt * (ay - by);
             dV.z = dV.z + dt * (az - bz);
             d.dV[o] = dV;
         }
-        d4 dvt = d.dVt[o];
         dvt.x = dvt.x + dt * ax;
         dvt.y = dvt.y + dt * ay;
         dvt.z = dvt.z + dt * az;
         d.dVt[o] = dvt;
-        const d4 v0 = d.Vt[(size_t)kBaseSlot * n + v];
         const d4 vt{v0.x + dvt.x, v0.y + dvt.y, v0.z + dvt.z, 0.0};
         if constexpr (OM) {
-            const d4 vo = d.Vt[o];
-            const double gm = G * d.mo[v];
+            const double gm = G * mo;
             const double gx = gm * so.x, gy = gm * so.y, gz = gm * so.z;
             wl = (gx * (0.5 * (vo.x + vt.x)) + gy * (0.5 * (vo.y + vt.y))) + gz * (0.5 * (vo.z + vt.z));
         }
         d.Vt[o] = vt;
-        tl = d.P[o].w * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
+        tl = mv * ((vt.x * vt.x + vt.y * vt.y) + vt.z * vt.z);
     }
-    const double ts = block_sum<kWG>(tl, sh);
+    const double ts = block_sum1<kWG>(tl, sh[2]);
     if (threadIdx.x == 0) d.Tpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ts;
     if constexpr (OM) {
-        const double ws = block_sum<kWG>(wl, sh);
+        const double ws = block_sum1<kWG>(wl, sh[3]);
         if (threadIdx.x == 0) d.wpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ws;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             DivScal &q = d.dscal[slot];

@@ -106,8 +106,10 @@ __global__ __launch_bounds__(kTreeWG) void k_mst_init(Dev d, const d4 *pos, int 
         sm = sm + mu;
         s0 = s0 + mu * p.x; s1 = s1 + mu * p.y; s2 = s2 + mu * p.z;
     }
-    const double M = block_sum<kTreeWG>(sm, sh);
-    const d4 c{block_sum<kTreeWG>(s0, sh) / M, block_sum<kTreeWG>(s1, sh) / M, block_sum<kTreeWG>(s2, sh) / M, 0.0};
+    constexpr int W = kTreeWG / 64;
+    const double M = block_sum1<kTreeWG>(sm, sh);
+    const d4 c{block_sum1<kTreeWG>(s0, sh + W) / M, block_sum1<kTreeWG>(s1, sh + 2 * W) / M,
+               block_sum1<kTreeWG>(s2, sh + 3 * W) / M, 0.0};
     double bw = INFINITY;
     int bi = 0x7fffffff;
     for (int v = threadIdx.x; v < n; v += kTreeWG) {
