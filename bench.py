@@ -41,13 +41,17 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 pair-interactions/s at N=5000; batched subsystems/s vs per-system"
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 FLOPS_PER_PAIR = 20
+# FP64 VALU instructions of the force pair loop besides the one hardware
+# 1/sqrt (3 differences, 3 for r^2, 5 for the 1/sqrt refinement, 3 for m/r and
+# m/r^3, 4 accumulations), counted in the gfx950 code of k_force
+LOOP_VALU_PER_PAIR = 18
 BATCH_T_END = 1e-2
 BATCH_ETA = 1e-12
 # HBM bytes per k_force launch on this workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
 # valid only for the force-kernel sources with this hash.
-FORCE_TRAFFIC = {"sha256": "94a0731b1302c8432905caa0b20d2b904afca22a1f32be7e9741ab01dbd33c4a",
-                 "fetch_bytes": 13979625.0, "write_bytes": 4593910.0}
+FORCE_TRAFFIC = {"sha256": "0f03aca3eefd563022c3c9f482e482213a7f1424210cf822957bdf5417efed9e",
+                 "fetch_bytes": 12846756.0, "write_bytes": 8412406.0}
 
 
 def force_traffic():
@@ -274,6 +278,12 @@ def main():
     avg_launch_s = kern_ms * 1e-3 / max(launches, 1)
     flops_per_launch = FLOPS_PER_PAIR * kern_pairs / max(launches, 1)
     achieved = flops_per_launch / avg_launch_s / 1e12
+    # instruction-mix ceiling of the pair loop at the clock the chip sustains
+    fma_cyc, rsq_cyc = ctx.issue_rates()
+    n_simd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    mix_cycles = LOOP_VALU_PER_PAIR * fma_cyc + rsq_cyc
+    ceiling_pairs = n_simd * 2.4e9 * 64 / mix_cycles
+    launch_pairs_per_s = kern_pairs / (kern_ms * 1e-3)
     out = {
         "metric": METRIC,
         "value": value,
@@ -310,6 +320,15 @@ def main():
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "issue_ceiling": {
+                "fma_cycles_per_wave_op": fma_cyc,
+                "rsq_cycles_per_wave_op": rsq_cyc,
+                "loop_valu_per_pair": LOOP_VALU_PER_PAIR,
+                "pairs_per_s": ceiling_pairs,
+                "tflops_algorithmic": FLOPS_PER_PAIR * ceiling_pairs / 1e12,
+                "frac_of_ceiling": launch_pairs_per_s / ceiling_pairs,
+                "note": "cycles at the nominal 2.4 GHz; 4.0 per FMA is the nominal peak",
+            },
         },
     }
     if not args.no_batch:

@@ -172,6 +172,15 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
 int mstar_profile_enable(mstar_ctx *ctx, int enable);
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
 
+/* Measurement aid for the force loop's roofline: SIMD cycles per wave-level
+ * FP64 fused multiply-add (*fma_cycles) and per hardware 1/sqrt
+ * (*rsq_cycles), from chip-wide streams of independent instructions timed
+ * with HIP events and expressed at the nominal 2.4 GHz clock (4 cycles per
+ * FMA at that clock is the nominal FP64 peak).  Allocates and frees 4 MiB of
+ * device memory; takes a few milliseconds.  Errors: MSTAR_E_INVAL, device
+ * errors. */
+int mstar_issue_rates(mstar_ctx *ctx, double *fma_cycles, double *rsq_cycles);
+
 /* ---- many independent small systems in one launch ----
  * The method applied to n_sys independent systems at once (Sec. 4.2 notes the
  * extension to several independent systems); each system is integrated

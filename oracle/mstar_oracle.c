@@ -258,8 +258,9 @@ int orc_separation(int i, int j, const int *parent, const int *level, const doub
  *   U = (G/2) sum_i m_i phi_i.
  * With beta != 0 also Omega = (G/2) sum_i mo_i sum_{j!=i} mo_j/|d_ij| and its
  * gradient dOm_i = G mo_i sum_j mo_j d_ij/|d_ij|^3, where mo_i = m_i if
- * m_i <= omega_mass_max else 0 (READING of the paper's "force function of the
- * least massive particles").  Separations follow orc_separation. */
+ * m_i <= omega_mass_max else 0 (READING: Sec. 2.1 gives a force function of
+ * the lightest bodies as its example of Omega).  Separations follow
+ * orc_separation. */
 int orc_force(int n, const double *m, const int *parent, const int *level, const double *X,
               const double *rho, const orc_params *p, double *acc, double *phi,
               double *U, double *Om, double *dOm) {

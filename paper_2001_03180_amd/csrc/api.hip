@@ -651,6 +651,20 @@ int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, dou
     return MSTAR_OK;
 }
 
+int mstar_issue_rates(mstar_ctx *ctx, double *fma_cycles, double *rsq_cycles) {
+    if (!ctx || !fma_cycles || !rsq_cycles) return fail(ctx, MSTAR_E_INVAL, "issue_rates: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    double *buf = nullptr;
+    HIPCK(hipMalloc((void **)&buf, issue_probe_bytes()));
+    double cyc[2] = {0.0, 0.0};
+    const hipError_t e = issue_probe(ctx->stream, buf, 4 * ctx->num_cu, 2.4, cyc);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(ctx, MSTAR_E_DEVICE, "issue_rates: %s", hipGetErrorString(e));
+    *fma_cycles = cyc[0];
+    *rsq_cycles = cyc[1];
+    return MSTAR_OK;
+}
+
 int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x, int32_t root_in,
                     int32_t *parent, int32_t *level, int32_t *root_out) {
     if (!ctx) return MSTAR_E_INVAL;

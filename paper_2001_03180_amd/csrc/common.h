@@ -177,6 +177,9 @@ void launch_unpack3(hipStream_t s, const d4 *in, double *out, int n);
 void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, double w, const double *rcm,
                     const double *vcm, int set_com);
 void launch_check_coincident(const Dev &d, hipStream_t s);
+// kernels_probe.hip
+size_t issue_probe_bytes();
+hipError_t issue_probe(hipStream_t s, double *out, int n_simd, double clock_ghz, double cycles[2]);
 // kernels_tree.hip
 void launch_tree_sums(const Dev &d, hipStream_t s, const d4 *X, const d4 *V, d4 *rho, d4 *ups);
 void launch_mst_init(const Dev &d, hipStream_t s, const d4 *pos, int root_in);

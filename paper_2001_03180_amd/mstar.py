@@ -80,6 +80,7 @@ EXPORTS = {
     "mstar_gbs_step": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mstar_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "mstar_issue_rates": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mstar_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
     "mstar_integrate_batch": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
@@ -416,6 +417,12 @@ class Context:
         o = _Arg(out, np.float64, writable=True)
         self._check(lib().mstar_force_hvp(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, o.ptr))
         return out
+
+    def issue_rates(self):
+        """(SIMD cycles per wave-level FP64 FMA, per hardware 1/sqrt) at the nominal 2.4 GHz."""
+        f, r = C.c_double(), C.c_double()
+        self._check(lib().mstar_issue_rates(self._h, C.byref(f), C.byref(r)))
+        return f.value, r.value
 
     def profile_enable(self, on=True):
         self._check(lib().mstar_profile_enable(self._h, 1 if on else 0))

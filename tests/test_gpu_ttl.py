@@ -2,7 +2,7 @@
 GPU path vs the CPU oracle, through the C ABI.
 
 Omega couples the bodies with m <= omega_mass_max (the oracle's reading of
-the paper's "force function of the least massive particles"); the auxiliary
+the example Sec. 2.1 gives: a force function of the lightest bodies); the auxiliary
 variable w starts at Omega and follows dw/dt = sum_i grad_i Omega . v_i.
 
 Tolerances are those of the Newtonian stages (see test_gpu_parity.py):
