@@ -66,7 +66,7 @@ typedef struct {
     double h_init;          /* > 0: first fictitious step; 0: automatic */
     int64_t max_steps;      /* GBS step attempts (accepted + rejected) */
     int32_t k_fix;          /* substep divisions n_k = 2k, k = 1..k_fix (Sec. 4.2); 2..16, default 8 */
-    int32_t n_d;            /* MST closeness N_d of eq. LCA; 0..2 here, default 2 */
+    int32_t n_d;            /* MST closeness N_d of eq. LCA; 0..4 here (0..2 in the batch call), default 2 */
     int32_t max_halvings;   /* consecutive rejections before MSTAR_E_NOCONV; default 60 */
     int32_t max_time_iter;  /* clipped end-time steps before MSTAR_W_TIME_TOL; default 8 */
     int32_t rebuild_every;  /* accepted steps between MST rebuilds (Sec. 3.5); default 1 */
@@ -114,7 +114,7 @@ const char *mstar_last_error(const mstar_ctx *ctx);
  * at t0 and overwritten with the state at stats->t_reached.  m [n] > 0.
  * Errors: MSTAR_E_INVAL (n < 2, bad masses or parameters), MSTAR_E_NONFINITE,
  * MSTAR_E_COINCIDENT, MSTAR_E_NOCONV, MSTAR_E_MAXSTEPS, MSTAR_E_UNSUPPORTED
- * (n_d > 2), device errors; warning MSTAR_W_TIME_TOL.  With beta != 0 the
+ * (n_d > 4), device errors; warning MSTAR_W_TIME_TOL.  With beta != 0 the
  * time transformation includes the TTL function Omega of Sec. 2.1 over the
  * bodies with m <= omega_mass_max, and its auxiliary variable w starts at
  * Omega(t0); alpha = gamma = 0 then needs at least two such bodies

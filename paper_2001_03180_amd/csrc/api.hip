@@ -65,7 +65,7 @@ struct mstar_ctx {
     hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
-    int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by N_d kind
+    int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
     // frozen-controller replay and adjoint (kernels_adjoint.hip)
     std::vector<void *> a_allocs;
     int a_n = 0, a_kf = 0;
@@ -192,7 +192,7 @@ constexpr int kResyncEvery = 32;     // accepted steps between re-deriving posit
 
 // Resident force workgroups on the whole chip (queried once per N_d kind).
 int force_cap(mstar_ctx *ctx, int nd) {
-    const int k = nd <= 0 ? 0 : (nd == 1 ? 1 : 2);
+    const int k = nd <= 0 ? 0 : (nd <= 2 ? 1 : 2);
     if (ctx->force_cap[k] <= 0) ctx->force_cap[k] = force_blocks_per_cu(nd) * ctx->num_cu;
     return ctx->force_cap[k];
 }
@@ -224,7 +224,7 @@ int check_params(mstar_ctx *ctx, const mstar_params *p) {
     if (!(p->eta > 0.0)) return fail(ctx, MSTAR_E_INVAL, "params: eta must be > 0");
     if (p->k_fix < 2 || p->k_fix > 16) return fail(ctx, MSTAR_E_INVAL, "params: k_fix must be in [2, 16]");
     if (p->n_d < 0) return fail(ctx, MSTAR_E_INVAL, "params: n_d must be >= 0");
-    if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: n_d > 2 is not implemented on the GPU");
+    if (p->n_d > kMaxNd) return fail(ctx, MSTAR_E_UNSUPPORTED, "params: n_d > %d is not implemented on the GPU", kMaxNd);
     if (!std::isfinite(p->alpha) || !std::isfinite(p->beta) || !std::isfinite(p->gamma) || p->alpha < 0.0 ||
         p->beta < 0.0 || p->gamma < 0.0 || (p->alpha == 0.0 && p->beta == 0.0 && p->gamma == 0.0))
         return fail(ctx, MSTAR_E_INVAL, "params: need alpha, beta, gamma >= 0, not all zero");
@@ -958,6 +958,7 @@ int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const i
     int rc = check_params(ctx, p);
     if (rc) return rc;
     if (ttl_on(p)) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: beta != 0 (TTL) is not implemented");
+    if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: n_d > 2 is not implemented");
     if (p->k_fix > kBatchMaxKF)
         return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: k_fix > %d is not implemented", kBatchMaxKF);
     if (n_sys < 1 || !off || !t_end) return fail(ctx, MSTAR_E_INVAL, "batch: need n_sys >= 1, offsets and t_end");

@@ -22,6 +22,7 @@ constexpr int kWG = 256;           // threads per workgroup of the O(N) kernels
 constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, split j-range)
 constexpr int kForceIPL = 1;       // i-bodies per lane in the force kernel (2 and 4 measured slower)
 constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
+constexpr int kMaxNd = 4;          // largest closeness N_d of eq. LCA on the GPU path
 
 // Deterministic sum of a block of values held one per thread (fixed tree).
 template <int NT>

@@ -11,7 +11,7 @@
 // in fixed order; j-splits across workgroups are combined later in fixed
 // order, so results are bitwise reproducible.
 //
-// Close pairs (tree distance <= N_d): the main loop uses Cartesian
+// Close pairs (tree distance <= N_d, any N_d up to kMaxNd): the main loop uses Cartesian
 // differences for every pair; one extra workgroup per i-block (grid row
 // y = 0, dispatched first) computes, for each close pair, the term built from
 // the MST path sum minus the Cartesian term (same operation sequence as the
@@ -35,6 +35,7 @@ struct ForceArgs {
     const int32_t *parent, *child_off, *child_idx;
     int n, nib, nib_alloc, nsplit, nsplit_max, jchunk;   // nib: force i-blocks of 64*IPL bodies
     int nparts;            // partials per i-block: nsplit j-splits (+1 correction block when N_d > 0)
+    int nd;                // closeness N_d of eq. LCA (0 .. kMaxNd)
     const double *mo;      // [n] Omega masses (OM only)
     d4 *opart;             // [slot][nsplit_max][n] partial (Omega gradient sums, Omega potential)
     double *Opart;         // [slot][nib * nsplit_max] partial sum_i mo_i (sum_j mo_j / r)
@@ -81,41 +82,103 @@ __device__ __forceinline__ d4 cur_edge(const d4 *X0, const d4 *dX, int u) {
     return d4{a.x + b.x, a.y + b.y, a.z + b.z, 0.0};
 }
 
-// Replace the Cartesian terms of all pairs (i, j) within ND tree edges by the
-// MST path-sum terms.  Separations follow the rule d_ij = S_j - S_i with S_v
-// the sum of edge vectors from the lowest common ancestor down to v.
-template <int ND, bool OM>
-__device__ void close_correction(int i, const d4 *P, const double *mo, const d4 *X0, const d4 *dX,
+// Top-down sum of the edge vectors on the path from the ancestor `a` levels
+// above v down to v (the vector from that ancestor to v).
+__device__ __forceinline__ d4 path_down(int v, int a, const int32_t *parent, const d4 *X0, const d4 *dX) {
+    int pth[kMaxNd];
+    int u = v;
+    for (int s = 0; s < a; ++s) {
+        pth[s] = u;
+        u = parent[u];
+    }
+    d4 S{0.0, 0.0, 0.0, 0.0};
+    for (int s = a - 1; s >= 0; --s) {
+        const d4 x = cur_edge(X0, dX, pth[s]);
+        S = d4{S.x + x.x, S.y + x.y, S.z + x.z, 0.0};
+    }
+    return S;
+}
+
+// Replace the Cartesian terms of all pairs (i, j) within nd tree edges
+// (eq. LCA) by the MST path-sum terms, d_ij = S_j - S_i with S_v the
+// top-down sum of edge vectors from the lowest common ancestor to v.  For
+// every ancestor A of i up to nd levels above it (A = i included), the pairs
+// whose lowest common ancestor is A: A itself, and A's descendants at most
+// nd - a levels below it outside the branch that holds i (depth-first, the
+// path sum of each descendant built from its parent's).
+template <bool GENERIC, bool OM>
+__device__ void close_correction(int i, int nd, const d4 *P, const double *mo, const d4 *X0, const d4 *dX,
                                  const int32_t *parent, const int32_t *coff, const int32_t *cidx, Sums &c) {
     const d4 pi = P[i];
-    const int p = parent[i];
     auto mom = [&](int j) { return OM ? mo[j] : 0.0; };
-    if (p >= 0) {
-        const d4 Xi = cur_edge(X0, dX, i);
-        add_close<OM>(-Xi.x, -Xi.y, -Xi.z, pi, P[p], mom(p), c);              // parent
-        if (ND >= 2) {
-            const int g = parent[p];
-            if (g >= 0) {
-                const d4 Xp = cur_edge(X0, dX, p);
-                add_close<OM>(-(Xp.x + Xi.x), -(Xp.y + Xi.y), -(Xp.z + Xi.z), pi, P[g], mom(g), c);  // grandparent
-            }
-            for (int k = coff[p]; k < coff[p + 1]; ++k) {                        // siblings
-                const int q = cidx[k];
-                if (q == i) continue;
-                const d4 Xs = cur_edge(X0, dX, q);
-                add_close<OM>(Xs.x - Xi.x, Xs.y - Xi.y, Xs.z - Xi.z, pi, P[q], mom(q), c);
+    if constexpr (!GENERIC) {
+        // the N_d <= 2 neighbourhood written out (same separations as the
+        // general walk below, with shorter chains of dependent loads)
+        const int p = parent[i];
+        if (p >= 0) {
+            const d4 Xi = cur_edge(X0, dX, i);
+            add_close<OM>(0.0 - Xi.x, 0.0 - Xi.y, 0.0 - Xi.z, pi, P[p], mom(p), c);          // parent
+            if (nd >= 2) {
+                const int g = parent[p];
+                if (g >= 0) {
+                    const d4 Xp = cur_edge(X0, dX, p);
+                    const d4 S{Xp.x + Xi.x, Xp.y + Xi.y, Xp.z + Xi.z, 0.0};
+                    add_close<OM>(0.0 - S.x, 0.0 - S.y, 0.0 - S.z, pi, P[g], mom(g), c);      // grandparent
+                }
+                for (int k = coff[p]; k < coff[p + 1]; ++k) {                                // siblings
+                    const int q = cidx[k];
+                    if (q == i) continue;
+                    const d4 Xs = cur_edge(X0, dX, q);
+                    add_close<OM>(Xs.x - Xi.x, Xs.y - Xi.y, Xs.z - Xi.z, pi, P[q], mom(q), c);
+                }
             }
         }
-    }
-    for (int k = coff[i]; k < coff[i + 1]; ++k) {                                // children
-        const int q = cidx[k];
-        const d4 Xc = cur_edge(X0, dX, q);
-        add_close<OM>(Xc.x, Xc.y, Xc.z, pi, P[q], mom(q), c);
-        if (ND >= 2) {
-            for (int r = coff[q]; r < coff[q + 1]; ++r) {                        // grandchildren
-                const int gc = cidx[r];
-                const d4 Xg = cur_edge(X0, dX, gc);
-                add_close<OM>(Xc.x + Xg.x, Xc.y + Xg.y, Xc.z + Xg.z, pi, P[gc], mom(gc), c);
+        for (int k = coff[i]; k < coff[i + 1]; ++k) {                                        // children
+            const int q = cidx[k];
+            const d4 Xc = cur_edge(X0, dX, q);
+            add_close<OM>(Xc.x, Xc.y, Xc.z, pi, P[q], mom(q), c);
+            if (nd >= 2) {
+                for (int r = coff[q]; r < coff[q + 1]; ++r) {                                // grandchildren
+                    const int gc = cidx[r];
+                    const d4 Xg = cur_edge(X0, dX, gc);
+                    add_close<OM>(Xc.x + Xg.x, Xc.y + Xg.y, Xc.z + Xg.z, pi, P[gc], mom(gc), c);
+                }
+            }
+        }
+    } else {
+        int anc = i, below = -1;
+        for (int a = 0; a <= nd; ++a) {
+            if (a > 0) {
+                below = anc;
+                anc = parent[anc];
+                if (anc < 0) break;
+            }
+            const d4 Si = path_down(i, a, parent, X0, dX);
+            if (a > 0) add_close<OM>(0.0 - Si.x, 0.0 - Si.y, 0.0 - Si.z, pi, P[anc], mom(anc), c);
+            const int bmax = nd - a;
+            if (bmax < 1) continue;
+            int sk[kMaxNd], se[kMaxNd];
+            d4 sS[kMaxNd];
+            int top = 0;
+            sk[0] = coff[anc];
+            se[0] = coff[anc + 1];
+            sS[0] = d4{0.0, 0.0, 0.0, 0.0};
+            while (top >= 0) {
+                if (sk[top] == se[top]) {
+                    --top;
+                    continue;
+                }
+                const int ch = cidx[sk[top]++];
+                if (top == 0 && ch == below) continue;
+                const d4 x = cur_edge(X0, dX, ch);
+                const d4 Sc{sS[top].x + x.x, sS[top].y + x.y, sS[top].z + x.z, 0.0};
+                add_close<OM>(Sc.x - Si.x, Sc.y - Si.y, Sc.z - Si.z, pi, P[ch], mom(ch), c);
+                if (top + 1 < bmax) {   // ch's children are within nd
+                    ++top;
+                    sk[top] = coff[ch];
+                    se[top] = coff[ch + 1];
+                    sS[top] = Sc;
+                }
             }
         }
     }
@@ -162,14 +225,18 @@ __device__ __forceinline__ void j_loop(const d4 *__restrict__ P, const double *_
     }
 }
 
-template <int ND, int NW, int IPL, bool OM>
+// CK: 0 no close pairs (N_d = 0), 1 the written-out N_d <= 2 rule, 2 the
+// general walk for N_d up to kMaxNd (its own instance, so that the stack it
+// needs does not cost the common instances registers).
+template <int CK, int NW, int IPL, bool OM>
 __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
+    constexpr bool CLOSE = CK > 0;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ib = blockIdx.x % a.nib;
     const int slot = a.sl.slot[blockIdx.x / a.nib];
     const int part = blockIdx.y;                          // partial index
-    const int split = ND > 0 ? part - 1 : part;            // j-split index (-1: correction block)
+    const int split = CLOSE ? part - 1 : part;             // j-split index (-1: correction block)
     const int n = a.n;
     const d4 *__restrict__ P = a.P + (size_t)slot * n;
     const size_t prow = ((size_t)slot * a.nsplit_max + part) * n;
@@ -186,14 +253,14 @@ __global__ __launch_bounds__(64 * NW) void k_force(ForceArgs a) {
         c[q] = Sums{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     }
     double u = 0.0, uo = 0.0;
-    if (ND > 0 && split < 0) {   // close-pair correction block (wave 0)
+    if (CLOSE && split < 0) {   // close-pair correction block (wave 0)
         if (wv != 0) return;
 #pragma unroll
         for (int q = 0; q < IPL; ++q) {
             const int i = i0 + q * 64 + lane;
             if (i < n) {
-                close_correction<ND, OM>(i, P, a.mo, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off,
-                                         a.child_idx, c[q]);
+                close_correction<CK == 2, OM>(i, a.nd, P, a.mo, a.X0, a.dX + (size_t)slot * n, a.parent, a.child_off,
+                                     a.child_idx, c[q]);
                 a.part[prow + i] = d4{c[q].ax, c[q].ay, c[q].az, c[q].ph};
                 u = u + pi[q].w * c[q].ph;
                 if constexpr (OM) {
@@ -274,7 +341,7 @@ int force_blocks_per_cu(int nd) {
     int nb = 0;
     hipError_t e;
     if (nd <= 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<0, NW, IPL, false>, 64 * NW, 0);
-    else if (nd == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<1, NW, IPL, false>, 64 * NW, 0);
+    else if (nd <= 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<1, NW, IPL, false>, 64 * NW, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force<2, NW, IPL, false>, 64 * NW, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -296,19 +363,21 @@ void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int n
     a.nsplit_max = d.nsplit_max;
     a.jchunk = (d.n + nsplit - 1) / nsplit;
     a.nparts = force_parts(nsplit, nd);
+    a.nd = nd;
     a.mo = d.mo;
     a.opart = d.opart;
     a.Opart = d.Opart;
     a.sl = sl;
     dim3 grid(sl.nact * d.nfb, a.nparts);
     constexpr int NW = kForceWaves, IPL = kForceIPL;
+    const int ck = nd <= 0 ? 0 : (nd <= 2 ? 1 : 2);
     if (om) {
-        if (nd <= 0) k_force<0, NW, IPL, true><<<grid, 64 * NW, 0, s>>>(a);
-        else if (nd == 1) k_force<1, NW, IPL, true><<<grid, 64 * NW, 0, s>>>(a);
+        if (ck == 0) k_force<0, NW, IPL, true><<<grid, 64 * NW, 0, s>>>(a);
+        else if (ck == 1) k_force<1, NW, IPL, true><<<grid, 64 * NW, 0, s>>>(a);
         else k_force<2, NW, IPL, true><<<grid, 64 * NW, 0, s>>>(a);
     } else {
-        if (nd <= 0) k_force<0, NW, IPL, false><<<grid, 64 * NW, 0, s>>>(a);
-        else if (nd == 1) k_force<1, NW, IPL, false><<<grid, 64 * NW, 0, s>>>(a);
+        if (ck == 0) k_force<0, NW, IPL, false><<<grid, 64 * NW, 0, s>>>(a);
+        else if (ck == 1) k_force<1, NW, IPL, false><<<grid, 64 * NW, 0, s>>>(a);
         else k_force<2, NW, IPL, false><<<grid, 64 * NW, 0, s>>>(a);
     }
 }

@@ -88,7 +88,7 @@ def _state(orc, m, x, v):
 
 
 FORCE_CASES = [("plummer32", 32, 101), ("plummer200_ragged", 200, 7), ("plummer1001", 1001, 201),
-               ("binary5002", 5002, 301)]
+               ("binary5002", 5002, 301), ("binary10002", 10002, 302)]
 
 
 def _scale(m, rho):
@@ -103,10 +103,10 @@ def _scale(m, rho):
 
 
 @pytest.mark.parametrize("name,n,seed", FORCE_CASES, ids=[c[0] for c in FORCE_CASES])
-@pytest.mark.parametrize("nd", [0, 1, 2])
+@pytest.mark.parametrize("nd", [0, 1, 2, 3, 4])
 def test_force_parity(ctx, orc, M, name, n, seed, nd):
-    if n == 5002:
-        m, x, v = ics.plummer_with_binary(5000, seed)
+    if n in (5002, 10002):
+        m, x, v = ics.plummer_with_binary(n - 2, seed)
     elif n == 1001:
         m, x, v = ics.plummer_with_central_mass(1000, seed)
     else:
@@ -189,6 +189,26 @@ def test_gbs_step_parity(ctx, orc, M, n, seed, H, kf):
         assert np.array_equal(Xg, X) and hn == 0.5 * H
 
 
+def test_gbs_step_parity_full_size(ctx, orc, M):
+    """One GBS step of the benchmark workload (N_p = 5002, k_fix = 8, eta = 1e-13)
+    in the launch configuration the benchmark times, against the oracle."""
+    m, x, v = ics.plummer_with_binary(5000, 301)
+    parent, X, V, scal, _ = _state(orc, m, x, v)
+    H = 5e-5
+    say(f"gbs_step n=5002 H={H} k_fix=8")
+    p = M.params(k_fix=8, eta=1e-13)
+    Xg, Vg, sg, acc, eps, hn = ctx.gbs_step(m, parent, X, V, scal, H, p)
+    Xo, Vo, so, acco, epso, hno, nf = orc.gbs_step(m, parent, X, V, scal, H,
+                                                   orc.params(k_fix=8, eta=1e-13, nthreads=0))
+    assert nf == 8 * 9 + 1
+    eps_tol = 1e-3 * epso + 5e-13
+    assert abs(eps - epso) <= eps_tol, (eps, epso)
+    assert acc == acco == 1
+    assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
+    assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+    assert abs(sg[0] - so[0]) <= 1e-14 * abs(so[0]) + 1e-16
+
+
 def _rel_state_err(xg, vg, xo, vo, m):
     rc = (m[:, None] * xo).sum(0) / m.sum()
     vc = (m[:, None] * vo).sum(0) / m.sum()
@@ -197,14 +217,15 @@ def _rel_state_err(xg, vg, xo, vo, m):
     return np.abs(xg - xo).max() / R, np.abs(vg - vo).max() / Vs
 
 
-@pytest.mark.parametrize("name,t_end", [("plummer32", 0.1), ("plummer32", 0.3)])
-def test_integrate_parity_plummer32(ctx, orc, M, name, t_end):
+@pytest.mark.parametrize("name,t_end,nd", [("plummer32", 0.1, 2), ("plummer32", 0.3, 2), ("plummer32", 0.1, 4),
+                                           ("plummer32", 0.1, 3)])
+def test_integrate_parity_plummer32(ctx, orc, M, name, t_end, nd):
     m, x, v, _ = ics.workload(name)
-    say(f"integrate {name} t_end={t_end}")
-    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=1e-12))
-    xg2, vg2, _, st2 = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=1e-12))
+    say(f"integrate {name} t_end={t_end} n_d={nd}")
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=1e-12, n_d=nd))
+    xg2, vg2, _, st2 = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=1e-12, n_d=nd))
     assert np.array_equal(xg, xg2) and np.array_equal(vg, vg2)
-    xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, t_end, orc.params(eta=1e-12))
+    xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, t_end, orc.params(eta=1e-12, n_d=nd))
     assert rc == rco == 0
     assert abs(st["t_reached"] - sto["t_reached"]) <= 2e-14 * t_end
     ex, ev = _rel_state_err(xg, vg, xo, vo, m)
@@ -250,7 +271,7 @@ def test_error_paths(ctx, M):
         ctx.integrate(m, xb, v, 0.0, 1.0)
     assert e.value.code == M.E_NONFINITE
     with pytest.raises(M.MstarError) as e:
-        ctx.integrate(m, x, v, 0.0, 1.0, M.params(n_d=3))
+        ctx.integrate(m, x, v, 0.0, 1.0, M.params(n_d=5))
     assert e.value.code == M.E_UNSUPPORTED
     with pytest.raises(M.MstarError) as e:
         ctx.integrate(m, x, v, 0.0, 1.0, M.params(k_fix=1))
