@@ -220,8 +220,8 @@ def main():
                     help="only a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
+              "drives one GPU per process and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

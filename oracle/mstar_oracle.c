@@ -16,7 +16,11 @@
  * ascending j), so results are bit-identical for any thread count.
  *
  * Each function names the passage of the paper it follows.  Readings taken
- * where the paper is silent are marked READING and listed in the design doc.
+ * where the paper is silent are marked READING.  Parity unpinned against the
+ * paper (no printed value or closed form fixes them; they are checked
+ * oracle-vs-GPU only): the step-controller constants a_GBS, f_min, f_max and
+ * the first-step factor q, the TTL weights omega_ij, and the rule that gives a
+ * new MST edge its vector at a rebuild.
  */
 #include <math.h>
 #include <stdint.h>

@@ -1,6 +1,6 @@
 """GPU (HIP, gfx950) path vs the CPU oracle, stage by stage, through the C ABI.
 
-Tolerances (derived from the arithmetic):
+Tolerances (derived from the arithmetic of each stage):
   * MST edge set: bit-exact (same positions, same no-FMA weights, same
     strict edge order); parent/level identical when the roots agree.
   * one force evaluation: max_i |a_i - a_i^oracle| / (G sum_j m_j/r_ij^2)
