@@ -283,6 +283,20 @@ def test_error_paths(ctx, M):
     assert rc == M.E_NOCONV
 
 
+def test_oversized_first_step_recovers(ctx, orc, M):
+    """Sec. 2.3 failure handling forced from the host: a first step spanning
+    the whole interval (q_first = 1e6, clipped to t_end) fails the error test
+    and is halved until it converges; the run then ends at t_end with the
+    energy kept at the tolerance level."""
+    m, x, v = ics.plummer(16, 7)
+    say("oversized first step")
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, 2.0, M.params(eta=1e-12, q_first=1e6))
+    assert rc == 0 and st["steps_rejected"] >= 5
+    assert abs(st["t_reached"] - 2.0) <= 1e-14 * 2.0
+    d0, d1 = orc.diagnostics(m, x, v), orc.diagnostics(m, xg, vg)
+    assert abs((d1["E"] - d0["E"]) / d0["E"]) <= 1e-13
+
+
 def test_workspace_reuse_across_sizes(ctx, orc, M):
     """Calls on one context with shrinking and growing N give the same result
     as on a fresh context (regression: stale start-slot increments)."""
