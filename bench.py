@@ -103,7 +103,10 @@ def bench_batch(M, ctx, threads, do_cpu, n_single=12, n_cpu=32):
         "n_sys": int(n_sys), "n_bodies": int(off[-1]), "t_end": BATCH_T_END, "eta": BATCH_ETA,
     }
     t0 = time.perf_counter()
-    best = ctx.batch_autotune(off, m, x, v, BATCH_T_END / 10, p=p)
+    # tuning horizon: a third of the run; shorter horizons favour the
+    # several-systems-per-wave tiles, whose waves wait for their slowest
+    # system more as the systems' step counts drift apart over time
+    best = ctx.batch_autotune(off, m, x, v, BATCH_T_END / 3, p=p)
     res["autotune_s"] = time.perf_counter() - t0
     res["launch_shape"] = best
     print(f"[bench] batch autotune: {best}", file=sys.stderr, flush=True)
