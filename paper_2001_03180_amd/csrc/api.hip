@@ -142,7 +142,7 @@ int ensure(mstar_ctx *ctx, int n) {
     A(d.parent, N) A(d.level, N) A(d.parent_new, N) A(d.level_new, N) A(d.child_off, N + 1) A(d.child_idx, N)
     A(d.root, 1) A(d.X0, N) A(d.V0, N) A(d.a0, N) A(d.m, N) A(d.sys, 1) A(d.ctl, 1)
     A(d.P, kMaxDiv * N) A(d.Vt, kMaxDiv * N) A(d.dX, kMaxDiv * N) A(d.dV, kMaxDiv * N) A(d.dX1, N) A(d.dV1, N)
-    A(d.dP, kMaxDiv * N) A(d.dVt, kMaxDiv * N) A(d.dP1, N) A(d.dVt1, N)
+    A(d.dP, kMaxDiv * N) A(d.dVt, kMaxDiv * N) A(d.dP1, N) A(d.dVt1, N) A(d.akick, kMaxDiv * N)
     A(d.dscal, kMaxDiv) A(d.dscal1, 1) A(d.part, (size_t)kMaxDiv * kNsplitMax * N)
     A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, nkwg + 1)
     A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)

@@ -117,6 +117,7 @@ struct Dev {
     // divisions (slot-major)
     d4 *P, *Vt, *dX, *dV;       // [slot][n]: positions+mass, COM-frame velocities, edge increments
     d4 *dP, *dVt;               // [slot][n]: increments of positions / velocities
+    d4 *akick;                  // [slot][n]: accelerations of the latest kick
     d4 *dX1, *dV1, *dP1, *dVt1; // extrapolated increments
     DivScal *dscal, *dscal1;    // [slot], extrapolated
     d4 *part;                   // force partials [slot][nsplit_max][n]

@@ -35,7 +35,8 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
     k_div_init<<<grid, kWG, 0, s>>>(d, ndiv, base_slot);
 }
 
-// Drift D(ds): dt = ds / (alpha (T + B) + beta w + gamma); X += dt V;
+// Drift D(ds): dt = ds / (alpha (T + B) + beta w + gamma); X += dt V, after
+// V has taken the preceding kick (see k_kick);
 // positions += dt v (kept as increments dP from the start positions,
 // P = P0 + dP); t += dt; r_cm += dt v_cm.  With OM (TTL), the w increment of
 // the preceding kick is completed here: dw += dt_kick sum_wg wpart, summed by
@@ -51,9 +52,14 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
     const int v = blockIdx.x * kWG + threadIdx.x;
     const size_t o = (size_t)slot * n + v;
     const bool live = v < n;
-    const bool edge = live && d.parent[v] >= 0;
-    d4 V0{0.0, 0.0, 0.0, 0.0}, dV = V0, dX = V0, vt = V0, p0 = V0, dp = V0;
-    if (edge) { V0 = d.V0[v]; dV = d.dV[o]; dX = d.dX[o]; }
+    const int par = live ? d.parent[v] : -1;
+    const bool edge = par >= 0;
+    const bool after_kick = !sl.first[ai];
+    d4 V0{0.0, 0.0, 0.0, 0.0}, dV = V0, dX = V0, vt = V0, p0 = V0, dp = V0, av = V0, ap = V0;
+    if (edge) {
+        V0 = d.V0[v]; dV = d.dV[o]; dX = d.dX[o];
+        if (after_kick) { av = d.akick[o]; ap = d.akick[(size_t)slot * n + par]; }
+    }
     if (live) { vt = d.Vt[o]; p0 = d.P[(size_t)kBaseSlot * n + v]; dp = d.dP[o]; }
     double T, w = d.sys->w;
     if (sl.first[ai]) {
@@ -79,6 +85,13 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
     const double ds = sl.half[ai] ? 0.5 * h : h;
     const double dt = ds / ((tr.alpha * (T + d.sys->B) + tr.beta * w) + tr.gamma);
     if (edge) {
+        if (after_kick) {   // the preceding kick's update of the edge velocity
+            const double dtk = d.dscal[slot].dtk;
+            dV.x = dV.x + dtk * (av.x - ap.x);
+            dV.y = dV.y + dtk * (av.y - ap.y);
+            dV.z = dV.z + dtk * (av.z - ap.z);
+            d.dV[o] = dV;
+        }
         dX.x = dX.x + dt * (V0.x + dV.x);
         dX.y = dX.y + dt * (V0.y + dV.y);
         dX.z = dX.z + dt * (V0.z + dV.z);
@@ -104,15 +117,18 @@ void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr) {
     else k_drift<false><<<grid, kWG, 0, s>>>(d, sl, tr);
 }
 
-// Kick K(ds): dt = ds / (alpha U + beta Omega + gamma); V_v += dt (a_v -
-// a_parent(v)); COM-frame velocities v += dt a (as increments dVt,
-// v = v0 + dVt); partial sums of m |v|^2 for the next drift.  With OM (TTL)
+// Kick K(ds): dt = ds / (alpha U + beta Omega + gamma); COM-frame velocities
+// v += dt a (as increments dVt, v = v0 + dVt); partial sums of m |v|^2 for the
+// next drift.  The edge velocities V_v += dt (a_v - a_parent(v)) are updated
+// by that drift from the accelerations stored here and dt (kept in dtk): each
+// body's acceleration is then summed from its j-split partials once, not once
+// more for every child.  With OM (TTL)
 // also per-workgroup partials of sum_i grad_i Omega . (v_i_old + v_i_new)/2;
 // the next drift scales them by dt (kept in dtk) into w.
 template <bool OM>
 __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, Ttl tr) {
     __shared__ double sh[4][kWG / 64];
-    __shared__ d4 ra[kWG], rb[kWG], rc[OM ? kWG : 1];
+    __shared__ d4 ra[kWG], rc[OM ? kWG : 1];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
@@ -124,39 +140,32 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     const size_t prow = (size_t)slot * d.nsplit_max * n;
     const size_t o = (size_t)slot * n + v;
     const d4 *pp = d.part + prow;
-    d4 sa{0.0, 0.0, 0.0, 0.0}, sb = sa, so = sa;
-    const int p = live ? d.parent[v] : -1;
+    d4 sa{0.0, 0.0, 0.0, 0.0}, so = sa;
     if (live) {
         for (int sp = part; sp < nsplit; sp += 4) {
             const d4 t = pp[(size_t)sp * n + v];
             sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
-            if (p >= 0) {
-                const d4 t2 = pp[(size_t)sp * n + p];
-                sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
-            }
             if constexpr (OM) {
                 const d4 t3 = d.opart[prow + (size_t)sp * n + v];
                 so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
             }
         }
     }
-    d4 dV = sa, dvt = sa, v0 = sa, vo = sa;
+    d4 dvt = sa, v0 = sa, vo = sa;
     double mv = 0.0, mo = 0.0;
     if (lead) {
-        if (p >= 0) dV = d.dV[o];
         dvt = d.dVt[o];
         v0 = d.Vt[(size_t)kBaseSlot * n + v];
         mv = d.P[o].w;
         if constexpr (OM) { vo = d.Vt[o]; mo = d.mo[v]; }
     }
     ra[threadIdx.x] = sa;
-    rb[threadIdx.x] = sb;
     if constexpr (OM) rc[threadIdx.x] = so;
     const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
     const int cnt = d.nfb * nsplit;
     double u = 0.0;
     for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
-    const double U = 0.5 * G * block_sum1<kWG>(u, sh[0]);   // its barrier also publishes ra, rb, rc
+    const double U = 0.5 * G * block_sum1<kWG>(u, sh[0]);   // its barrier also publishes ra, rc
     double Om = 0.0;
     if constexpr (OM) {
         const double *op = d.Opart + (size_t)slot * d.nib * d.nsplit_max;
@@ -170,22 +179,15 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     double tl = 0.0, wl = 0.0;
     if (lead) {
         for (int k = 1; k < 4; ++k) {
-            const d4 t = ra[threadIdx.x + k], t2 = rb[threadIdx.x + k];
+            const d4 t = ra[threadIdx.x + k];
             sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
-            sb.x = sb.x + t2.x; sb.y = sb.y + t2.y; sb.z = sb.z + t2.z;
             if constexpr (OM) {
                 const d4 t3 = rc[threadIdx.x + k];
                 so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
             }
         }
         const double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
-        if (p >= 0) {
-            const double bx = G * sb.x, by = G * sb.y, bz = G * sb.z;
-            dV.x = dV.x + dt * (ax - bx);
-            dV.y = dV.y + dt * (ay - by);
-            dV.z = dV.z + dt * (az - bz);
-            d.dV[o] = dV;
-        }
+        d.akick[o] = d4{ax, ay, az, 0.0};   // the edge velocities take it in the next drift
         dvt.x = dvt.x + dt * ax;
         dvt.y = dvt.y + dt * ay;
         dvt.z = dvt.z + dt * az;
@@ -204,11 +206,11 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     if constexpr (OM) {
         const double ws = block_sum1<kWG>(wl, sh[3]);
         if (threadIdx.x == 0) d.wpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ws;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            DivScal &q = d.dscal[slot];
-            q.dw = q.dwn;
-            q.dtk = dt;
-        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DivScal &q = d.dscal[slot];
+        if constexpr (OM) q.dw = q.dwn;
+        q.dtk = dt;
     }
 }
 
