@@ -133,6 +133,28 @@ __device__ __forceinline__ void gargmin(double &w, int &a, int &b, int &c) {
     if constexpr (L >= 32) argmin_step<4>(w, a, b, c);
     if constexpr (L >= 64) argmin_step<5>(w, a, b, c);
 }
+// Minimum over a lane group of a double without NaNs, and of a uint32; every
+// lane ends with the group minimum.
+template <int L>
+__device__ __forceinline__ double gmin_f64(double w) {
+    w = fmin(w, partner_f64<0>(w));
+    w = fmin(w, partner_f64<1>(w));
+    w = fmin(w, partner_f64<2>(w));
+    w = fmin(w, partner_f64<3>(w));
+    if constexpr (L >= 32) w = fmin(w, partner_f64<4>(w));
+    if constexpr (L >= 64) w = fmin(w, partner_f64<5>(w));
+    return w;
+}
+template <int L>
+__device__ __forceinline__ uint32_t gmin_u32(uint32_t k) {
+    k = min(k, (uint32_t)partner_i32<0>((int)k));
+    k = min(k, (uint32_t)partner_i32<1>((int)k));
+    k = min(k, (uint32_t)partner_i32<2>((int)k));
+    k = min(k, (uint32_t)partner_i32<3>((int)k));
+    if constexpr (L >= 32) k = min(k, (uint32_t)partner_i32<4>((int)k));
+    if constexpr (L >= 64) k = min(k, (uint32_t)partner_i32<5>((int)k));
+    return k;
+}
 // Lane k's value in every lane (k uniform; group 0 starts at lane 0).
 __device__ __forceinline__ int lane_i32(int v, int k) {
     return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(k));
@@ -268,13 +290,17 @@ __device__ __forceinline__ void group_prim(SysLDS<KF, L, G> &S, const d4 &p, int
     double bw = (live && !in) ? w3(rx, ry, rz, p.x, p.y, p.z) : INFINITY;
     int bu = root;
     for (int step = 1; step < n; ++step) {
+        // the smallest candidate edge under the strict order: first the
+        // weight, then (min, max index) among the edges of that weight; the
+        // edge's end outside the tree is the body added
         const bool cand = live && !in;
-        double kw = cand ? bw : INFINITY;
-        int klo = cand ? min(bu, i) : 0x7fffffff, khi = cand ? max(bu, i) : 0x7fffffff;
-        int kv = cand ? i : 0x7fffffff;
-        gargmin<L>(kw, klo, khi, kv);
-        const int pick = kv;
-        const int pu = lane_i32(bu, pick);
+        const double wmin = gmin_f64<L>(cand ? bw : INFINITY);
+        const uint32_t kk = (cand && bw == wmin) ? (((uint32_t)min(bu, i) << 16) | (uint32_t)max(bu, i)) : 0xffffffffu;
+        const uint32_t kmin = gmin_u32<L>(kk);
+        const int lo = (int)(kmin >> 16), hi = (int)(kmin & 0xffffu);
+        const uint64_t inmask = __ballot(in ? 1 : 0);   // group 0 occupies lanes 0 .. L-1
+        const int pick = ((inmask >> lo) & 1ull) ? hi : lo;
+        const int pu = pick == lo ? hi : lo;
         const int plev = lane_i32(mylev, pu);
         if (i == pick) {
             in = true;
