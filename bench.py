@@ -50,8 +50,8 @@ BATCH_ETA = 1e-12
 # HBM bytes per k_force launch on this workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
 # valid only for the force-kernel sources with this hash.
-FORCE_TRAFFIC = {"sha256": "0f03aca3eefd563022c3c9f482e482213a7f1424210cf822957bdf5417efed9e",
-                 "fetch_bytes": 12846756.0, "write_bytes": 8412406.0}
+FORCE_TRAFFIC = {"sha256": "5b8f31bf1b5fe41179ab371d93b3a576cf1e5cffe0a7c9d9f0335f3c79b10985",
+                 "fetch_bytes": 12840207.0, "write_bytes": 8406907.0}
 
 
 def force_traffic():
