@@ -209,6 +209,64 @@ def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
     }
 
 
+def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
+    """Coordinate round trips of Sec. 3.5: `seeds` equal-mass Hernquist clusters
+    of N = 379, each with the MST and with the chain, n_cycles build /
+    deconstruct cycles in one call per stretch (all 2 * seeds systems side by
+    side); the energy error of every system after each stretch."""
+    import math
+    import numpy as np
+    import ics
+    sys_ = [ics.hernquist(n, seed) for seed in range(1, seeds + 1)]
+    off = np.cumsum([0] + [n] * (2 * seeds))
+    m = np.concatenate([s[0] for s in sys_] * 2)
+    x = np.concatenate([s[1] for s in sys_] * 2)
+    v = np.concatenate([s[2] for s in sys_] * 2)
+    kinds = [0] * seeds + [1] * seeds
+
+    def energy(s, xx, vv):
+        """E = T - U with every term summed exactly rounded (math.fsum)."""
+        o, e = off[s], off[s + 1]
+        ms, xs_, vs_ = m[o:e], xx[o:e], vv[o:e]
+        terms = list(0.5 * ms * (vs_ * vs_).sum(1))
+        for i in range(len(ms) - 1):
+            d = xs_[i + 1:] - xs_[i]
+            terms.extend(-(ms[i] * ms[i + 1:]) / np.sqrt((d * d).sum(1)))
+        return math.fsum(terms)
+
+    E0 = [energy(s, x, v) for s in range(2 * seeds)]
+    marks = [c for c in (300, 1000, 3000, 10000, 30000, 100000) if c < n_cycles] + [n_cycles]
+    curve, done, gpu_s, levels = [], 0, 0.0, None
+    xc, vc = x.copy(), v.copy()
+    for c in marks:
+        t0 = time.perf_counter()
+        xs, vs, ml = ctx.rebuild_cycles(off, kinds, m, xc, vc, c - done, 1)
+        gpu_s += time.perf_counter() - t0
+        xc, vc, done = xs[0].copy(), vs[0].copy(), c
+        levels = ml if levels is None else levels
+        err = [abs(energy(s, xc, vc) - E0[s]) / abs(E0[s]) for s in range(2 * seeds)]
+        curve.append({"cycles": c, "mst_mean": float(np.mean(err[:seeds])), "mst_sd": float(np.std(err[:seeds])),
+                      "chain_mean": float(np.mean(err[seeds:])), "chain_sd": float(np.std(err[seeds:]))})
+        print(f"[bench] rebuild {c} cycles: MST |dE/E| {curve[-1]['mst_mean']:.3e}, chain "
+              f"{curve[-1]['chain_mean']:.3e} ({gpu_s:.1f} s)", file=sys.stderr, flush=True)
+    # CPU baseline: the oracle on a bounded sample, one system, both structures, 200 cycles
+    import oracle as orc
+    t0 = time.perf_counter()
+    for kind in (0, 1):
+        orc.rebuild_cycles(sys_[0][0], sys_[0][1], sys_[0][2], kind, 200, 0)
+    cpu_s = time.perf_counter() - t0
+    return {
+        "workload": f"{seeds} equal-mass Hernquist clusters, N={n}, r_half=1 (seeds 1..{seeds}), each with the "
+                    f"MST and with the chain; {n_cycles} build/deconstruct cycles",
+        "mean_level_mst": float(np.mean(levels[:seeds])), "mean_level_chain": float(np.mean(levels[seeds:])),
+        "curve": curve,
+        "gpu_s": gpu_s,
+        "round_trips_per_s": 2 * seeds * n_cycles / gpu_s,
+        "cpu_oracle": {"round_trips_per_s": 400 / cpu_s, "cores": 1, "kind": "oracle",
+                       "sample": "one cluster, MST and chain, 200 cycles each"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +277,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched small-systems measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement")
+    ap.add_argument("--rebuild-only", action="store_true",
+                    help="only the coordinate round-trip experiment (Sec. 3.5; a few minutes)")
+    ap.add_argument("--rebuild-cycles", type=int, default=100000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -245,6 +306,9 @@ def main():
     ctx = M.Context(0)
     if args.adjoint_only:
         print(json.dumps({"adjoint": bench_adjoint(M, ctx)}), flush=True)
+        return
+    if args.rebuild_only:
+        print(json.dumps({"rebuild": bench_rebuild(M, ctx, args.rebuild_cycles)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)

@@ -19,6 +19,8 @@ Workloads (sizes are the ones the benchmark and parity tests use):
 * ``pythagorean``                      Burrau's three-body problem (Sec. 5.2)
 * ``lidov_kozai``                      hierarchical triple (Sec. 5.3)
 * ``batch_subsystems``                 thousands of small independent systems
+* ``hernquist(n, seed)``               equal-mass Hernquist sphere (Sec. 5.4 clusters;
+                                       the Sec. 3.5 coordinate round-trip test)
 """
 from __future__ import annotations
 
@@ -244,3 +246,53 @@ def workload(name: str):
         m, x, v = plummer_with_central_mass(256, 501)
         return m, x, v, dict(eta=1e-12, t_end=None)
     raise KeyError(name)
+
+
+def _hernquist_df(q):
+    """Hernquist (1990) isotropic distribution function up to a constant, as a
+    function of q = sqrt(binding energy * a / (G M)) in [0, 1)."""
+    q2 = q * q
+    return (3.0 * np.arcsin(q) + q * np.sqrt(1.0 - q2) * (1.0 - 2.0 * q2) * (8.0 * q2 * q2 - 8.0 * q2 - 3.0)) \
+        / (1.0 - q2) ** 2.5
+
+
+def hernquist(n: int, seed: int, r_half: float = 1.0, rmax_over_rhalf: float = 100.0):
+    """Equal-mass Hernquist sphere (total mass 1, G = 1) with half-mass radius
+    r_half: radii from the inverse cumulative mass r^2/(r+a)^2 with
+    a = r_half / (1 + sqrt 2), truncated at rmax_over_rhalf * r_half; speeds
+    drawn by rejection from v^2 f(psi - v^2/2) with the isotropic distribution
+    function f (Eddington inversion of the Hernquist pair, Hernquist 1990) and
+    psi = 1/(r + a); isotropic directions; centre of mass at rest at the origin.
+    Returns (m, x, v)."""
+    rng = _rng(seed)
+    a = r_half / (1.0 + math.sqrt(2.0))
+    rmax = rmax_over_rhalf * r_half
+    r = np.empty(n)
+    k = 0
+    while k < n:
+        s = np.sqrt(rng.uniform(0.0, 1.0, n))
+        rr = a * s / (1.0 - s)
+        rr = rr[rr <= rmax]
+        take = min(n - k, len(rr))
+        r[k:k + take] = rr[:take]
+        k += take
+    x = r[:, None] * _isotropic(rng, n)
+    speed = np.empty(n)
+    grid = np.linspace(0.0, 1.0, 257)[1:-1]
+    for i in range(n):
+        psi = 1.0 / (r[i] + a)
+        vesc = math.sqrt(2.0 * psi)
+        vg = grid * vesc
+        qg = np.sqrt((psi - 0.5 * vg * vg) * a)
+        bound = 1.2 * np.max(vg * vg * _hernquist_df(qg))
+        while True:
+            vv = rng.uniform(0.0, vesc)
+            q = math.sqrt(max(psi - 0.5 * vv * vv, 0.0) * a)
+            if rng.uniform(0.0, bound) <= vv * vv * float(_hernquist_df(np.array([q]))[0]):
+                speed[i] = vv
+                break
+    v = speed[:, None] * _isotropic(rng, n)
+    m = np.full(n, 1.0 / n)
+    x = x - (m[:, None] * x).sum(0)
+    v = v - (m[:, None] * v).sum(0)
+    return m, x, v

@@ -172,6 +172,24 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
 int mstar_profile_enable(mstar_ctx *ctx, int enable);
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
 
+/* Coordinate round trips (Sec. 3.5): for each of n_sys systems (bodies
+ * offsets[s] .. offsets[s+1]-1, 2 <= N <= 512), n_cycles times: build the
+ * coordinate structure from the Cartesian state -- kinds[s] = 0: the MST of
+ * Sec. 3.1-3.4 rooted at the body nearest the centre of mass; 1: the chain of
+ * Sec. 2.2 (the ends of the shortest edge start it, the body nearest either
+ * end joins there; edges compared under the strict order of the MST, the
+ * lower-indexed end of the first edge is the first tail) -- form the edge
+ * vectors and the centre of mass, and rebuild x, v from them (x = r_cm +
+ * (rho - rho_bar), rho the root-relative path sums).  The inputs x, v
+ * ([n_tot][3]) are not modified; after cycle (k+1) n_cycles / n_out the state
+ * is written to x_out[k], v_out[k] ([n_out][n_tot][3]).  mean_level (host,
+ * nullable, [n_sys]) receives the structure's mean body level averaged over
+ * the cycles (a chain's is (N-1)/2).  Pointers per `flags` except mean_level.
+ * Errors: MSTAR_E_INVAL, MSTAR_E_NOMEM, device errors. */
+int mstar_rebuild_cycles(mstar_ctx *ctx, uint32_t flags, int32_t n_sys, const int64_t *offsets,
+                         const int32_t *kinds, const double *m, const double *x, const double *v,
+                         int64_t n_cycles, int32_t n_out, double *x_out, double *v_out, double *mean_level);
+
 /* Measurement aid for the force loop's roofline: SIMD cycles per wave-level
  * FP64 fused multiply-add (*fma_cycles) and per hardware 1/sqrt
  * (*rsq_cycles), from chip-wide streams of independent instructions timed

@@ -73,6 +73,8 @@ def lib():
         sig = {
             "orc_root_nearest_com": (C.c_int, [C.c_int, D, D]),
             "orc_mst_prim": (C.c_int, [C.c_int, D, C.c_int, I, I, I]),
+            "orc_chain_build": (C.c_int, [C.c_int, D, I, I, I]),
+            "orc_rebuild_cycles": (C.c_int, [C.c_int, D, D, D, C.c_int, C.c_int64, C.c_int, D, D, D]),
             "orc_tree_levels": (C.c_int, [C.c_int, I, I, I]),
             "orc_deconstruct": (None, [C.c_int, I, I, D, D]),
             "orc_separation": (C.c_int, [C.c_int, C.c_int, I, I, D, D, C.c_int, D]),
@@ -131,6 +133,34 @@ def mst(x, root):
     order, po = _i(np.empty(n, dtype=np.int32))
     _check(lib().orc_mst_prim(n, px, int(root), pp, pl, po), "mst")
     return parent, level, order
+
+
+def chain(x):
+    """Greedy chain of Sec. 2.2 as a tree rooted at its tail: (parent, level, order)."""
+    x, px = _d(x)
+    n = len(x)
+    parent, pp = _i(np.empty(n, dtype=np.int32))
+    level, pl = _i(np.empty(n, dtype=np.int32))
+    order, po = _i(np.empty(n, dtype=np.int32))
+    _check(lib().orc_chain_build(n, px, pp, pl, po), "chain")
+    return parent, level, order
+
+
+def rebuild_cycles(m, x, v, kind, n_cycles, n_out):
+    """Sec. 3.5 rebuild test: n_cycles build / deconstruct round trips (kind 0
+    MST, 1 chain).  Returns the states after cycles (k+1) n_cycles / n_out,
+    shape [n_out, n, 3] each, and the mean level of the structure averaged
+    over the cycles."""
+    m, pm = _d(m)
+    x = np.array(x, dtype=np.float64, order="C")
+    v = np.array(v, dtype=np.float64, order="C")
+    n = len(m)
+    xs = np.empty((max(n_out, 1), n, 3))
+    vs = np.empty((max(n_out, 1), n, 3))
+    ls = C.c_double()
+    _check(lib().orc_rebuild_cycles(n, pm, _d(x)[1], _d(v)[1], int(kind), int(n_cycles), int(n_out),
+                                    _d(xs)[1], _d(vs)[1], C.byref(ls)), "rebuild_cycles")
+    return xs[:n_out], vs[:n_out], ls.value / max(n_cycles, 1)
 
 
 def tree_levels(parent):

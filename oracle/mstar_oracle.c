@@ -1405,3 +1405,112 @@ out:
     free(dt0); free(dtt); free(adt); free(dU); free(dBv);
     return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Coordinate round trips (Sec. 3.5): the chained coordinates of Sec. 2.2 and
+ * the repeated build / deconstruct cycle that compares them with the MST. */
+
+/* Greedy chain (Sec. 2.2): the two ends of the shortest edge start the chain;
+ * then the body outside the chain nearest to either end joins at that end,
+ * until every body is in.  READINGS: edges and candidates are compared under
+ * the strict order (w, min index, max index) of the MST; the lower-indexed end
+ * of the first edge starts as the tail.  The chain is returned as a tree rooted
+ * at its final tail: parent[] points one step towards the tail, level[] is the
+ * distance from it, order[] lists the chain from tail to head. */
+int orc_chain_build(int n, const double *x, int *parent, int *level, int *order) {
+    if (n < 2) return ORC_E_INVAL;
+    int a = 0, b = 1;
+    double bw = edge_w(x, x + 3);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double w = edge_w(x + 3 * i, x + 3 * j);
+            if (key_less(w, i, j, bw, a, b)) { bw = w; a = i; b = j; }
+        }
+    /* the chain as a deque in a buffer of 2n slots, tail at lo, head at hi - 1 */
+    int *dq = (int *)malloc(sizeof(int) * 2 * (size_t)n);
+    char *in = (char *)calloc((size_t)n, 1);
+    if (!dq || !in) { free(dq); free(in); return ORC_E_NOMEM; }
+    int lo = n, hi = n;
+    dq[hi++] = a;
+    dq[hi++] = b;
+    in[a] = in[b] = 1;
+    for (int added = 2; added < n; ++added) {
+        const int tail = dq[lo], head = dq[hi - 1];
+        int pick = -1, at_tail = 0;
+        double pw = 0.0;
+        int pend = -1;
+        for (int u = 0; u < n; ++u) {
+            if (in[u]) continue;
+            const double wt = edge_w(x + 3 * tail, x + 3 * u), wh = edge_w(x + 3 * head, x + 3 * u);
+            /* this body's nearer end, then the best body over all */
+            int e = tail;
+            double w = wt;
+            if (key_less(wh, head, u, wt, tail, u)) { e = head; w = wh; }
+            if (pick < 0 || key_less(w, e, u, pw, pend, pick)) { pick = u; pw = w; pend = e; at_tail = (e == tail); }
+        }
+        in[pick] = 1;
+        if (at_tail) dq[--lo] = pick;
+        else dq[hi++] = pick;
+    }
+    for (int k = 0; k < n; ++k) {
+        const int v = dq[lo + k];
+        order[k] = v;
+        level[v] = k;
+        parent[v] = k == 0 ? -1 : dq[lo + k - 1];
+    }
+    free(dq);
+    free(in);
+    return ORC_OK;
+}
+
+/* The rebuild test of Sec. 3.5: n_cycles times build the coordinate structure
+ * from the Cartesian state (kind 0: MST rooted at the body nearest the centre of
+ * mass, Sec. 3.2; kind 1: the chain above), form the edge vectors
+ * X_v = x_v - x_parent(v), V_v likewise and the centre of mass, and deconstruct
+ * back to Cartesian coordinates (orc_state_to_cartesian).  The physical state
+ * does not change; only rounding accumulates.  x, v are updated in place; after
+ * cycle (k+1) n_cycles / n_out (k < n_out) the state is copied to
+ * xs[k], vs[k] ([n_out][n][3]).  levels_sum (nullable) receives the sum over
+ * cycles of the mean level of the structure. */
+int orc_rebuild_cycles(int n, const double *m, double *x, double *v, int kind, int64_t n_cycles, int n_out,
+                       double *xs, double *vs, double *levels_sum) {
+    if (n < 2 || (kind != 0 && kind != 1) || n_cycles < 0 || n_out < 0 || (n_out > 0 && (!xs || !vs)))
+        return ORC_E_INVAL;
+    int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
+    int *order = (int *)malloc(sizeof(int) * (size_t)n);
+    double *X = (double *)malloc(sizeof(double) * 3 * (size_t)n), *V = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!parent || !level || !order || !X || !V) {
+        free(parent); free(level); free(order); free(X); free(V);
+        return ORC_E_NOMEM;
+    }
+    int rc = ORC_OK, k = 0;
+    double lsum = 0.0;
+    for (int64_t cyc = 1; cyc <= n_cycles && !rc; ++cyc) {
+        if (kind == 0) rc = orc_mst_prim(n, x, orc_root_nearest_com(n, m, x), parent, level, order);
+        else rc = orc_chain_build(n, x, parent, level, order);
+        if (rc) break;
+        double ls = 0.0;
+        for (int u = 0; u < n; ++u) ls += level[u];
+        lsum += ls / n;
+        double scal[9];
+        for (int u = 0; u < n; ++u) {
+            const int q = parent[u];
+            for (int c = 0; c < 3; ++c) {
+                X[3 * u + c] = q < 0 ? 0.0 : x[3 * u + c] - x[3 * q + c];
+                V[3 * u + c] = q < 0 ? 0.0 : v[3 * u + c] - v[3 * q + c];
+            }
+        }
+        com3(n, m, x, scal + 3);
+        com3(n, m, v, scal + 6);
+        scal[0] = scal[1] = scal[2] = 0.0;
+        rc = orc_state_to_cartesian(n, m, parent, X, V, scal, x, v);
+        while (!rc && k < n_out && cyc == ((int64_t)(k + 1) * n_cycles) / n_out) {
+            memcpy(xs + (size_t)k * 3 * n, x, sizeof(double) * 3 * (size_t)n);
+            memcpy(vs + (size_t)k * 3 * n, v, sizeof(double) * 3 * (size_t)n);
+            ++k;
+        }
+    }
+    if (levels_sum) *levels_sum = lsum;
+    free(parent); free(level); free(order); free(X); free(V);
+    return rc;
+}

@@ -26,6 +26,7 @@
 #include "adjoint.h"
 #include "batch.h"
 #include "common.h"
+#include "rebuild.h"
 
 using namespace mstar;
 
@@ -1423,3 +1424,89 @@ int mstar_force_hvp(mstar_ctx *ctx, const mstar_params *params, int64_t n, const
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// Coordinate round trips (kernels_rebuild.hip).
+
+extern "C" int mstar_rebuild_cycles(mstar_ctx *ctx, uint32_t flags, int32_t n_sys, const int64_t *offsets,
+                                    const int32_t *kinds, const double *m, const double *x, const double *v,
+                                    int64_t n_cycles, int32_t n_out, double *x_out, double *v_out,
+                                    double *mean_level) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    if (n_sys < 1 || !offsets || !kinds || !m || !x || !v || n_cycles < 0 || n_out < 0 ||
+        (n_out > 0 && (!x_out || !v_out)))
+        return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: bad arguments");
+    (void)hipSetDevice(ctx->device);
+    std::vector<int64_t> off((size_t)n_sys + 1);
+    std::vector<int32_t> kd((size_t)n_sys);
+    if (is_dev(flags)) {
+        HIPCK(hipMemcpy(off.data(), offsets, sizeof(int64_t) * (n_sys + 1), hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(kd.data(), kinds, sizeof(int32_t) * n_sys, hipMemcpyDeviceToHost));
+    } else {
+        memcpy(off.data(), offsets, sizeof(int64_t) * (n_sys + 1));
+        memcpy(kd.data(), kinds, sizeof(int32_t) * n_sys);
+    }
+    if (off[0] != 0) return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: offsets[0] must be 0");
+    for (int32_t s = 0; s < n_sys; ++s) {
+        const int64_t n = off[s + 1] - off[s];
+        if (n < 2 || n > kRebuildMaxN)
+            return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: system %d has %lld bodies (need 2..%d)", s, (long long)n,
+                        kRebuildMaxN);
+        if (kd[s] != 0 && kd[s] != 1) return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: kind must be 0 or 1");
+    }
+    const int64_t n_tot = off[n_sys];
+    // device buffers for this call (freed before returning)
+    std::vector<void *> bufs;
+    auto alloc = [&](size_t bytes, void **p) -> int {
+        if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) return fail(ctx, MSTAR_E_NOMEM, "rebuild_cycles: allocation failed");
+        bufs.push_back(*p);
+        return MSTAR_OK;
+    };
+    auto release = [&]() { for (void *p : bufs) (void)hipFree(p); };
+    RebuildArgs a{};
+    int64_t *d_off; int32_t *d_kind, *d_next; double *d_m, *d_x, *d_v, *d_xo, *d_vo, *d_ls; RebuildArgs *d_args;
+    int rc = 0;
+    if ((rc = alloc(sizeof(int64_t) * (n_sys + 1), (void **)&d_off)) || (rc = alloc(sizeof(int32_t) * n_sys, (void **)&d_kind)) ||
+        (rc = alloc(sizeof(int32_t) * n_sys, (void **)&d_next)) || (rc = alloc(sizeof(double) * n_tot, (void **)&d_m)) ||
+        (rc = alloc(sizeof(double) * 3 * n_tot, (void **)&d_x)) || (rc = alloc(sizeof(double) * 3 * n_tot, (void **)&d_v)) ||
+        (rc = alloc(sizeof(double) * 3 * n_tot * (size_t)n_out, (void **)&d_xo)) ||
+        (rc = alloc(sizeof(double) * 3 * n_tot * (size_t)n_out, (void **)&d_vo)) ||
+        (rc = alloc(sizeof(double) * n_sys, (void **)&d_ls)) || (rc = alloc(sizeof(RebuildArgs), (void **)&d_args))) {
+        release();
+        return rc;
+    }
+    const hipMemcpyKind k = is_dev(flags) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipSuccess;
+    auto ck = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    ck(hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice, ctx->stream));
+    ck(hipMemcpyAsync(d_kind, kd.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice, ctx->stream));
+    ck(hipMemcpyAsync(d_m, m, sizeof(double) * n_tot, k, ctx->stream));
+    ck(hipMemcpyAsync(d_x, x, sizeof(double) * 3 * n_tot, k, ctx->stream));
+    ck(hipMemcpyAsync(d_v, v, sizeof(double) * 3 * n_tot, k, ctx->stream));
+    ck(hipMemsetAsync(d_ls, 0, sizeof(double) * n_sys, ctx->stream));
+    ck(hipMemsetAsync(d_next, 0, sizeof(int32_t) * n_sys, ctx->stream));
+    a.off = d_off; a.kind = d_kind; a.m = d_m; a.x = d_x; a.v = d_v;
+    a.n_cycles = n_cycles; a.n_tot = n_tot; a.n_out = n_out;
+    a.x_out = d_xo; a.v_out = d_vo; a.level_sum = d_ls; a.next_out = d_next;
+    ck(hipMemcpyAsync(d_args, &a, sizeof a, hipMemcpyHostToDevice, ctx->stream));
+    // launches of at most kChunk cycles keep every kernel short
+    constexpr int64_t kChunk = 500;
+    for (int64_t c0 = 0; c0 < n_cycles && e == hipSuccess; c0 += kChunk) {
+        launch_rebuild(ctx->stream, d_args, n_sys, c0, std::min(n_cycles, c0 + kChunk));
+        ck(hipGetLastError());
+    }
+    std::vector<double> ls((size_t)n_sys);
+    if (n_out > 0) {
+        const hipMemcpyKind ko = is_dev(flags) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        ck(hipMemcpyAsync(x_out, d_xo, sizeof(double) * 3 * n_tot * n_out, ko, ctx->stream));
+        ck(hipMemcpyAsync(v_out, d_vo, sizeof(double) * 3 * n_tot * n_out, ko, ctx->stream));
+    }
+    ck(hipMemcpyAsync(ls.data(), d_ls, sizeof(double) * n_sys, hipMemcpyDeviceToHost, ctx->stream));
+    ck(hipStreamSynchronize(ctx->stream));
+    release();
+    if (e != hipSuccess) return fail(ctx, MSTAR_E_DEVICE, "rebuild_cycles: %s", hipGetErrorString(e));
+    if (mean_level)
+        for (int32_t s = 0; s < n_sys; ++s) mean_level[s] = n_cycles > 0 ? ls[s] / (double)n_cycles : 0.0;
+    return MSTAR_OK;
+}

@@ -81,6 +81,9 @@ EXPORTS = {
                                  C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mstar_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "mstar_issue_rates": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mstar_rebuild_cycles": (C.c_int, [C.c_void_p, C.c_uint32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_double)]),
     "mstar_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
     "mstar_integrate_batch": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
@@ -417,6 +420,35 @@ class Context:
         o = _Arg(out, np.float64, writable=True)
         self._check(lib().mstar_force_hvp(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, o.ptr))
         return out
+
+    def rebuild_cycles(self, offsets, kinds, m, x, v, n_cycles, n_out):
+        """Coordinate round trips (kind 0 MST, 1 chain per system): returns the
+        states after cycles (k+1) n_cycles / n_out as [n_out, n_tot, 3] arrays
+        and each system's mean structure level over the cycles."""
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        n_sys = len(off) - 1
+        kd = np.ascontiguousarray(kinds, dtype=np.int32)
+        n_tot = int(off[-1])
+        a = [_Arg(m, np.float64, (n_tot,)), _Arg(x, np.float64, (n_tot, 3)), _Arg(v, np.float64, (n_tot, 3))]
+        flags = _mode(*a)
+        if flags:
+            import torch
+            dev = a[1].obj.device
+            xo = torch.empty((max(n_out, 1), n_tot, 3), dtype=torch.float64, device=dev)
+            vo = torch.empty((max(n_out, 1), n_tot, 3), dtype=torch.float64, device=dev)
+            doff = torch.tensor(off, device=dev)
+            dkd = torch.tensor(kd, device=dev)
+            po, pk = C.c_void_p(doff.data_ptr()), C.c_void_p(dkd.data_ptr())
+        else:
+            xo = np.empty((max(n_out, 1), n_tot, 3))
+            vo = np.empty((max(n_out, 1), n_tot, 3))
+            po, pk = C.c_void_p(off.ctypes.data), C.c_void_p(kd.ctypes.data)
+        X, V = _Arg(xo, np.float64, writable=True), _Arg(vo, np.float64, writable=True)
+        ml = np.empty(n_sys)
+        self._check(lib().mstar_rebuild_cycles(self._h, flags, n_sys, po, pk, a[0].ptr, a[1].ptr, a[2].ptr,
+                                               int(n_cycles), int(n_out), X.ptr, V.ptr,
+                                               ml.ctypes.data_as(C.POINTER(C.c_double))))
+        return xo[:n_out], vo[:n_out], ml
 
     def issue_rates(self):
         """(SIMD cycles per wave-level FP64 FMA, per hardware 1/sqrt) at the nominal 2.4 GHz."""
