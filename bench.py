@@ -267,6 +267,82 @@ def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
     }
 
 
+def _energy(m, x, v, block=1024):
+    """E = T - U of a Cartesian state (G = 1), plain numpy in row blocks."""
+    import numpy as np
+    e = 0.5 * float(np.sum(m * (v * v).sum(1)))
+    for i0 in range(0, len(m), block):
+        d = x[None, :, :] - x[i0:i0 + block, None, :]
+        r = np.sqrt((d * d).sum(2))
+        r[np.arange(r.shape[0]), np.arange(i0, i0 + r.shape[0])] = np.inf
+        e -= 0.5 * float(np.sum(m[i0:i0 + block, None] * m[None, :] / r))
+    return e
+
+
+def bench_timing(M, ctx, sizes=None, seeds=3, eta=1e-6, sweep_n=1129, sweep_etas=None, do_cpu=True):
+    """The N-body timing tests of Sec. 5.4 on one GPU: equal-mass Hernquist
+    clusters without hard binaries (M = 1e7 Msun, r_half = 10 pc), integrated
+    for 0.1 Myr at eta = 1e-6, `seeds` clusters per size; wall-clock seconds
+    per simulated Gyr as in the paper's timing figure.  Then the tolerance
+    sweep at N = sweep_n (eta from 1e-6 down to 1e-12)."""
+    import numpy as np
+    import ics
+    sizes = sizes or ics.timing_sizes()
+    sweep_etas = sweep_etas or [10.0 ** -k for k in range(6, 13)]
+    gyr_per_run = 0.1e-3                                   # 0.1 Myr in Gyr
+    allow = (M.OK, M.W_TIME_TOL)
+
+    def run(m, x, v, e):
+        ctx.integrate(m, x, v, 0.0, ics.TIMING_T_END, M.params(eta=e, max_steps=1),
+                      allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))      # sizes the context's buffers
+        t0 = time.perf_counter()
+        x1, v1, rc, st = ctx.integrate(m, x, v, 0.0, ics.TIMING_T_END, M.params(eta=e), allow=allow)
+        wall = time.perf_counter() - t0
+        return wall, st, abs(_energy(m, x1, v1) / _energy(m, x, v) - 1.0)
+
+    rows, clusters = [], {}
+    for n in sizes:
+        recs = []
+        for seed in range(1, seeds + 1):
+            m, x, v, _ = ics.timing_cluster(n, seed)
+            if n == sweep_n:
+                clusters[seed] = (m, x, v)
+            recs.append(run(m, x, v, eta))
+        wall = np.array([r[0] for r in recs])
+        ev = np.array([r[1]["force_evals"] for r in recs], dtype=float)
+        rows.append({"n": n, "wall_s": float(wall.mean()), "s_per_gyr": float(wall.mean() / gyr_per_run),
+                     "steps_accepted": float(np.mean([r[1]["steps_accepted"] for r in recs])),
+                     "steps_rejected": float(np.mean([r[1]["steps_rejected"] for r in recs])),
+                     "force_evals": float(ev.mean()),
+                     "pairs_per_s": float(np.sum(ev) * n * (n - 1) / np.sum(wall)),
+                     "max_abs_dE_over_E": float(max(r[2] for r in recs))})
+        print(f"[bench] timing N={n}: {rows[-1]['wall_s']:.3f} s per 0.1 Myr, "
+              f"{rows[-1]['steps_accepted']:.0f}+{rows[-1]['steps_rejected']:.0f} steps", file=sys.stderr, flush=True)
+    sweep = []
+    if sweep_n in [r["n"] for r in rows]:
+        for e in sweep_etas:
+            recs = [run(*clusters[seed], e) for seed in sorted(clusters)]
+            sweep.append({"eta": e, "wall_s": float(np.mean([r[0] for r in recs])),
+                          "steps_accepted": float(np.mean([r[1]["steps_accepted"] for r in recs])),
+                          "steps_rejected": float(np.mean([r[1]["steps_rejected"] for r in recs])),
+                          "max_abs_dE_over_E": float(max(r[2] for r in recs))})
+            print(f"[bench] timing N={sweep_n} eta={e:.0e}: {sweep[-1]['wall_s']:.3f} s", file=sys.stderr, flush=True)
+        for r in sweep:
+            r["wall_over_eta1e-6"] = r["wall_s"] / sweep[0]["wall_s"]
+    out = {"workload": f"equal-mass Hernquist clusters without hard binaries, M=1e7 Msun, r_half=10 pc, "
+                       f"0.1 Myr ({ics.TIMING_T_END:.4f} N-body units), eta={eta:g}, {seeds} seeds per N",
+           "sizes": rows, "eta_sweep": {"n": sweep_n, "runs": sweep}}
+    if do_cpu:
+        import oracle as orc
+        m, x, v, _ = ics.timing_cluster(379, 1)
+        t0 = time.perf_counter()
+        orc.integrate(m, x, v, 0.0, ics.TIMING_T_END, orc.params(eta=eta))
+        cpu = time.perf_counter() - t0
+        out["cpu_oracle"] = {"n": 379, "wall_s": cpu, "s_per_gyr": cpu / gyr_per_run, "cores": 1, "kind": "oracle",
+                             "sample": "one N=379 cluster (seed 1), 0.1 Myr"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +356,9 @@ def main():
     ap.add_argument("--rebuild-only", action="store_true",
                     help="only the coordinate round-trip experiment (Sec. 3.5; a few minutes)")
     ap.add_argument("--rebuild-cycles", type=int, default=100000)
+    ap.add_argument("--timing-only", action="store_true",
+                    help="only the cluster timing tests (Sec. 5.4: 20 sizes x 3 seeds, 0.1 Myr, and the eta sweep)")
+    ap.add_argument("--timing-max-n", type=int, default=10000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +388,10 @@ def main():
         return
     if args.rebuild_only:
         print(json.dumps({"rebuild": bench_rebuild(M, ctx, args.rebuild_cycles)}), flush=True)
+        return
+    if args.timing_only:
+        sizes = [k for k in ics.timing_sizes() if k <= args.timing_max_n]
+        print(json.dumps({"timing": bench_timing(M, ctx, sizes, do_cpu=not args.no_cpu)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)

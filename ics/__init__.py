@@ -21,6 +21,9 @@ Workloads (sizes are the ones the benchmark and parity tests use):
 * ``batch_subsystems``                 thousands of small independent systems
 * ``hernquist(n, seed)``               equal-mass Hernquist sphere (Sec. 5.4 clusters;
                                        the Sec. 3.5 coordinate round-trip test)
+* ``timing_cluster(n, seed)``          the same without hard binaries (Sec. 5.4 timing
+                                       tests; the selection evaluates pair binding
+                                       energies, which is input selection only)
 """
 from __future__ import annotations
 
@@ -296,3 +299,51 @@ def hernquist(n: int, seed: int, r_half: float = 1.0, rmax_over_rhalf: float = 1
     x = x - (m[:, None] * x).sum(0)
     v = v - (m[:, None] * v).sum(0)
     return m, x, v
+
+
+# The timing clusters of the paper's N-body timing tests: M = 1e7 solar masses,
+# r_half = 10 pc, integrated for 0.1 Myr.  In the units used here (G = M =
+# r_half = 1) the time unit is sqrt(r_half^3 / (G M)) with
+# G = 4.498502151469552e-3 pc^3 / (Msun Myr^2) (from the IAU nominal solar
+# GM, the parsec and the Julian year), i.e. 0.149096 Myr.
+TIMING_MYR_PER_UNIT = 0.1490960142591554
+TIMING_T_END = 0.1 / TIMING_MYR_PER_UNIT
+
+
+def timing_sizes():
+    """The 20 cluster sizes, logarithmically spaced from 10 to 10^4."""
+    return [int(round(10.0 ** (1.0 + 3.0 * k / 19.0))) for k in range(20)]
+
+
+def hard_binaries(m, x, v):
+    """Pairs bound more tightly than the mean kinetic energy of a body: the
+    pair's two-body binding energy G m_i m_j / r - mu |v_i - v_j|^2 / 2 (with
+    G = 1, mu the reduced mass) at least <m v^2 / 2> over the cluster (centre
+    of mass frame).  Only pairs closer than max(m)^2 / <m v^2 / 2> can qualify,
+    so a k-d tree lists the candidates.  Returns a sorted list of (i, j), i < j."""
+    from scipy.spatial import cKDTree
+    m = np.asarray(m, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    vc = v - (m[:, None] * v).sum(0) / m.sum()
+    thresh = 0.5 * float(np.mean(m * (vc * vc).sum(1)))
+    cand = cKDTree(x).query_pairs(float(m.max()) ** 2 / thresh, output_type="ndarray")
+    if len(cand) == 0:
+        return []
+    i, j = cand[:, 0], cand[:, 1]
+    dx, dv = x[j] - x[i], v[j] - v[i]
+    mu = m[i] * m[j] / (m[i] + m[j])
+    eb = m[i] * m[j] / np.sqrt((dx * dx).sum(1)) - 0.5 * mu * (dv * dv).sum(1)
+    hit = eb >= thresh
+    return sorted((int(min(a, b)), int(max(a, b))) for a, b in zip(i[hit], j[hit]))
+
+
+def timing_cluster(n: int, seed: int, max_draws: int = 1000):
+    """A Hernquist cluster of the timing tests (``hernquist(n, ...)``, r_half = 1)
+    with no hard binary: draws with seeds 1000 * seed + k, k = 0, 1, ..., until
+    ``hard_binaries`` finds none.  Returns (m, x, v, k)."""
+    for k in range(max_draws):
+        m, x, v = hernquist(n, 1000 * seed + k)
+        if not hard_binaries(m, x, v):
+            return m, x, v, k
+    raise RuntimeError(f"no cluster without hard binaries in {max_draws} draws (n={n}, seed={seed})")

@@ -98,3 +98,24 @@ def test_two_body_logh_exact_orbit(ctx, orc, M, H, nsub):
     assert np.abs(e1["h"] - e0["h"]).max() < 1e-13 * np.linalg.norm(e0["h"])
     assert np.abs(e1["A"] - e0["A"]).max() < 1e-12 * mu
     assert s1[0] > 0 and np.abs(x1 - x).max() > 1e-3
+
+
+@pytest.mark.parametrize("n", [30, 183])
+def test_timing_cluster_parity(ctx, orc, M, n):
+    """Sec. 5.4 timing workload: a Hernquist cluster without hard binaries over
+    0.1 Myr at eta = 1e-6.  The GPU takes the same accepted and rejected steps
+    as the oracle and ends within rounding growth of its state; the energy
+    error stays at the tolerance level."""
+    m, x, v, _ = ics.timing_cluster(n, 1)
+    say(f"timing cluster N={n}")
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, ics.TIMING_T_END, M.params(eta=1e-6))
+    xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, ics.TIMING_T_END, orc.params(eta=1e-6))
+    assert rc == rco == 0
+    assert (st["steps_accepted"], st["steps_rejected"]) == (sto["steps_accepted"], sto["steps_rejected"])
+    rcm = (m[:, None] * xo).sum(0)
+    vcm = (m[:, None] * vo).sum(0)
+    ex = np.abs(xg - xo).max() / np.abs(xo - rcm).max()
+    ev = np.abs(vg - vo).max() / np.abs(vo - vcm).max()
+    assert ex <= 1e-9 and ev <= 1e-9, (ex, ev)
+    d0, d1 = orc.diagnostics(m, x, v), orc.diagnostics(m, xg, vg)
+    assert abs((d1["E"] - d0["E"]) / d0["E"]) < 1e-7
