@@ -85,6 +85,9 @@ def lib():
             "orc_build_state": (C.c_int, [C.c_int, D, D, D, I, D, D, D]),
             "orc_state_to_cartesian": (C.c_int, [C.c_int, D, I, D, D, D, D, D]),
             "orc_integrate": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats)]),
+            "orc_integrate_ext": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.c_int, D, D,
+                                            C.POINTER(Stats)]),
+            "orc_external_accel": (C.c_int, [C.c_int, D, D, C.c_double, C.c_int, D, D]),
             "orc_diagnostics": (None, [C.c_int, D, D, D, C.c_double, D]),
             "orc_sdiv": (C.c_double, [C.c_int, C.c_int, I]),
             "orc_integrate_rec": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats),
@@ -278,6 +281,40 @@ def integrate(m, x, v, t0, t_end, p: Params | None = None, raise_on_error=True):
     if raise_on_error and rc < 0:
         raise RuntimeError(f"oracle integrate failed with code {rc}")
     return x, v, rc, st.as_dict()
+
+
+def _ext_args(g, points):
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(3))
+    pts = np.zeros((0, 5)) if points is None else np.asarray(points, dtype=np.float64).reshape(-1, 5)
+    pts = np.ascontiguousarray(pts)
+    return g, pts
+
+
+def integrate_ext(m, x, v, t0, t_end, g=(0.0, 0.0, 0.0), points=None, p: Params | None = None,
+                  raise_on_error=True):
+    """Integration under an external perturbation (Sec. 2.1): a uniform
+    acceleration g and fixed Plummer-softened point masses points[k] =
+    (M, X, Y, Z, b).  Returns (x, v, rc, stats dict)."""
+    p = p or params()
+    m, pm = _d(m)
+    g, pts = _ext_args(g, points)
+    x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
+    st = Stats()
+    rc = lib().orc_integrate_ext(len(m), pm, _d(x)[1], _d(v)[1], float(t0), float(t_end), C.byref(p),
+                                 len(pts), _d(g)[1], _d(pts)[1], C.byref(st))
+    if raise_on_error and rc < 0:
+        raise RuntimeError(f"oracle integrate_ext failed with code {rc}")
+    return x, v, rc, st.as_dict()
+
+
+def external_accel(r, g=(0.0, 0.0, 0.0), points=None, G=1.0):
+    """The external acceleration field at positions r[n][3]."""
+    g, pts = _ext_args(g, points)
+    r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1, 3))
+    f = np.empty_like(r)
+    _check(lib().orc_external_accel(len(pts), _d(g)[1], _d(pts)[1], float(G), len(r), _d(r)[1], _d(f)[1]),
+           "external_accel")
+    return f
 
 
 def diagnostics(m, x, v, G=1.0):

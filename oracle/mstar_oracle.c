@@ -333,6 +333,40 @@ int orc_force(int n, const double *m, const int *parent, const int *level, const
 }
 
 /* ------------------------------------------------------------------ */
+/* External perturbation f_i (Sec. 2.1: an acceleration that depends only on
+ * the body's position, added to the Newtonian one).  The family offered here:
+ * a uniform acceleration g plus np fixed Plummer-softened point masses,
+ * pt[k] = (M_k, X_k, Y_k, Z_k, b_k):
+ *   f(r) = g + G sum_k M_k (R_k - r) / (|R_k - r|^2 + b_k^2)^(3/2),
+ * the gradient field of Phi(r) = -g.r - G sum_k M_k / sqrt(|r - R_k|^2 + b_k^2). */
+typedef struct {
+    int np;
+    double g[3];
+    const double *pt;
+} orc_ext;
+
+static void ext_accel(const orc_ext *e, double G, const double *r, double *f) {
+    for (int c = 0; c < 3; ++c) f[c] = e->g[c];
+    for (int k = 0; k < e->np; ++k) {
+        const double *q = e->pt + 5 * k;
+        double d[3] = {q[1] - r[0], q[2] - r[1], q[3] - r[2]};
+        double s2 = ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) + q[4] * q[4];
+        double w = G * q[0] / (s2 * sqrt(s2));
+        for (int c = 0; c < 3; ++c) f[c] = f[c] + w * d[c];
+    }
+}
+
+/* f at n positions r[n][3] (exported for the field's own pins). */
+int orc_external_accel(int np, const double *g, const double *pt, double G, int n, const double *r, double *f) {
+    if (np < 0 || n < 0) return ORC_E_INVAL;
+    orc_ext e;
+    e.np = np; e.pt = pt;
+    for (int c = 0; c < 3; ++c) e.g[c] = g[c];
+    for (int i = 0; i < n; ++i) ext_accel(&e, G, r + 3 * i, f + 3 * i);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* The integrated state (READING of Sec. 2.2 with Sec. 3.4): MST edge vectors
  * X_v, V_v (row v = the edge from parent(v) to v; the root row is zero), the
  * centre of mass r_cm, v_cm, physical time t, binding energy B = -H and the TTL
@@ -344,6 +378,7 @@ typedef struct {
     double *X, *V;
     double t, B, w;
     double rcm[3], vcm[3];
+    const orc_ext *ext;   /* external perturbation, or NULL */
 } ostate;
 
 /* A substep division works on increments from the step's start state y0
@@ -355,11 +390,12 @@ typedef struct {
     const ostate *y0;
     double *dX, *dV;
     double tau, dw, drcm[3];
+    double dB, dvcm[3];   /* change of B and v_cm under an external perturbation */
 } odiv;
 
 /* Scratch buffers for one leapfrog evaluation. */
 typedef struct {
-    double *rho, *ups, *acc, *phi, *dom, *vt_old, *vt_new, *Xc, *Vc;
+    double *rho, *ups, *acc, *phi, *dom, *vt_old, *vt_new, *Xc, *Vc, *fex;
 } oscratch;
 
 static int scratch_alloc(oscratch *s, int n) {
@@ -367,13 +403,13 @@ static int scratch_alloc(oscratch *s, int n) {
     s->rho = (double *)malloc(b); s->ups = (double *)malloc(b); s->acc = (double *)malloc(b);
     s->phi = (double *)malloc(b / 3); s->dom = (double *)malloc(b);
     s->vt_old = (double *)malloc(b); s->vt_new = (double *)malloc(b);
-    s->Xc = (double *)malloc(b); s->Vc = (double *)malloc(b);
-    return (s->rho && s->ups && s->acc && s->phi && s->dom && s->vt_old && s->vt_new && s->Xc && s->Vc)
+    s->Xc = (double *)malloc(b); s->Vc = (double *)malloc(b); s->fex = (double *)malloc(b);
+    return (s->rho && s->ups && s->acc && s->phi && s->dom && s->vt_old && s->vt_new && s->Xc && s->Vc && s->fex)
                ? ORC_OK : ORC_E_NOMEM;
 }
 static void scratch_free(oscratch *s) {
     free(s->rho); free(s->ups); free(s->acc); free(s->phi); free(s->dom); free(s->vt_old); free(s->vt_new);
-    free(s->Xc); free(s->Vc);
+    free(s->Xc); free(s->Vc); free(s->fex);
 }
 
 /* Centre-of-mass-frame velocities from MST velocity edges V (Sec. 2.2: the
@@ -403,6 +439,21 @@ static int eval_force(const ostate *y, const double *X, const orc_params *p, osc
     return orc_force(y->n, y->m, y->parent, y->level, X, s->rho, p, s->acc, s->phi, U, Om, s->dom);
 }
 
+/* External accelerations at the bodies' positions r_i = r_cm + (rho_i - rho_bar)
+ * (rho as left in s->rho by eval_force, rcm the current centre of mass) into
+ * s->fex; returns sum_i m_i f_i / M in Fm. */
+static void external_at(const ostate *y, const double *rcm, const orc_params *p, oscratch *s, double *Fm) {
+    const int n = y->n;
+    double rb[3];
+    com3(n, y->m, s->rho, rb);
+    for (int i = 0; i < n; ++i) {
+        double r[3];
+        for (int c = 0; c < 3; ++c) r[c] = rcm[c] + (s->rho[3 * i + c] - rb[c]);
+        ext_accel(y->ext, p->G, r, s->fex + 3 * i);
+    }
+    com3(n, y->m, s->fex, Fm);
+}
+
 static void current_X(const odiv *d, double *Xc) {
     const int n = d->y0->n;
     for (int k = 0; k < 3 * n; ++k) Xc[k] = d->y0->X[k] + d->dX[k];
@@ -421,19 +472,24 @@ static void drift(odiv *d, const orc_params *p, oscratch *s, double ds) {
     current_V(d, s->Vc);
     double T = com_frame_velocities(y, s->Vc, s->ups, s->vt_old);
     double w = y->w + d->dw;
-    double dt = ds / ((p->alpha * (T + y->B) + p->beta * w) + p->gamma);
+    double dt = ds / ((p->alpha * (T + (y->B + d->dB)) + p->beta * w) + p->gamma);
     for (int v = 0; v < n; ++v) {
         if (y->parent[v] < 0) continue;
         for (int c = 0; c < 3; ++c) d->dX[3 * v + c] = d->dX[3 * v + c] + dt * s->Vc[3 * v + c];
     }
-    for (int c = 0; c < 3; ++c) d->drcm[c] = d->drcm[c] + dt * y->vcm[c];
+    for (int c = 0; c < 3; ++c) d->drcm[c] = d->drcm[c] + dt * (y->vcm[c] + d->dvcm[c]);
     d->tau = d->tau + dt;
 }
 
 /* Kick K(ds): dt = ds / (alpha U + beta Omega + gamma);  V_v += dt (a_v -
  * a_parent(v)) (the MST analogue of A_k in eq. chained);  with beta != 0 also
  * w += dt sum_i dOmega_i . (v_i_old + v_i_new)/2 (TTL, Mikkola & Aarseth 2002).
- * B is unchanged without external perturbations (Sec. 2.1). */
+ * B is unchanged without external perturbations (Sec. 2.1).  With an external
+ * field f (READING of Sec. 2.1 with the COM motion split off): every body
+ * takes a_i + f_i, so V_v += dt (a_v + f_v - a_q - f_q) and v_cm += dt F/M
+ * (F = sum m_i f_i); f is fixed during the kick, so the COM-frame velocities
+ * change linearly in t and the binding-energy equation integrates exactly:
+ * B -= dt sum_i m_i f_i . (v_i_old + v_i_new)/2 (COM-frame velocities). */
 static int kick(odiv *d, const orc_params *p, oscratch *s, double ds, int64_t *nforce) {
     const ostate *y = d->y0;
     const int n = y->n;
@@ -443,7 +499,14 @@ static int kick(odiv *d, const orc_params *p, oscratch *s, double ds, int64_t *n
     if (rc) return rc;
     (*nforce)++;
     double dt = ds / ((p->alpha * U + p->beta * Om) + p->gamma);
-    if (p->beta != 0.0) {
+    double Fm[3] = {0.0, 0.0, 0.0};
+    if (y->ext) {
+        double rc_now[3];
+        for (int c = 0; c < 3; ++c) rc_now[c] = y->rcm[c] + d->drcm[c];
+        external_at(y, rc_now, p, s, Fm);
+        for (int k = 0; k < 3 * n; ++k) s->acc[k] = s->acc[k] + s->fex[k];
+    }
+    if (p->beta != 0.0 || y->ext) {
         current_V(d, s->Vc);
         com_frame_velocities(y, s->Vc, s->ups, s->vt_old);
     }
@@ -452,6 +515,17 @@ static int kick(odiv *d, const orc_params *p, oscratch *s, double ds, int64_t *n
         if (q < 0) continue;
         for (int c = 0; c < 3; ++c)
             d->dV[3 * v + c] = d->dV[3 * v + c] + dt * (s->acc[3 * v + c] - s->acc[3 * q + c]);
+    }
+    if (y->ext) {
+        current_V(d, s->Vc);
+        com_frame_velocities(y, s->Vc, s->ups, s->vt_new);
+        nsum db;
+        ns_init(&db);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c)
+                ns_add(&db, y->m[i] * (s->fex[3 * i + c] * (0.5 * (s->vt_old[3 * i + c] + s->vt_new[3 * i + c]))));
+        d->dB = d->dB - dt * ns_get(&db);
+        for (int c = 0; c < 3; ++c) d->dvcm[c] = d->dvcm[c] + dt * Fm[c];
     }
     if (p->beta != 0.0) {
         current_V(d, s->Vc);
@@ -473,6 +547,7 @@ static int leapfrog(odiv *d, const orc_params *p, oscratch *s, double H, int nsu
     memset(d->dX, 0, sizeof(double) * 3 * (size_t)n);
     memset(d->dV, 0, sizeof(double) * 3 * (size_t)n);
     d->tau = 0.0; d->dw = 0.0; d->drcm[0] = d->drcm[1] = d->drcm[2] = 0.0;
+    d->dB = 0.0; d->dvcm[0] = d->dvcm[1] = d->dvcm[2] = 0.0;
     double h = H / (double)nsub;
     drift(d, p, s, 0.5 * h);
     for (int k = 0; k < nsub - 1; ++k) {
@@ -486,8 +561,9 @@ static int leapfrog(odiv *d, const orc_params *p, oscratch *s, double H, int nsu
     return ORC_OK;
 }
 
-/* Flattened extrapolated variables: X (3n), V (3n), t, r_cm (3), w. */
-static int nvars(int n) { return 6 * n + 5; }
+/* Flattened extrapolated variables: X (3n), V (3n), t, r_cm (3), w, B, v_cm (3)
+ * (B and v_cm change only under an external perturbation). */
+static int nvars(int n) { return 6 * n + 9; }
 static void pack_state(const ostate *y, double *out) {
     const int n = y->n;
     memcpy(out, y->X, sizeof(double) * 3 * (size_t)n);
@@ -495,6 +571,8 @@ static void pack_state(const ostate *y, double *out) {
     out[6 * n] = y->t;
     out[6 * n + 1] = y->rcm[0]; out[6 * n + 2] = y->rcm[1]; out[6 * n + 3] = y->rcm[2];
     out[6 * n + 4] = y->w;
+    out[6 * n + 5] = y->B;
+    out[6 * n + 6] = y->vcm[0]; out[6 * n + 7] = y->vcm[1]; out[6 * n + 8] = y->vcm[2];
 }
 static void pack_incr(const odiv *d, double *out) {
     const int n = d->y0->n;
@@ -503,6 +581,8 @@ static void pack_incr(const odiv *d, double *out) {
     out[6 * n] = d->tau;
     out[6 * n + 1] = d->drcm[0]; out[6 * n + 2] = d->drcm[1]; out[6 * n + 3] = d->drcm[2];
     out[6 * n + 4] = d->dw;
+    out[6 * n + 5] = d->dB;
+    out[6 * n + 6] = d->dvcm[0]; out[6 * n + 7] = d->dvcm[1]; out[6 * n + 8] = d->dvcm[2];
 }
 /* y += increments */
 static void apply_incr(ostate *y, const double *in) {
@@ -511,6 +591,8 @@ static void apply_incr(ostate *y, const double *in) {
     y->t = y->t + in[6 * n];
     for (int c = 0; c < 3; ++c) y->rcm[c] = y->rcm[c] + in[6 * n + 1 + c];
     y->w = y->w + in[6 * n + 4];
+    y->B = y->B + in[6 * n + 5];
+    for (int c = 0; c < 3; ++c) y->vcm[c] = y->vcm[c] + in[6 * n + 6 + c];
 }
 
 /* Aitken-Neville polynomial extrapolation to h -> 0 in the variable h^2
@@ -550,7 +632,8 @@ static double norm_k(const double *a, int k) {
 }
 
 /* Error measure of eq. gbs-criterion (READING): for every variable group g
- * (each X_v and each V_v as a 3-vector; t; r_cm; w when beta != 0)
+ * (each X_v and each V_v as a 3-vector; t; r_cm; w when beta != 0; B and
+ * v_cm under an external perturbation)
  *   eps_g = |dS_g| / |S_g(s0) + (H/n) S'_g(s0)|,
  * skipped when the denominator is zero; eps = max_g eps_g.  A non-finite
  * value anywhere gives eps = +inf. */
@@ -558,7 +641,7 @@ static double gbs_error(const ostate *y0, const double *dS, const double *S0, co
                         double hn, int beta_on) {
     const int n = y0->n;
     double eps = 0.0;
-    for (int g = 0; g < 2 * n + 2 + (beta_on ? 1 : 0); ++g) {
+    for (int g = 0; g < 2 * n + 5; ++g) {
         int off, k;
         if (g < 2 * n) {
             int v = g % n;
@@ -566,7 +649,9 @@ static double gbs_error(const ostate *y0, const double *dS, const double *S0, co
             off = 3 * g; k = 3;   /* X rows 0..n-1, V rows n..2n-1 */
         } else if (g == 2 * n) { off = 6 * n; k = 1; }
         else if (g == 2 * n + 1) { off = 6 * n + 1; k = 3; }
-        else { off = 6 * n + 4; k = 1; }
+        else if (g == 2 * n + 2) { if (!beta_on) continue; off = 6 * n + 4; k = 1; }
+        else if (g == 2 * n + 3) { if (!y0->ext) continue; off = 6 * n + 5; k = 1; }
+        else { if (!y0->ext) continue; off = 6 * n + 6; k = 3; }
         double num[3], den[3];
         for (int c = 0; c < k; ++c) {
             num[c] = dS[off + c];
@@ -597,6 +682,17 @@ static int start_eval(ostate *y, const orc_params *p, oscratch *s, double *S0, d
     double T0 = com_frame_velocities(y, y->V, s->ups, s->vt_old);
     double gd = (p->alpha * (T0 + y->B) + p->beta * y->w) + p->gamma;
     double gk = (p->alpha * U0 + p->beta * Om0) + p->gamma;
+    double Fm[3] = {0.0, 0.0, 0.0};
+    if (y->ext) {
+        external_at(y, y->rcm, p, s, Fm);
+        for (int k = 0; k < 3 * n; ++k) s->acc[k] = s->acc[k] + s->fex[k];
+        nsum db;
+        ns_init(&db);
+        for (int i = 0; i < n; ++i)
+            for (int c = 0; c < 3; ++c) ns_add(&db, y->m[i] * (s->fex[3 * i + c] * s->vt_old[3 * i + c]));
+        dS0[6 * n + 5] = -ns_get(&db) / gk;
+        for (int c = 0; c < 3; ++c) dS0[6 * n + 6 + c] = Fm[c] / gk;
+    }
     for (int v = 0; v < n; ++v) {
         int q = y->parent[v];
         if (q < 0) continue;
@@ -690,6 +786,7 @@ static int make_state(ostate *y, int n, const double *m, int *parent, int *level
     y->X = X; y->V = V;
     if (orc_tree_levels(n, parent, level, order) < 0) return ORC_E_INVAL;
     y->t = scal[0]; y->B = scal[1]; y->w = scal[2];
+    y->ext = NULL;
     for (int c = 0; c < 3; ++c) { y->rcm[c] = scal[3 + c]; y->vcm[c] = scal[6 + c]; }
     return ORC_OK;
 }
@@ -862,11 +959,22 @@ static int all_finite(int k, const double *a) {
  * at t_reached. */
 static int integrate_impl(int n, const double *m, double *x, double *v, double t0, double t_end,
                           const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
-                          int32_t *rec_par, int64_t *n_rec);
+                          int32_t *rec_par, int64_t *n_rec, const orc_ext *ext);
 
 int orc_integrate(int n, const double *m, double *x, double *v, double t0, double t_end,
                   const orc_params *p, orc_stats *st) {
-    return integrate_impl(n, m, x, v, t0, t_end, p, st, -1, NULL, NULL, NULL);
+    return integrate_impl(n, m, x, v, t0, t_end, p, st, -1, NULL, NULL, NULL, NULL);
+}
+
+/* The driver under the external perturbation of ext_accel (Sec. 2.1):
+ * g[3] and np points pt[np][5] = (M, X, Y, Z, b).  Only with beta = 0. */
+int orc_integrate_ext(int n, const double *m, double *x, double *v, double t0, double t_end,
+                      const orc_params *p, int np, const double *g, const double *pt, orc_stats *st) {
+    if (np < 0 || (np > 0 && !pt) || !g || p->beta != 0.0) return ORC_E_INVAL;
+    orc_ext e;
+    e.np = np; e.pt = pt;
+    for (int c = 0; c < 3; ++c) e.g[c] = g[c];
+    return integrate_impl(n, m, x, v, t0, t_end, p, st, -1, NULL, NULL, NULL, &e);
 }
 
 /* The driver with a record of its accepted steps, for the frozen-controller
@@ -877,12 +985,12 @@ int orc_integrate_rec(int n, const double *m, double *x, double *v, double t0, d
                       const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
                       int32_t *rec_par, int64_t *n_rec) {
     if (max_acc < 1 || !rec_H || !rec_par || !n_rec) return ORC_E_INVAL;
-    return integrate_impl(n, m, x, v, t0, t_end, p, st, max_acc, rec_H, rec_par, n_rec);
+    return integrate_impl(n, m, x, v, t0, t_end, p, st, max_acc, rec_H, rec_par, n_rec, NULL);
 }
 
 static int integrate_impl(int n, const double *m, double *x, double *v, double t0, double t_end,
                           const orc_params *p, orc_stats *st, int64_t max_acc, double *rec_H,
-                          int32_t *rec_par, int64_t *n_rec) {
+                          int32_t *rec_par, int64_t *n_rec, const orc_ext *ext) {
     memset(st, 0, sizeof(*st));
     if (n_rec) *n_rec = 0;
     st->t_reached = t0;
@@ -908,6 +1016,7 @@ static int integrate_impl(int n, const double *m, double *x, double *v, double t
     ostate y;
     make_state(&y, n, m, parent, level, order, X, V, scal);
     y.t = t0;
+    y.ext = ext;
     {
         double U0, Om0;
         rc = eval_force(&y, y.X, p, &s, &U0, &Om0);
