@@ -122,6 +122,35 @@ const char *mstar_last_error(const mstar_ctx *ctx);
 int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
                     double *x, double *v, double t0, double t_end, mstar_stats *stats);
 
+/* External perturbation of the N-body system (Sec. 2.1: a position-dependent
+ * acceleration f_i(r_i) added to the Newtonian one).  The field offered:
+ *   f(r) = g + G sum_k M_k (R_k - r) / (|R_k - r|^2 + b_k^2)^(3/2),
+ * a uniform acceleration plus n_point fixed Plummer-softened point masses,
+ * point[k] = {M_k, X_k, Y_k, Z_k, b_k} in host memory (M_k >= 0, b_k >= 0;
+ * b_k = 0 is a bare point mass).  Caller-owned; read during the call only. */
+#define MSTAR_MAX_EXT_POINTS 16
+typedef struct {
+    uint32_t struct_size;      /* sizeof(mstar_external) */
+    int32_t n_point;           /* 0 .. MSTAR_MAX_EXT_POINTS */
+    double g[3];
+    const double *point;       /* [n_point][5], may be NULL when n_point = 0 */
+} mstar_external;
+
+/* mstar_integrate under the external field *ext (Sec. 2.1).  Each kick adds
+ * f_i to every body's acceleration and to the centre-of-mass velocity (as
+ * F/M, F = sum m_i f_i); since f is constant over a kick, the binding energy
+ * B = -(T - U) of the internal motion takes the field's work exactly,
+ * B -= dt sum_i m_i f_i . (v_i_old + v_i_new)/2 with centre-of-mass-frame
+ * velocities.  B and v_cm are extrapolated and error-tested with the rest of
+ * the state.  Arguments, layout, ownership and errors as mstar_integrate, and
+ * MSTAR_E_INVAL for a NULL, wrongly sized or non-finite field, a negative
+ * mass or softening, or n_point out of range; MSTAR_E_UNSUPPORTED with
+ * beta != 0.  A body exactly on an unsoftened point mass makes f infinite;
+ * the step then fails to converge (MSTAR_E_NOCONV). */
+int mstar_integrate_ext(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m,
+                        double *x, double *v, double t0, double t_end, const mstar_external *ext,
+                        mstar_stats *stats);
+
 /* ---- stage entry points (each is one row of the method; used by parity
  * tests, the benchmark and callers that drive the steps themselves) ---- */
 

@@ -67,6 +67,8 @@ struct mstar_ctx {
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
+    bool ext_on = false;               // an external field applies to the running integration
+    ExtField h_ext{};                  // host copy of that field
     // frozen-controller replay and adjoint (kernels_adjoint.hip)
     std::vector<void *> a_allocs;
     int a_n = 0, a_kf = 0;
@@ -182,6 +184,49 @@ int ensure_ttl(mstar_ctx *ctx) {
         d.opart = nullptr; d.Opart = nullptr; d.wpart = nullptr;
         return rc;
     }
+    return MSTAR_OK;
+}
+
+// Buffers of the external field, allocated on the first perturbed integration
+// at the current capacity.
+int ensure_ext(mstar_ctx *ctx) {
+    Dev &d = ctx->d;
+    if (d.fext) return MSTAR_OK;
+    const size_t N = (size_t)ctx->cap_n;
+    const size_t nkwg4 = (N + kWG / 4 - 1) / (kWG / 4);
+    int rc;
+    if ((rc = dalloc(ctx, &d.ext, 1)) || (rc = dalloc(ctx, &d.fext, (size_t)kMaxDiv * N)) ||
+        (rc = dalloc(ctx, &d.fpart, (size_t)kMaxDiv * nkwg4)) || (rc = dalloc(ctx, &d.bpart, (size_t)kMaxDiv * nkwg4))) {
+        d.ext = nullptr; d.fext = nullptr; d.fpart = nullptr; d.bpart = nullptr;
+        return rc;
+    }
+    return MSTAR_OK;
+}
+
+// Validate an external field and stage it in ctx->h_ext (G folded into the
+// point masses, softening squared).
+int stage_ext(mstar_ctx *ctx, const mstar_params *p, const mstar_external *e) {
+    if (e->struct_size != sizeof(mstar_external)) return fail(ctx, MSTAR_E_INVAL, "external: bad struct_size");
+    if (e->n_point < 0 || e->n_point > MSTAR_MAX_EXT_POINTS)
+        return fail(ctx, MSTAR_E_INVAL, "external: n_point must be in [0, %d]", MSTAR_MAX_EXT_POINTS);
+    if (e->n_point > 0 && !e->point) return fail(ctx, MSTAR_E_INVAL, "external: point is NULL");
+    if (p->beta != 0.0) return fail(ctx, MSTAR_E_UNSUPPORTED, "external: not supported with beta != 0");
+    ExtField h{};
+    for (int c = 0; c < 3; ++c) {
+        if (!std::isfinite(e->g[c])) return fail(ctx, MSTAR_E_INVAL, "external: g must be finite");
+        h.g[c] = e->g[c];
+    }
+    for (int k = 0; k < e->n_point; ++k) {
+        const double *q = e->point + 5 * k;
+        for (int c = 0; c < 5; ++c)
+            if (!std::isfinite(q[c])) return fail(ctx, MSTAR_E_INVAL, "external: point %d is not finite", k);
+        if (q[0] < 0.0 || q[4] < 0.0) return fail(ctx, MSTAR_E_INVAL, "external: point %d needs M, b >= 0", k);
+        h.pt[k][0] = p->G * q[0];
+        h.pt[k][1] = q[1]; h.pt[k][2] = q[2]; h.pt[k][3] = q[3];
+        h.pt[k][4] = q[4] * q[4];
+    }
+    h.np = e->n_point;
+    ctx->h_ext = h;
     return MSTAR_OK;
 }
 
@@ -376,6 +421,7 @@ int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool wi
         if (rc) return rc;
         launch_reduce_start(d, ctx->stream, kBase, p->G, force_parts(ns, p->n_d), d.a0, &d.ctl->U0, ttl_on(p),
                             ttl_on(p));
+        if (ctx->ext_on) launch_ext(d, ctx->stream, sl, 1);
         if (nforce) ++*nforce;
     }
     HIPCK(hipGetLastError());
@@ -422,12 +468,13 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
             dr.nact++;
             if (s <= nk) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nk; fk.nact++; }
         }
-        if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p));
+        if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p), ctx->ext_on);
         if (!fk.nact) continue;
         const int ns = nsplit_for(d, fk.nact, force_cap(ctx, p->n_d));
         int rc = prof_force(ctx, fk, p->n_d, ns, ttl_on(p));
         if (rc) return rc;
-        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, ttl_of(p));
+        if (ctx->ext_on) launch_ext(d, ctx->stream, fk, 0);
+        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, ttl_of(p), ctx->ext_on);
         if (nforce) *nforce += fk.nact;
     }
     HIPCK(hipGetLastError());
@@ -771,7 +818,7 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     int nl[16];
     for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
     if ((rc = run_divisions(ctx, params, nl, params->k_fix, nullptr))) return rc;
-    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, ttl_of(params), kBase);
+    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, ttl_of(params), kBase, false);
     launch_control(ctx->d, ctx->stream, params->k_fix, params->eta, params->a_gbs, params->f_min, params->f_max);
     launch_commit(ctx->d, ctx->stream, 1, 0);
     HIPCK(hipGetLastError());
@@ -786,10 +833,24 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
 
 // The driver (Sec. 2.4); with rec_H, the fictitious step of every accepted
 // step is recorded and the run stops after max_acc accepted steps.
+static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
+                         double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
+                         int64_t *n_rec, const mstar_external *ext);
+
+// The external field applies for the duration of one integration only.
 static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
                           double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
-                          int64_t *n_rec) {
+                          int64_t *n_rec, const mstar_external *ext = nullptr) {
     if (!ctx) return MSTAR_E_INVAL;
+    const int rc = integrate_run(ctx, params, n, m, x, v, t0, t_end, stats, max_acc, rec_H, n_rec, ext);
+    ctx->ext_on = false;
+    return rc;
+}
+
+static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
+                         double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
+                         int64_t *n_rec, const mstar_external *ext) {
+    ctx->ext_on = false;
     if (n_rec) *n_rec = 0;
     int rc = check_params(ctx, params);
     if (rc) return rc;
@@ -803,8 +864,15 @@ static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n,
     (void)hipSetDevice(ctx->device);
     const uint32_t flags = params->flags;
     const mstar_params &p = *params;
+    if (ext && (rc = stage_ext(ctx, params, ext))) return rc;
     if ((rc = ensure(ctx, (int)n))) return rc;
     if ((rc = load_bodies(ctx, flags, n, m, x, v, params))) return rc;
+    if (ext) {
+        if ((rc = ensure_ext(ctx))) return rc;
+        HIPCK(hipMemcpyAsync(ctx->d.ext, &ctx->h_ext, sizeof(ExtField), hipMemcpyHostToDevice, ctx->stream));
+        launch_ext_minv(ctx->d, ctx->stream);
+        ctx->ext_on = true;
+    }
     const Dev &d = ctx->d;
     const void *xd, *vd;
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
@@ -845,7 +913,7 @@ static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n,
         }
         launch_set_h(d, ctx->stream, H, t_end, 1, ttl_of(&p));
         if ((rc = run_divisions(ctx, &p, nl, p.k_fix, &st.force_evals))) break;
-        launch_extrapolate(d, ctx->stream, p.k_fix, ttl_of(&p), kBase);
+        launch_extrapolate(d, ctx->stream, p.k_fix, ttl_of(&p), kBase, ctx->ext_on);
         launch_control(d, ctx->stream, p.k_fix, p.eta, p.a_gbs, p.f_min, p.f_max);
         launch_commit(d, ctx->stream, 1, 0);
         if ((rc = read_ctl(ctx))) break;
@@ -893,6 +961,13 @@ extern "C" {
 int mstar_integrate(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
                     double t0, double t_end, mstar_stats *stats) {
     return integrate_impl(ctx, params, n, m, x, v, t0, t_end, stats, -1, nullptr, nullptr);
+}
+
+int mstar_integrate_ext(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                        double t0, double t_end, const mstar_external *ext, mstar_stats *stats) {
+    if (!ctx) return MSTAR_E_INVAL;
+    if (!ext) return fail(ctx, MSTAR_E_INVAL, "integrate_ext: ext is NULL");
+    return integrate_impl(ctx, params, n, m, x, v, t0, t_end, stats, -1, nullptr, nullptr, ext);
 }
 
 int mstar_integrate_record(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,

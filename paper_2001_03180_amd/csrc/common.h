@@ -18,6 +18,7 @@ struct __attribute__((aligned(32))) d4 {
 
 constexpr int kMaxDiv = 17;        // k_fix <= 16 divisions plus the start-state slot
 constexpr int kBaseSlot = kMaxDiv - 1;   // slot holding the start state of a GBS step
+constexpr int kMaxExtPoints = 16;   // point masses of an external field
 constexpr int kWG = 256;           // threads per workgroup of the O(N) kernels
 constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, split j-range)
 constexpr int kForceIPL = 1;       // i-bodies per lane in the force kernel (2 and 4 measured slower)
@@ -95,9 +96,21 @@ struct SysScal {           // start-of-step scalars of the integrated state
 
 struct DivScal {           // per-division increments of the scalar variables
     double tau, dw, drcm[3];
-    double dtk;            // TTL: time step of the latest kick
+    double dtk;            // time step of the latest kick
     double dwn;            // TTL: dw including the latest kick (set by the drift after it)
-    double pad;
+    double dB;             // external field: change of B up to the kick before the latest
+    double dBn;            // external field: dB including the latest kick (set by the drift after it)
+    double dvcm[3];        // external field: change of v_cm
+    double pad[4];
+};
+
+// External perturbation (device memory): uniform acceleration g and np fixed
+// Plummer-softened point masses pt[k] = (G M_k, X_k, Y_k, Z_k, b_k^2).
+struct ExtField {
+    double g[3];
+    double Minv;           // 1 / total mass of the system
+    double pt[kMaxExtPoints][5];
+    int32_t np, pad;
 };
 
 // Workspace pointers used by the kernels (device memory).
@@ -129,6 +142,11 @@ struct Dev {
     double *wpart;              // [slot][nkwg4] partial sum_i grad_i Omega . v_i
     d4 *dOm0;                   // [n] grad Omega at the start state
     double *Tpart;              // [slot][nkwg4] (kick: nkwg4 workgroups; commit: nkwg)
+    // external perturbation (allocated on first use)
+    ExtField *ext;
+    d4 *fext;                   // [slot][n] external accelerations at the latest kick's positions
+    d4 *fpart;                  // [slot][nkwg4] partial (sum m f, sum m f . v) per workgroup
+    double *bpart;              // [slot][nkwg4] partial sum m f . (v_old + v_new)/2 of the latest kick
     double *epspart;            // [nkwg + 1]
     int nsplit_max, nkwg, nkwg4;  // nkwg = ceil(n/256), nkwg4 = ceil(n/64)
     // tree scratch
@@ -164,10 +182,12 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot);
 struct Ttl {
     double alpha, beta, gamma;
 };
-void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr);
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr);
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr, bool ex);
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr, bool ex);
+void launch_ext(const Dev &d, hipStream_t s, const SlotList &sl, int at_start);
+void launch_ext_minv(const Dev &d, hipStream_t s);
 void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr);
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot);
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot, bool ex);
 void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max);
 void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot);
 void launch_state_from_cartesian(const Dev &d, hipStream_t s, const double *x, const double *v);

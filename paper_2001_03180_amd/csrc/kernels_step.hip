@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kWG) void k_div_init(Dev d, int ndiv, int base) {
         d.dP[o] = d4{0.0, 0.0, 0.0, 0.0};
         d.dVt[o] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{0.0, 0.0, {0.0, 0.0, 0.0}, 0.0, 0.0, 0.0};
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot] = DivScal{};
 }
 
 void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
@@ -41,10 +41,12 @@ void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot) {
 // P = P0 + dP); t += dt; r_cm += dt v_cm.  With OM (TTL), the w increment of
 // the preceding kick is completed here: dw += dt_kick sum_wg wpart, summed by
 // every workgroup in the same order; block 0 records the result in dwn (the
-// kick copies it to dw before it overwrites dtk and wpart).
-template <bool OM>
+// kick copies it to dw before it overwrites dtk and wpart).  With EX (an
+// external field) the preceding kick's work on B is completed the same way:
+// dB -= dt_kick sum_wg bpart, recorded in dBn; r_cm moves with v_cm + dv_cm.
+template <bool OM, bool EX>
 __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
-    __shared__ double sh[2][kWG / 64];
+    __shared__ double sh[3][kWG / 64];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
     const int n = d.n;
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
         if (after_kick) { av = d.akick[o]; ap = d.akick[(size_t)slot * n + par]; }
     }
     if (live) { vt = d.Vt[o]; p0 = d.P[(size_t)kBaseSlot * n + v]; dp = d.dP[o]; }
-    double T, w = d.sys->w;
+    double T, w = d.sys->w, B = d.sys->B;
     if (sl.first[ai]) {
         T = d.ctl->T0;
     } else {
@@ -79,11 +81,21 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
             w = w + dw;
             if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot].dwn = dw;
         }
+        if constexpr (EX) {
+            const double *bp = d.bpart + (size_t)slot * d.nkwg4;
+            double a = 0.0;
+            for (int k = threadIdx.x; k < d.nkwg4; k += kWG) a = a + bp[k];
+            const double S = block_sum1<kWG>(a, sh[2]);
+            const DivScal &q = d.dscal[slot];
+            const double dB = q.dB - q.dtk * S;
+            B = B + dB;
+            if (blockIdx.x == 0 && threadIdx.x == 0) d.dscal[slot].dBn = dB;
+        }
     }
     const double H = d.ctl->H;
     const double h = H / (double)sl.nsub[ai];
     const double ds = sl.half[ai] ? 0.5 * h : h;
-    const double dt = ds / ((tr.alpha * (T + d.sys->B) + tr.beta * w) + tr.gamma);
+    const double dt = ds / ((tr.alpha * (T + B) + tr.beta * w) + tr.gamma);
     if (edge) {
         if (after_kick) {   // the preceding kick's update of the edge velocity
             const double dtk = d.dscal[slot].dtk;
@@ -107,15 +119,72 @@ __global__ __launch_bounds__(kWG) void k_drift(Dev d, SlotList sl, Ttl tr) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DivScal &q = d.dscal[slot];
         q.tau = q.tau + dt;
-        for (int c = 0; c < 3; ++c) q.drcm[c] = q.drcm[c] + dt * d.sys->vcm[c];
+        if constexpr (EX) {
+            for (int c = 0; c < 3; ++c) q.drcm[c] = q.drcm[c] + dt * (d.sys->vcm[c] + q.dvcm[c]);
+        } else {
+            for (int c = 0; c < 3; ++c) q.drcm[c] = q.drcm[c] + dt * d.sys->vcm[c];
+        }
     }
 }
 
-void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr) {
+void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr, bool ex) {
     dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
-    if (tr.beta != 0.0) k_drift<true><<<grid, kWG, 0, s>>>(d, sl, tr);
-    else k_drift<false><<<grid, kWG, 0, s>>>(d, sl, tr);
+    if (ex) k_drift<false, true><<<grid, kWG, 0, s>>>(d, sl, tr);
+    else if (tr.beta != 0.0) k_drift<true, false><<<grid, kWG, 0, s>>>(d, sl, tr);
+    else k_drift<false, false><<<grid, kWG, 0, s>>>(d, sl, tr);
 }
+
+// External perturbation (Sec. 2.1) at the bodies' positions r_i = r_cm + P_i
+// of every slot in the list (at_start: the start state, r_cm = the system's):
+//   f_i = g + sum_k G M_k (R_k - r_i) / (|R_k - r_i|^2 + b_k^2)^(3/2),
+// stored per body, and per-workgroup partials of sum m_i f_i and of
+// sum m_i f_i . v_i (COM-frame velocities; the start state's dB/dt).
+__global__ __launch_bounds__(kWG) void k_ext(Dev d, SlotList sl, int at_start) {
+    __shared__ double sh[4][kWG / 64];
+    const int slot = sl.slot[blockIdx.y];
+    const int n = d.n;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const size_t o = (size_t)slot * n + v;
+    const ExtField &e = *d.ext;
+    double rc[3];
+    for (int c = 0; c < 3; ++c) rc[c] = at_start ? d.sys->rcm[c] : d.sys->rcm[c] + d.dscal[slot].drcm[c];
+    double mfx = 0.0, mfy = 0.0, mfz = 0.0, mfv = 0.0;
+    if (v < n) {
+        const d4 P = d.P[o], W = d.Vt[o];
+        const double rx = rc[0] + P.x, ry = rc[1] + P.y, rz = rc[2] + P.z;
+        double fx = e.g[0], fy = e.g[1], fz = e.g[2];
+        for (int k = 0; k < e.np; ++k) {
+            const double dx = e.pt[k][1] - rx, dy = e.pt[k][2] - ry, dz = e.pt[k][3] - rz;
+            const double s2 = ((dx * dx + dy * dy) + dz * dz) + e.pt[k][4];
+            const double w = e.pt[k][0] / (s2 * sqrt(s2));
+            fx = fx + w * dx; fy = fy + w * dy; fz = fz + w * dz;
+        }
+        d.fext[o] = d4{fx, fy, fz, 0.0};
+        mfx = P.w * fx; mfy = P.w * fy; mfz = P.w * fz;
+        mfv = P.w * ((fx * W.x + fy * W.y) + fz * W.z);
+    }
+    const double a = block_sum1<kWG>(mfx, sh[0]);
+    const double b = block_sum1<kWG>(mfy, sh[1]);
+    const double c = block_sum1<kWG>(mfz, sh[2]);
+    const double q = block_sum1<kWG>(mfv, sh[3]);
+    if (threadIdx.x == 0) d.fpart[(size_t)slot * d.nkwg4 + blockIdx.x] = d4{a, b, c, q};
+}
+
+void launch_ext(const Dev &d, hipStream_t s, const SlotList &sl, int at_start) {
+    dim3 grid((d.n + kWG - 1) / kWG, sl.nact);
+    k_ext<<<grid, kWG, 0, s>>>(d, sl, at_start);
+}
+
+// 1 / total mass, for the external field's acceleration of the centre of mass.
+__global__ __launch_bounds__(kTreeWG) void k_ext_minv(Dev d) {
+    __shared__ double sh[kTreeWG];
+    double s = 0.0;
+    for (int u = threadIdx.x; u < d.n; u += kTreeWG) s = s + d.m[u];
+    const double M = block_sum<kTreeWG>(s, sh);
+    if (threadIdx.x == 0) d.ext->Minv = 1.0 / M;
+}
+
+void launch_ext_minv(const Dev &d, hipStream_t s) { k_ext_minv<<<1, kTreeWG, 0, s>>>(d); }
 
 // Kick K(ds): dt = ds / (alpha U + beta Omega + gamma); COM-frame velocities
 // v += dt a (as increments dVt, v = v0 + dVt); partial sums of m |v|^2 for the
@@ -124,10 +193,14 @@ void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr) {
 // body's acceleration is then summed from its j-split partials once, not once
 // more for every child.  With OM (TTL)
 // also per-workgroup partials of sum_i grad_i Omega . (v_i_old + v_i_new)/2;
-// the next drift scales them by dt (kept in dtk) into w.
-template <bool OM>
+// the next drift scales them by dt (kept in dtk) into w.  With EX (external
+// field f from k_ext): every body takes a_i + f_i, the COM-frame velocities
+// take dt (a_i + f_i - F/M) with F = sum m f, v_cm takes dt F/M (in dvcm),
+// and per-workgroup partials of sum m_i f_i . (v_i_old + v_i_new)/2 give the
+// work on B, which the next drift scales by dt.
+template <bool OM, bool EX>
 __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, Ttl tr) {
-    __shared__ double sh[4][kWG / 64];
+    __shared__ double sh[8][kWG / 64];
     __shared__ d4 ra[kWG], rc[OM ? kWG : 1];
     const int ai = blockIdx.y;
     const int slot = sl.slot[ai];
@@ -151,13 +224,14 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
             }
         }
     }
-    d4 dvt = sa, v0 = sa, vo = sa;
+    d4 dvt = sa, v0 = sa, vo = sa, fe = sa;
     double mv = 0.0, mo = 0.0;
     if (lead) {
         dvt = d.dVt[o];
         v0 = d.Vt[(size_t)kBaseSlot * n + v];
         mv = d.P[o].w;
         if constexpr (OM) { vo = d.Vt[o]; mo = d.mo[v]; }
+        if constexpr (EX) { vo = d.Vt[o]; fe = d.fext[o]; }
     }
     ra[threadIdx.x] = sa;
     if constexpr (OM) rc[threadIdx.x] = so;
@@ -173,6 +247,19 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
         for (int k = threadIdx.x; k < cnt; k += kWG) q = q + op[k];
         Om = 0.5 * G * block_sum1<kWG>(q, sh[1]);
     }
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    if constexpr (EX) {
+        const d4 *fp = d.fpart + (size_t)slot * d.nkwg4;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int k = threadIdx.x; k < d.nkwg; k += kWG) {
+            const d4 t = fp[k];
+            a = a + t.x; b = b + t.y; c = c + t.z;
+        }
+        const double Minv = d.ext->Minv;
+        Fx = block_sum1<kWG>(a, sh[4]) * Minv;
+        Fy = block_sum1<kWG>(b, sh[5]) * Minv;
+        Fz = block_sum1<kWG>(c, sh[6]) * Minv;
+    }
     const double H = d.ctl->H;
     const double ds = H / (double)sl.nsub[ai];
     const double dt = ds / ((tr.alpha * U + tr.beta * Om) + tr.gamma);
@@ -186,13 +273,22 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
                 so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
             }
         }
-        const double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
+        double ax = G * sa.x, ay = G * sa.y, az = G * sa.z;
+        if constexpr (EX) { ax = ax + fe.x; ay = ay + fe.y; az = az + fe.z; }
         d.akick[o] = d4{ax, ay, az, 0.0};   // the edge velocities take it in the next drift
-        dvt.x = dvt.x + dt * ax;
-        dvt.y = dvt.y + dt * ay;
-        dvt.z = dvt.z + dt * az;
+        if constexpr (EX) {
+            dvt.x = dvt.x + dt * (ax - Fx);
+            dvt.y = dvt.y + dt * (ay - Fy);
+            dvt.z = dvt.z + dt * (az - Fz);
+        } else {
+            dvt.x = dvt.x + dt * ax;
+            dvt.y = dvt.y + dt * ay;
+            dvt.z = dvt.z + dt * az;
+        }
         d.dVt[o] = dvt;
         const d4 vt{v0.x + dvt.x, v0.y + dvt.y, v0.z + dvt.z, 0.0};
+        if constexpr (EX)
+            wl = mv * ((fe.x * (0.5 * (vo.x + vt.x)) + fe.y * (0.5 * (vo.y + vt.y))) + fe.z * (0.5 * (vo.z + vt.z)));
         if constexpr (OM) {
             const double gm = G * mo;
             const double gx = gm * so.x, gy = gm * so.y, gz = gm * so.z;
@@ -207,17 +303,28 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
         const double ws = block_sum1<kWG>(wl, sh[3]);
         if (threadIdx.x == 0) d.wpart[(size_t)slot * d.nkwg4 + blockIdx.x] = ws;
     }
+    if constexpr (EX) {
+        const double bs = block_sum1<kWG>(wl, sh[7]);
+        if (threadIdx.x == 0) d.bpart[(size_t)slot * d.nkwg4 + blockIdx.x] = bs;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DivScal &q = d.dscal[slot];
         if constexpr (OM) q.dw = q.dwn;
+        if constexpr (EX) {
+            q.dB = q.dBn;
+            q.dvcm[0] = q.dvcm[0] + dt * Fx;
+            q.dvcm[1] = q.dvcm[1] + dt * Fy;
+            q.dvcm[2] = q.dvcm[2] + dt * Fz;
+        }
         q.dtk = dt;
     }
 }
 
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr) {
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr, bool ex) {
     dim3 grid((d.n + kWG / 4 - 1) / (kWG / 4), sl.nact);
-    if (tr.beta != 0.0) k_kick<true><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
-    else k_kick<false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
+    if (ex) k_kick<false, true><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
+    else if (tr.beta != 0.0) k_kick<true, false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
+    else k_kick<false, false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
 }
 
 // Step length of this attempt with the end-time clip of Sec. 2.4: the
@@ -314,7 +421,7 @@ __device__ __forceinline__ void extrap3(const d4 *arr, int n, int v, d4 &out, do
 }
 
 template <int KF>
-__global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
+__global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base, int with_ext) {
     __shared__ double sh[kWG];
     const int n = d.n;
     const int v = blockIdx.x * kWG + threadIdx.x;
@@ -338,7 +445,12 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
         const int p = d.parent[v];
         if (p >= 0) {
             const d4 X0 = d.X0[v], V0 = d.V0[v];
-            const d4 av = d.a0[v], ap = d.a0[p];
+            d4 av = d.a0[v], ap = d.a0[p];
+            if (with_ext) {   // S' of the edge velocities includes the external field
+                const d4 fv = d.fext[(size_t)kBaseSlot * n + v], fp = d.fext[(size_t)kBaseSlot * n + p];
+                av.x = av.x + fv.x; av.y = av.y + fv.y; av.z = av.z + fv.z;
+                ap.x = ap.x + fp.x; ap.y = ap.y + fp.y; ap.z = ap.z + fp.z;
+            }
             const double ex = group_err(xx, xy, xz, X0.x + hn * (V0.x / gd), X0.y + hn * (V0.y / gd),
                                         X0.z + hn * (V0.z / gd));
             const double ev = group_err(vx, vy, vz, V0.x + hn * ((av.x - ap.x) / gk), V0.y + hn * ((av.y - ap.y) / gk),
@@ -356,7 +468,7 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
     if (threadIdx.x == 0) d.epspart[blockIdx.x] = sh[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // scalar groups: t (extrapolated through its increment tau), r_cm
-        // and, with TTL, w
+        // and, with TTL, w; under an external field also B and v_cm
         double pt[KF], rx[KF], ry[KF], rz[KF], pw[KF];
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
@@ -364,7 +476,35 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
             pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2]; pw[k] = q.dwn;
         }
         neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz); neville<KF>(pw);
-        DivScal out{pt[KF - 1], pw[KF - 1], {rx[KF - 1], ry[KF - 1], rz[KF - 1]}, 0.0, 0.0, 0.0};
+        DivScal out{};
+        out.tau = pt[KF - 1];
+        out.dw = pw[KF - 1];
+        out.drcm[0] = rx[KF - 1]; out.drcm[1] = ry[KF - 1]; out.drcm[2] = rz[KF - 1];
+        double eb = 0.0;
+        if (with_ext) {
+            double pb[KF], ux[KF], uy[KF], uz[KF];
+#pragma unroll
+            for (int k = 0; k < KF; ++k) {
+                const DivScal q = d.dscal[k];
+                pb[k] = q.dBn; ux[k] = q.dvcm[0]; uy[k] = q.dvcm[1]; uz[k] = q.dvcm[2];
+            }
+            neville<KF>(pb); neville<KF>(ux); neville<KF>(uy); neville<KF>(uz);
+            out.dB = pb[KF - 1];
+            out.dvcm[0] = ux[KF - 1]; out.dvcm[1] = uy[KF - 1]; out.dvcm[2] = uz[KF - 1];
+            // start-state rates: dB/ds = -sum m f.v / g_k, dv_cm/ds = F / (M g_k)
+            const d4 *fp = d.fpart + (size_t)kBaseSlot * d.nkwg4;
+            double F[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < d.nkwg; ++k) {
+                const d4 t = fp[k];
+                F[0] = F[0] + t.x; F[1] = F[1] + t.y; F[2] = F[2] + t.z; F[3] = F[3] + t.w;
+            }
+            const double Minv = d.ext->Minv;
+            const SysScal &y0 = *d.sys;
+            eb = fmax_nan(group_err(pb[KF - 1] - pb[KF - 2], 0.0, 0.0, y0.B + hn * (-F[3] / gk), 0.0, 0.0),
+                          group_err(ux[KF - 1] - ux[KF - 2], uy[KF - 1] - uy[KF - 2], uz[KF - 1] - uz[KF - 2],
+                                    y0.vcm[0] + hn * (F[0] * Minv / gk), y0.vcm[1] + hn * (F[1] * Minv / gk),
+                                    y0.vcm[2] + hn * (F[2] * Minv / gk)));
+        }
         *d.dscal1 = out;
         const SysScal &y = *d.sys;
         const double et = group_err(pt[KF - 1] - pt[KF - 2], 0.0, 0.0, y.t + hn * (1.0 / gd), 0.0, 0.0);
@@ -374,14 +514,15 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base) {
         double es = fmax_nan(et, er);
         if (tr.beta != 0.0)
             es = fmax_nan(es, group_err(pw[KF - 1] - pw[KF - 2], 0.0, 0.0, y.w + hn * (c.dw0 / gk), 0.0, 0.0));
+        if (with_ext) es = fmax_nan(es, eb);
         d.epspart[d.nkwg] = es;
     }
 }
 
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base) {
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base, bool ex) {
     const int nb = (d.n + kWG - 1) / kWG;
     switch (kf) {
-#define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, tr, base); break;
+#define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, tr, base, ex ? 1 : 0); break;
         KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
         KFC(15) KFC(16)
 #undef KFC
@@ -451,7 +592,11 @@ __global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot
         SysScal &y = *d.sys;
         y.t = y.t + q.tau;
         y.w = y.w + (from_extrap ? q.dw : q.dwn);
-        for (int c = 0; c < 3; ++c) y.rcm[c] = y.rcm[c] + q.drcm[c];
+        y.B = y.B + (from_extrap ? q.dB : q.dBn);
+        for (int c = 0; c < 3; ++c) {
+            y.rcm[c] = y.rcm[c] + q.drcm[c];
+            y.vcm[c] = y.vcm[c] + q.dvcm[c];
+        }
     }
 }
 

@@ -45,6 +45,14 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("struct_size", "reserved")}
 
 
+class External(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_point", C.c_int32), ("g", C.c_double * 3),
+                ("point", C.POINTER(C.c_double))]
+
+
+MAX_EXT_POINTS = 16
+
+
 class BatchConfig(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("wave_lanes", C.c_int32), ("wave_max_n", C.c_int32),
@@ -71,6 +79,8 @@ EXPORTS = {
     "mstar_last_error": (C.c_char_p, [C.c_void_p]),
     "mstar_integrate": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_double, C.c_double, C.POINTER(Stats)]),
+    "mstar_integrate_ext": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_double, C.c_double, C.POINTER(External), C.POINTER(Stats)]),
     "mstar_mst_build": (C.c_int, [C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "mstar_force": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -293,6 +303,31 @@ class Context:
         st.struct_size = C.sizeof(Stats)
         rc = lib().mstar_integrate(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), float(t_end),
                                    C.byref(st))
+        self._check(rc, allow)
+        return x, v, rc, st.as_dict()
+
+    def integrate_ext(self, m, x, v, t0, t_end, g=(0.0, 0.0, 0.0), points=None, p: Params | None = None,
+                      allow=(OK, W_TIME_TOL)):
+        """integrate() under an external field: uniform acceleration g and
+        fixed Plummer-softened point masses points[k] = (M, X, Y, Z, b)."""
+        p = p or params()
+        n = len(m)
+        x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
+        v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
+        a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
+        p.flags = _mode(*a)
+        pts = np.ascontiguousarray(np.zeros((0, 5)) if points is None else np.asarray(points, dtype=np.float64)
+                                   .reshape(-1, 5))
+        e = External()
+        e.struct_size = C.sizeof(External)
+        e.n_point = len(pts)
+        for c, gc in enumerate(np.asarray(g, dtype=np.float64).reshape(3)):
+            e.g[c] = float(gc)
+        e.point = pts.ctypes.data_as(C.POINTER(C.c_double)) if len(pts) else None
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().mstar_integrate_ext(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), float(t_end),
+                                       C.byref(e), C.byref(st))
         self._check(rc, allow)
         return x, v, rc, st.as_dict()
 

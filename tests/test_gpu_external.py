@@ -1,0 +1,180 @@
+"""GPU integration under an external perturbation (Sec. 2.1: f_i(r_i) added
+to the Newtonian acceleration, the binding energy B taking the work of f
+analytically over each kick) vs the CPU oracle, through the C ABI.
+
+Tolerances as for the free integrations: states within 1e-10 of the state
+scale inside the predictability horizon; the conservation laws of the
+perturbed system (energy with the field's potential, angular momentum about
+a single point mass) to 1e-11, as the oracle's own pins."""
+import sys
+
+import numpy as np
+import pytest
+
+import ics
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_03180_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2001_03180_amd as M
+    return M
+
+
+def _com(m, a):
+    return (m[:, None] * a).sum(0) / m.sum()
+
+
+def _rel_err(xg, vg, xo, vo, m):
+    R = np.abs(xo - _com(m, xo)).max()
+    V = np.abs(vo - _com(m, vo)).max()
+    return np.abs(xg - xo).max() / R, np.abs(vg - vo).max() / V
+
+
+def _cluster_near_mass():
+    m, x, v, _ = ics.workload("plummer32")
+    pts = np.array([[5.0, 4.0, 0.0, 0.0, 0.5]])
+    vc = np.sqrt(5.0 * 16.0 / (16.0 + 0.25) ** 1.5)
+    return m, x, v + np.array([0.0, vc, 0.0]), pts
+
+
+def _phi(r, pts, G=1.0):
+    out = np.zeros(len(r))
+    for M_, X, Y, Z, b in pts:
+        d = r - np.array([X, Y, Z])
+        out -= G * M_ / np.sqrt((d * d).sum(1) + b * b)
+    return out
+
+
+@pytest.mark.parametrize("case", ["uniform", "point_mass", "two_points_and_g"])
+def test_external_parity(ctx, orc, M, case):
+    if case == "uniform":
+        m, x, v, _ = ics.workload("plummer32")
+        g, pts, T = np.array([0.3, -0.2, 0.1]), None, 0.3
+    elif case == "point_mass":
+        m, x, v, pts = _cluster_near_mass()
+        g, T = np.zeros(3), 0.3
+    else:
+        m, x, v, _ = ics.workload("plummer32")
+        pts = np.array([[2.0, 3.0, 1.0, 0.0, 0.2], [1.0, -2.0, -2.0, 1.0, 0.0]])
+        g, T = np.array([0.0, 0.05, -0.1]), 0.3
+    say(f"external parity {case}")
+    p = dict(eta=1e-12)
+    xg, vg, rc, st = ctx.integrate_ext(m, x, v, 0.0, T, g=g, points=pts, p=M.params(**p))
+    xg2, vg2, _, _ = ctx.integrate_ext(m, x, v, 0.0, T, g=g, points=pts, p=M.params(**p))
+    assert np.array_equal(xg, xg2) and np.array_equal(vg, vg2)
+    xo, vo, rco, sto = orc.integrate_ext(m, x, v, 0.0, T, g=g, points=pts, p=orc.params(**p))
+    assert rc == rco == 0
+    assert abs(st["t_reached"] - sto["t_reached"]) <= 2e-14 * T
+    assert st["steps_accepted"] == sto["steps_accepted"]
+    ex, ev = _rel_err(xg, vg, xo, vo, m)
+    assert ex <= 1e-10 and ev <= 1e-10, (ex, ev)
+
+
+def test_external_conservation(ctx, orc, M):
+    """Energy with the field's potential and angular momentum about the
+    point mass, over a stretch where the field changes the internal energy by
+    several per cent."""
+    m, x, v, pts = _cluster_near_mass()
+    say("external conservation T=1")
+    x1, v1, rc, st = ctx.integrate_ext(m, x, v, 0.0, 1.0, points=pts, p=M.params(eta=1e-12))
+    assert rc == 0
+
+    def etot(xx, vv):
+        return orc.diagnostics(m, xx, vv)["E"] + float((m * _phi(xx, pts)).sum())
+
+    def lz(xx, vv):
+        return (m[:, None] * np.cross(xx - pts[0, 1:4], vv)).sum(0)
+
+    assert abs(etot(x1, v1) / etot(x, v) - 1) <= 1e-11
+    L0 = lz(x, v)
+    assert np.abs(lz(x1, v1) - L0).max() <= 1e-11 * np.abs(L0).max()
+    ein0 = orc.diagnostics(m, x - _com(m, x), v - _com(m, v))["E"]
+    ein1 = orc.diagnostics(m, x1 - _com(m, x1), v1 - _com(m, v1))["E"]
+    assert abs(ein1 / ein0 - 1) > 1e-2
+
+
+def test_uniform_field_com_parabola(ctx, M):
+    m, x, v, _ = ics.workload("plummer32")
+    v = v + np.array([0.2, 0.0, -0.1])
+    g = np.array([0.3, -0.2, 0.1])
+    T = 0.5
+    say("uniform field vs free")
+    x0, v0, _, _ = ctx.integrate(m, x, v, 0.0, T, M.params(eta=1e-12))
+    x1, v1, _, _ = ctx.integrate_ext(m, x, v, 0.0, T, g=g, p=M.params(eta=1e-12))
+    R = np.abs(x0 - _com(m, x0)).max()
+    assert np.abs((x1 - _com(m, x1)) - (x0 - _com(m, x0))).max() <= 1e-11 * R
+    rc, vc = _com(m, x), _com(m, v)
+    assert np.abs(_com(m, x1) - (rc + vc * T + 0.5 * g * T * T)).max() <= 1e-13
+    assert np.abs(_com(m, v1) - (vc + g * T)).max() <= 1e-13
+
+
+def test_zero_field_is_the_plain_integration(ctx, M):
+    """f = 0 adds exact zeros on the perturbed path: bit for bit the result
+    of mstar_integrate."""
+    m, x, v, _ = ics.workload("plummer32")
+    say("zero field")
+    a = ctx.integrate(m, x, v, 0.0, 0.2, M.params(eta=1e-12))
+    b = ctx.integrate_ext(m, x, v, 0.0, 0.2, p=M.params(eta=1e-12))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[3]["steps_accepted"] == b[3]["steps_accepted"]
+
+
+def test_external_parity_several_tiles(ctx, orc, M):
+    """N = 379 (two 256-wide workgroups and a ragged tail) in the field of a
+    softened point mass, a short stretch."""
+    m, x, v, _ = ics.timing_cluster(379, 1)
+    pts = np.array([[10.0, 6.0, -2.0, 1.0, 1.0]])
+    say("external parity N=379")
+    xg, vg, rc, st = ctx.integrate_ext(m, x, v, 0.0, 0.02, points=pts, p=M.params(eta=1e-10))
+    xo, vo, rco, sto = orc.integrate_ext(m, x, v, 0.0, 0.02, points=pts, p=orc.params(eta=1e-10))
+    assert rc == rco == 0 and st["steps_accepted"] == sto["steps_accepted"]
+    ex, ev = _rel_err(xg, vg, xo, vo, m)
+    assert ex <= 1e-10 and ev <= 1e-10, (ex, ev)
+
+
+def test_external_device_pointers(ctx, M):
+    import torch
+    m, x, v, pts = _cluster_near_mass()
+    say("external device pointers")
+    a = ctx.integrate_ext(m, x, v, 0.0, 0.1, points=pts, p=M.params(eta=1e-12))
+    b = ctx.integrate_ext(torch.tensor(m, device="cuda"), torch.tensor(x, device="cuda"),
+                          torch.tensor(v, device="cuda"), 0.0, 0.1, points=pts, p=M.params(eta=1e-12))
+    assert np.array_equal(b[0].cpu().numpy(), a[0]) and np.array_equal(b[1].cpu().numpy(), a[1])
+
+
+def test_external_error_paths(ctx, M):
+    m, x, v, _ = ics.workload("plummer32")
+    say("external error paths")
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_ext(m, x, v, 0.0, 0.1, points=np.ones((17, 5)))
+    assert e.value.code == M.E_INVAL
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_ext(m, x, v, 0.0, 0.1, g=(np.nan, 0.0, 0.0))
+    assert e.value.code == M.E_INVAL
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_ext(m, x, v, 0.0, 0.1, points=[[1.0, 5.0, 0.0, 0.0, -1.0]])
+    assert e.value.code == M.E_INVAL
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_ext(m, x, v, 0.0, 0.1, g=(1.0, 0.0, 0.0), p=M.params(alpha=0.0, beta=1.0, omega_mass_max=1.0))
+    assert e.value.code == M.E_UNSUPPORTED
+    # the context still integrates without a field afterwards
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, 0.05, M.params(eta=1e-12))
+    assert rc == 0
