@@ -39,7 +39,8 @@ struct mstar_ctx {
     int cap_n = 0;
     std::vector<void *> allocs;
     double *xin = nullptr, *vin = nullptr, *xout = nullptr;   // staging [3n]
-    Ctl *h_ctl = nullptr;       // pinned host copies
+    CtlBlock *h_blk = nullptr;  // pinned host copy of the control block
+    Ctl *h_ctl = nullptr;       // its two parts
     SysScal *h_sys = nullptr;
     int32_t *h_flags = nullptr; // [done, rounds]
     int mst_rounds_est = 0;     // Boruvka rounds of the previous build
@@ -143,14 +144,20 @@ int ensure(mstar_ctx *ctx, int n) {
 #define A(ptr, cnt) \
     if ((rc = dalloc(ctx, &(ptr), (cnt))) != MSTAR_OK) { free_workspace(ctx); return rc; }
     A(d.parent, N) A(d.level, N) A(d.parent_new, N) A(d.level_new, N) A(d.child_off, N + 1) A(d.child_idx, N)
-    A(d.root, 1) A(d.X0, N) A(d.V0, N) A(d.a0, N) A(d.m, N) A(d.sys, 1) A(d.ctl, 1)
+    CtlBlock *cb = nullptr;
+    int32_t *flags2 = nullptr;
+    A(d.root, 1) A(d.X0, N) A(d.V0, N) A(d.a0, N) A(d.m, N) A(cb, 1) A(flags2, 2)
+    d.ctl = &cb->ctl;
+    d.sys = &cb->sys;
+    d.done = flags2;
+    d.rounds = flags2 + 1;
     A(d.P, kMaxDiv * N) A(d.Vt, kMaxDiv * N) A(d.dX, kMaxDiv * N) A(d.dV, kMaxDiv * N) A(d.dX1, N) A(d.dV1, N)
     A(d.dP, kMaxDiv * N) A(d.dVt, kMaxDiv * N) A(d.dP1, N) A(d.dVt1, N) A(d.akick, kMaxDiv * N)
     A(d.dscal, kMaxDiv) A(d.dscal1, 1) A(d.part, (size_t)kMaxDiv * kNsplitMax * N)
     A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, nkwg + 1)
     A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)
-    A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.rounds, 1) A(d.comp, N) A(d.ecomp_tmp, N)
-    A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.done, 1) A(d.ncomp, 1)
+    A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.comp, N) A(d.ecomp_tmp, N)
+    A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.ncomp, 1)
     A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
     A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N) A(d.mo, N) A(d.dOm0, N)
     A(ctx->xin, 3 * N) A(ctx->vin, 3 * N) A(ctx->xout, 3 * N)
@@ -406,9 +413,11 @@ int zero_base_increments(mstar_ctx *ctx) {
 // (a0, U0) for S'(s0) of eq. gbs-criterion and the end-time clip.
 int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool with_force, int64_t *nforce) {
     const Dev &d = ctx->d;
-    int rc0 = zero_base_increments(ctx);
-    if (rc0) return rc0;
     if (transform) {
+        // the start slot's edge increments stay zero (only division slots
+        // are drifted), so clearing them with each transform is enough
+        int rc0 = zero_base_increments(ctx);
+        if (rc0) return rc0;
         launch_tree_sums(d, ctx->stream, d.X0, d.V0, d.tsA, d.tsB);
         launch_com_frame(d, ctx->stream, kBase);
     }
@@ -482,8 +491,8 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
 }
 
 int read_ctl(mstar_ctx *ctx) {
-    HIPCK(hipMemcpyAsync(ctx->h_ctl, ctx->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCK(hipMemcpyAsync(ctx->h_sys, ctx->d.sys, sizeof(SysScal), hipMemcpyDeviceToHost, ctx->stream));
+    // one copy: Ctl and SysScal are adjacent in the device control block
+    HIPCK(hipMemcpyAsync(ctx->h_blk, ctx->d.ctl, sizeof(CtlBlock), hipMemcpyDeviceToHost, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
     return MSTAR_OK;
 }
@@ -495,13 +504,14 @@ int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in) {
     const Dev &d = ctx->d;
     int maxr = 2;
     for (int m = 1; m < d.n; m <<= 1) ++maxr;
-    const int ns = std::max(1, std::min(8, d.n / 64));   // j-splits of the Boruvka scan
+    // j-splits of the Boruvka scan: 16 gives every SIMD enough waves to hide the
+    // j loads at N ~ 5e3 (8 left the scan latency-bound: 1.5% of the step)
+    const int ns = std::max(1, std::min(16, d.n / 64));
     launch_mst_init(d, ctx->stream, pos, root_in);
     int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est, maxr) : maxr - 2;
     launch_mst_rounds(d, ctx->stream, pos, est, ns);
     for (int extra = 0;; ++extra) {
-        HIPCK(hipMemcpyAsync(ctx->h_flags, d.done, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCK(hipMemcpyAsync(ctx->h_flags + 1, d.rounds, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipMemcpyAsync(ctx->h_flags, d.done, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));  // done, rounds
         HIPCK(hipStreamSynchronize(ctx->stream));
         if (ctx->h_flags[0]) break;
         if (est + extra >= 4 * maxr) return fail(ctx, MSTAR_E_DEVICE, "MST did not complete");
@@ -625,12 +635,13 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return MSTAR_E_DEVICE; }
         ctx->own_stream = true;
     }
-    if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_sys, sizeof(SysScal), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void **)&ctx->h_blk, sizeof(CtlBlock), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         mstar_destroy(ctx);
         return MSTAR_E_NOMEM;
     }
+    ctx->h_ctl = &ctx->h_blk->ctl;
+    ctx->h_sys = &ctx->h_blk->sys;
     if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         ctx->num_cu <= 0 || hipEventCreate(&ctx->b_ev[0]) != hipSuccess ||
         hipEventCreate(&ctx->b_ev[1]) != hipSuccess) {
@@ -662,8 +673,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     for (hipEvent_t e : ctx->b_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
-    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
-    if (ctx->h_sys) (void)hipHostFree(ctx->h_sys);
+    if (ctx->h_blk) (void)hipHostFree(ctx->h_blk);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

@@ -94,6 +94,11 @@ struct SysScal {           // start-of-step scalars of the integrated state
     double rcm[3], vcm[3];
 };
 
+struct CtlBlock {          // Ctl and SysScal side by side: one read-back per GBS step
+    Ctl ctl;
+    SysScal sys;
+};
+
 struct DivScal {           // per-division increments of the scalar variables
     double tau, dw, drcm[3];
     double dtk;            // time step of the latest kick
