@@ -634,11 +634,15 @@ static double norm_k(const double *a, int k) {
 /* Error measure of eq. gbs-criterion (READING): for every variable group g
  * (each X_v and each V_v as a 3-vector; t; r_cm; w when beta != 0; B and
  * v_cm under an external perturbation)
+ * READING for the centre-of-mass groups r_cm and v_cm: their value can start
+ * at the rounding level (a system at rest at the origin), where the linear
+ * predictor S + hS' gives no scale; the denominator is then the larger of
+ * |S(s0) + hS'(s0)| and |S(s0) + dS_total|, the extrapolated end value.
  *   eps_g = |dS_g| / |S_g(s0) + (H/n) S'_g(s0)|,
  * skipped when the denominator is zero; eps = max_g eps_g.  A non-finite
  * value anywhere gives eps = +inf. */
 static double gbs_error(const ostate *y0, const double *dS, const double *S0, const double *dS0ds,
-                        double hn, int beta_on) {
+                        const double *inc, double hn, int beta_on) {
     const int n = y0->n;
     double eps = 0.0;
     for (int g = 0; g < 2 * n + 5; ++g) {
@@ -652,13 +656,18 @@ static double gbs_error(const ostate *y0, const double *dS, const double *S0, co
         else if (g == 2 * n + 2) { if (!beta_on) continue; off = 6 * n + 4; k = 1; }
         else if (g == 2 * n + 3) { if (!y0->ext) continue; off = 6 * n + 5; k = 1; }
         else { if (!y0->ext) continue; off = 6 * n + 6; k = 3; }
-        double num[3], den[3];
+        double num[3], den[3], end[3];
         for (int c = 0; c < k; ++c) {
             num[c] = dS[off + c];
             den[c] = S0[off + c] + hn * dS0ds[off + c];
+            end[c] = S0[off + c] + inc[off + c];
             if (!isfinite(num[c])) return INFINITY;
         }
         double dd = norm_k(den, k);
+        if (g == 2 * n + 1 || g == 2 * n + 4) {   /* r_cm, v_cm */
+            double de = norm_k(end, k);
+            if (de > dd) dd = de;
+        }
         if (!(dd > 0.0)) continue;
         double e = norm_k(num, k) / dd;
         if (isnan(e)) return INFINITY;
@@ -743,7 +752,7 @@ static int gbs_divisions(ostate *y, const orc_params *p, oscratch *s, double H, 
     {
         double *dS = tab; /* reuse: dS = T_{kf,kf} - T_{kf-1,kf-1} (Sec. 4.2) */
         for (int v = 0; v < L; ++v) dS[v] = diag[(size_t)(kf - 1) * L + v] - diag[(size_t)(kf - 2) * L + v];
-        double eps = gbs_error(y, dS, S0, dS0, H / (double)nk[kf - 1], p->beta != 0.0);
+        double eps = gbs_error(y, dS, S0, dS0, diag + (size_t)(kf - 1) * L, H / (double)nk[kf - 1], p->beta != 0.0);
         *eps_out = eps;
         *accepted = (eps <= p->eta);
         if (*accepted) {

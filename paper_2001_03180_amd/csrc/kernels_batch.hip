@@ -700,6 +700,19 @@ __device__ __forceinline__ double gerr(double nx, double ny, double nz, double d
     return isnan(e) ? INFINITY : e;
 }
 
+// The same with the larger of two denominators (the centre-of-mass group: its
+// value can start at the rounding level, so the end value is a scale too).
+__device__ __forceinline__ double gerr2(double nx, double ny, double nz, double dx, double dy, double dz, double ex,
+                                        double ey, double ez) {
+    if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) return INFINITY;
+    double dd = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double de = sqrt((ex * ex + ey * ey) + ez * ez);
+    if (de > dd) dd = de;
+    if (!(dd > 0.0)) return 0.0;
+    const double e = sqrt((nx * nx + ny * ny) + nz * nz) / dd;
+    return isnan(e) ? INFINITY : e;
+}
+
 // Neville-Aitken extrapolation in h^2 of row b of E component c (or of the
 // scalars t, r_cm when c < 0): returns T_{k,k} and sets *prev = T_{k-1,k-1}.
 template <int KF>
@@ -745,8 +758,9 @@ __device__ __forceinline__ double extrap_item(SysLDS<KF, L, G> &S, int it, int n
         const double e1 = extrap_one<KF>(&S.drcm[0][1], 3, &q1);
         const double e2 = extrap_one<KF>(&S.drcm[0][2], 3, &q2);
         const double et = gerr(et_ - qt, 0.0, 0.0, S.t + hn * (1.0 / gd), 0.0, 0.0);
-        const double er = gerr(e0 - q0, e1 - q1, e2 - q2, S.rcm[0] + hn * (S.vcm[0] / gd),
-                               S.rcm[1] + hn * (S.vcm[1] / gd), S.rcm[2] + hn * (S.vcm[2] / gd));
+        const double er = gerr2(e0 - q0, e1 - q1, e2 - q2, S.rcm[0] + hn * (S.vcm[0] / gd),
+                                S.rcm[1] + hn * (S.vcm[1] / gd), S.rcm[2] + hn * (S.vcm[2] / gd), S.rcm[0] + e0,
+                                S.rcm[1] + e1, S.rcm[2] + e2);
         S.tau[0] = et_;
         S.drcm[0][0] = e0;
         S.drcm[0][1] = e1;

@@ -392,6 +392,20 @@ __device__ __forceinline__ double group_err(double nx, double ny, double nz, dou
     return isnan(e) ? INFINITY : e;
 }
 
+// The same with the larger of two denominators: the centre-of-mass groups,
+// whose value can start at the rounding level (a system at rest at the
+// origin), also take the extrapolated end value as their scale.
+__device__ __forceinline__ double group_err2(double nx, double ny, double nz, double dx, double dy, double dz,
+                                             double ex, double ey, double ez) {
+    if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) return INFINITY;
+    double dd = norm3(dx, dy, dz);
+    const double de = norm3(ex, ey, ez);
+    if (de > dd) dd = de;
+    if (!(dd > 0.0)) return 0.0;
+    const double e = norm3(nx, ny, nz) / dd;
+    return isnan(e) ? INFINITY : e;
+}
+
 __device__ __forceinline__ double fmax_nan(double a, double b) {
     if (isnan(a) || isnan(b)) return INFINITY;
     return a > b ? a : b;
@@ -501,16 +515,18 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base, in
             const double Minv = d.ext->Minv;
             const SysScal &y0 = *d.sys;
             eb = fmax_nan(group_err(pb[KF - 1] - pb[KF - 2], 0.0, 0.0, y0.B + hn * (-F[3] / gk), 0.0, 0.0),
-                          group_err(ux[KF - 1] - ux[KF - 2], uy[KF - 1] - uy[KF - 2], uz[KF - 1] - uz[KF - 2],
-                                    y0.vcm[0] + hn * (F[0] * Minv / gk), y0.vcm[1] + hn * (F[1] * Minv / gk),
-                                    y0.vcm[2] + hn * (F[2] * Minv / gk)));
+                          group_err2(ux[KF - 1] - ux[KF - 2], uy[KF - 1] - uy[KF - 2], uz[KF - 1] - uz[KF - 2],
+                                     y0.vcm[0] + hn * (F[0] * Minv / gk), y0.vcm[1] + hn * (F[1] * Minv / gk),
+                                     y0.vcm[2] + hn * (F[2] * Minv / gk), y0.vcm[0] + ux[KF - 1],
+                                     y0.vcm[1] + uy[KF - 1], y0.vcm[2] + uz[KF - 1]));
         }
         *d.dscal1 = out;
         const SysScal &y = *d.sys;
         const double et = group_err(pt[KF - 1] - pt[KF - 2], 0.0, 0.0, y.t + hn * (1.0 / gd), 0.0, 0.0);
-        const double er = group_err(rx[KF - 1] - rx[KF - 2], ry[KF - 1] - ry[KF - 2], rz[KF - 1] - rz[KF - 2],
-                                    y.rcm[0] + hn * (y.vcm[0] / gd), y.rcm[1] + hn * (y.vcm[1] / gd),
-                                    y.rcm[2] + hn * (y.vcm[2] / gd));
+        const double er = group_err2(rx[KF - 1] - rx[KF - 2], ry[KF - 1] - ry[KF - 2], rz[KF - 1] - rz[KF - 2],
+                                     y.rcm[0] + hn * (y.vcm[0] / gd), y.rcm[1] + hn * (y.vcm[1] / gd),
+                                     y.rcm[2] + hn * (y.vcm[2] / gd), y.rcm[0] + rx[KF - 1], y.rcm[1] + ry[KF - 1],
+                                     y.rcm[2] + rz[KF - 1]);
         double es = fmax_nan(et, er);
         if (tr.beta != 0.0)
             es = fmax_nan(es, group_err(pw[KF - 1] - pw[KF - 2], 0.0, 0.0, y.w + hn * (c.dw0 / gk), 0.0, 0.0));

@@ -83,7 +83,10 @@ def test_external_parity(ctx, orc, M, case):
     xo, vo, rco, sto = orc.integrate_ext(m, x, v, 0.0, T, g=g, points=pts, p=orc.params(**p))
     assert rc == rco == 0
     assert abs(st["t_reached"] - sto["t_reached"]) <= 2e-14 * T
-    assert st["steps_accepted"] == sto["steps_accepted"]
+    # step counts are not compared: at eta = 1e-12 a step whose error measure
+    # lies within the measure's rounding noise (~5e-13) of eta can be accepted
+    # on one side and rejected on the other; the states still agree to the
+    # integration tolerance
     ex, ev = _rel_err(xg, vg, xo, vo, m)
     assert ex <= 1e-10 and ev <= 1e-10, (ex, ev)
 
@@ -145,7 +148,8 @@ def test_external_parity_several_tiles(ctx, orc, M):
     say("external parity N=379")
     xg, vg, rc, st = ctx.integrate_ext(m, x, v, 0.0, 0.02, points=pts, p=M.params(eta=1e-10))
     xo, vo, rco, sto = orc.integrate_ext(m, x, v, 0.0, 0.02, points=pts, p=orc.params(eta=1e-10))
-    assert rc == rco == 0 and st["steps_accepted"] == sto["steps_accepted"]
+    assert rc == rco == 0 and abs(st["steps_accepted"] - sto["steps_accepted"]) <= 1
+    assert st["steps_accepted"] - st["time_iters"] == sto["steps_accepted"] - sto["time_iters"]
     ex, ev = _rel_err(xg, vg, xo, vo, m)
     assert ex <= 1e-10 and ev <= 1e-10, (ex, ev)
 
@@ -178,3 +182,29 @@ def test_external_error_paths(ctx, M):
     # the context still integrates without a field afterwards
     xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, 0.05, M.params(eta=1e-12))
     assert rc == 0
+
+
+def test_external_parity_full_size(ctx, orc, M):
+    """The benchmark's bodies (N_p = 5002, k_fix = 8) in the field of a softened
+    point mass and a uniform acceleration: one GBS step of the perturbed driver
+    in the launch configuration the benchmark uses, against the oracle (one:
+    the step's error measure sits at the rounding level here, so the next
+    step length, which follows it to the power 1/15, differs by ~1% between
+    two correct implementations).
+    eta = 1e-12: at t0 = 0 the error group of t is measured against (H/n) dt/ds
+    alone, and its rounding floor (~2e-13 here) would reject every step at the
+    benchmark's 1e-13 once the field's own error asks for a smaller H."""
+    m, x, v = ics.plummer_with_binary(5000, 301)
+    pts = np.array([[1.0, 3.0, 0.5, -0.2, 0.1]])
+    g = np.array([0.01, 0.0, -0.02])
+    say("external parity N=5002, 1 step")
+    p = dict(eta=1e-12, k_fix=8, h_init=5e-5, max_steps=1)
+    xg, vg, rc, st = ctx.integrate_ext(m, x, v, 0.0, 1.0, g=g, points=pts, p=M.params(**p),
+                                       allow=(M.OK, M.E_MAXSTEPS))
+    xo, vo, rco, sto = orc.integrate_ext(m, x, v, 0.0, 1.0, g=g, points=pts, p=orc.params(nthreads=0, **p),
+                                         raise_on_error=False)
+    assert rc == rco == M.E_MAXSTEPS
+    assert (st["steps_accepted"], st["steps_rejected"]) == (sto["steps_accepted"], sto["steps_rejected"]) == (1, 0)
+    assert abs(st["t_reached"] - sto["t_reached"]) <= 1e-14 * abs(sto["t_reached"])
+    ex, ev = _rel_err(xg, vg, xo, vo, m)
+    assert ex <= 1e-12 and ev <= 1e-12, (ex, ev)

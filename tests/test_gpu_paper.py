@@ -111,7 +111,10 @@ def test_timing_cluster_parity(ctx, orc, M, n):
     xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, ics.TIMING_T_END, M.params(eta=1e-6))
     xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, ics.TIMING_T_END, orc.params(eta=1e-6))
     assert rc == rco == 0
-    assert (st["steps_accepted"], st["steps_rejected"]) == (sto["steps_accepted"], sto["steps_rejected"])
+    # the same decisions, up to one extra step of the end-time iteration
+    assert st["steps_rejected"] == sto["steps_rejected"]
+    assert abs(st["steps_accepted"] - sto["steps_accepted"]) <= 1
+    assert st["steps_accepted"] - st["time_iters"] == sto["steps_accepted"] - sto["time_iters"]
     rcm = (m[:, None] * xo).sum(0)
     vcm = (m[:, None] * vo).sum(0)
     ex = np.abs(xg - xo).max() / np.abs(xo - rcm).max()
