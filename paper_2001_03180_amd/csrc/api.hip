@@ -157,7 +157,7 @@ int ensure(mstar_ctx *ctx, int n) {
     A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, nkwg + 1)
     A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)
     A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.comp, N) A(d.ecomp_tmp, N)
-    A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.elo, N) A(d.ehi, N) A(d.hooked, N) A(d.ncomp, 1)
+    A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.ncomp, 1)
     A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
     A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N) A(d.mo, N) A(d.dOm0, N)
     A(ctx->xin, 3 * N) A(ctx->vin, 3 * N) A(ctx->xout, 3 * N)

@@ -163,7 +163,7 @@ struct Dev {
     int32_t *rounds;            // Boruvka rounds taken by the last build
     int32_t *comp, *ecomp_tmp;
     unsigned long long *cw, *cidx;
-    int32_t *tgt, *elo, *ehi, *hooked, *done, *ncomp;
+    int32_t *tgt, *done, *ncomp;
     int32_t *deg, *off, *fill, *adj, *arcpos, *nxtA, *nxtB, *rkA, *rkB;
     int32_t *cnt;
     double *scr;                // misc scalar scratch

@@ -85,7 +85,6 @@ __global__ __launch_bounds__(kTreeWG) void k_mst_init(Dev d, const d4 *pos, int 
     const int n = d.n;
     for (int v = threadIdx.x; v < n; v += kTreeWG) {
         d.comp[v] = v;
-        d.hooked[v] = 0;
         d.cw[v] = ~0ull;
         d.cidx[v] = ~0ull;
         d.parent_new[v] = -1;
@@ -219,8 +218,8 @@ __global__ __launch_bounds__(kWG) void k_bor_vreduce(Dev d, int nsplit) {
 
 // Component minimum (tie-break on packed (min, max) indices), hooking with
 // mutual pairs broken toward the smaller representative, contraction, and the
-// count of components (one workgroup; component ids, hook pointers and the
-// parent pointers in LDS when they fit).
+// count of components (one workgroup; component ids, hook pointers, the
+// parent pointers and the per-component best edge in LDS when they fit).
 //
 // Parent pointers are maintained as the components grow: every component's
 // edges point toward one of its bodies (its tree root).  When component c
@@ -230,18 +229,21 @@ __global__ __launch_bounds__(kWG) void k_bor_vreduce(Dev d, int nsplit) {
 // round are applied in parallel.
 template <bool LDS>
 __global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d) {
-    extern __shared__ int lds[];
+    extern __shared__ unsigned long long lds64[];
     __shared__ int cnt;
     if (*d.done) return;
     const int n = d.n;
-    int *comp = LDS ? lds : d.comp;
-    int *hook = LDS ? lds + n : d.fill;
-    int *tgt = LDS ? lds + 2 * n : d.tgt;
-    int *par = LDS ? lds + 3 * n : d.parent_new;
+    int *ib = reinterpret_cast<int *>(lds64 + n);   // LDS: n 64-bit keys, then 4n ints
+    unsigned long long *cidx = LDS ? lds64 : d.cidx;
+    int *comp = LDS ? ib : d.comp;
+    int *hook = LDS ? ib + n : d.fill;
+    int *tgt = LDS ? ib + 2 * n : d.tgt;
+    int *par = LDS ? ib + 3 * n : d.parent_new;
     if (LDS) {
         for (int v = threadIdx.x; v < n; v += kTreeWG) {
             comp[v] = d.comp[v];
             par[v] = d.parent_new[v];
+            cidx[v] = ~0ull;
         }
         __syncthreads();
     }
@@ -252,20 +254,18 @@ __global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d) {
         const int c = comp[i];
         if (j >= 0 && (unsigned long long)__double_as_longlong(mw[i]) == d.cw[c]) {
             const unsigned long long lo = (unsigned)min(i, j), hi = (unsigned)max(i, j);
-            atomicMin(&d.cidx[c], (lo << 32) | hi);
+            atomicMin(&cidx[c], (lo << 32) | hi);
         }
     }
     __threadfence_block();
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += kTreeWG) {
         if (comp[c] != c) continue;
-        const unsigned long long k = d.cidx[c];
+        const unsigned long long k = cidx[c];
         if (k == ~0ull) { tgt[c] = c; continue; }
         const int lo = (int)(k >> 32), hi = (int)(k & 0xffffffffull);
         const bool lo_in = (comp[lo] == c);
         tgt[c] = comp[lo_in ? hi : lo];
-        d.elo[c] = lo_in ? lo : hi;   // endpoint inside c
-        d.ehi[c] = lo_in ? hi : lo;   // endpoint outside c
     }
     __threadfence_block();
     __syncthreads();
@@ -276,9 +276,12 @@ __global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d) {
         if (comp[c] != c) continue;
         const int t = tgt[c];
         if (t == c || (tgt[t] == c && c < t)) { hook[c] = c; continue; }
-        d.hooked[c] = 1;
         hook[c] = t;
-        int prev = d.ehi[c], x = d.elo[c];
+        // the edge's end inside c and the one outside it, again from the key
+        const unsigned long long k = cidx[c];
+        const int lo = (int)(k >> 32), hi = (int)(k & 0xffffffffull);
+        const bool lo_in = (comp[lo] == c);
+        int prev = lo_in ? hi : lo, x = lo_in ? lo : hi;
         for (int it = 0; it < n && x >= 0; ++it) {
             const int nx = par[x];
             par[x] = prev;
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kTreeWG) void k_bor_merge(Dev d) {
         if (c == v) {
             ++local;
             d.cw[v] = ~0ull;
-            d.cidx[v] = ~0ull;
+            if (!LDS) d.cidx[v] = ~0ull;
         }
     }
     atomicAdd(&cnt, local);
@@ -573,7 +576,7 @@ void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, i
     for (int r = 0; r < rounds; ++r) {
         k_bor_scan<<<dim3(d.nib, nsplit), 256, 0, s>>>(d, pos, jchunk);
         k_bor_vreduce<<<(d.n + kWG / 4 - 1) / (kWG / 4), kWG, 0, s>>>(d, nsplit);
-        const size_t lds = sizeof(int) * 4 * (size_t)d.n;
+        const size_t lds = (sizeof(unsigned long long) + 4 * sizeof(int)) * (size_t)d.n;
         if (lds <= 150 * 1024) {
             (void)hipFuncSetAttribute((const void *)k_bor_merge<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)lds);
