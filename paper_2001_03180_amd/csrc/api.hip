@@ -242,6 +242,7 @@ bool ttl_on(const mstar_params *p) { return p->beta != 0.0; }
 
 constexpr int kBase = kBaseSlot;     // slot of the start state
 constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
+constexpr int kMstSpareRounds = 1;   // Boruvka rounds queued beyond the previous build's count
 
 // Resident force workgroups on the whole chip (queried once per N_d kind).
 int force_cap(mstar_ctx *ctx, int nd) {
@@ -500,13 +501,21 @@ int read_ctl(mstar_ctx *ctx) {
 // MST of the complete graph on `pos` (Sec. 3.1-3.4): as many Boruvka rounds
 // as the previous build needed, a check of completion on the host, more
 // rounds if needed, then rooting.
-int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in) {
-    const Dev &d = ctx->d;
+// j-splits of the Boruvka scan: 16 gives every SIMD enough waves to hide the
+// j loads at N ~ 5e3 (8 left the scan latency-bound: 1.5% of the step)
+int mst_splits(const Dev &d) { return std::max(1, std::min(16, d.n / 64)); }
+
+// Upper bound on Boruvka rounds (each round at least halves the components).
+int mst_max_rounds(const Dev &d) {
     int maxr = 2;
     for (int m = 1; m < d.n; m <<= 1) ++maxr;
-    // j-splits of the Boruvka scan: 16 gives every SIMD enough waves to hide the
-    // j loads at N ~ 5e3 (8 left the scan latency-bound: 1.5% of the step)
-    const int ns = std::max(1, std::min(16, d.n / 64));
+    return maxr;
+}
+
+int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in) {
+    const Dev &d = ctx->d;
+    const int maxr = mst_max_rounds(d);
+    const int ns = mst_splits(d);
     launch_mst_init(d, ctx->stream, pos, root_in);
     int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est, maxr) : maxr - 2;
     launch_mst_rounds(d, ctx->stream, pos, est, ns);
@@ -532,6 +541,25 @@ int rebuild(mstar_ctx *ctx, const mstar_params *p) {
     const d4 *vel = d.Vt + (size_t)kBase * d.n;
     int rc = build_mst(ctx, pos, -1);
     if (rc) return rc;
+    launch_rebuild_edges(d, ctx->stream, pos, vel, p->n_d);
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+// The same rebuild queued without waiting for the host: one Boruvka round
+// more than the previous build needed, then rooting and the new edge vectors.
+// If the rounds did not finish the tree, those kernels leave the old tree in
+// place and flag it (ctl->tree_bad), the step that follows is not committed,
+// and the driver rebuilds with rebuild() and repeats that step.
+int rebuild_queued(mstar_ctx *ctx, const mstar_params *p) {
+    const Dev &d = ctx->d;
+    const d4 *pos = d.P + (size_t)kBase * d.n;
+    const d4 *vel = d.Vt + (size_t)kBase * d.n;
+    const int maxr = mst_max_rounds(d);
+    const int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est + kMstSpareRounds, maxr) : maxr;
+    launch_mst_init(d, ctx->stream, pos, -1);
+    launch_mst_rounds(d, ctx->stream, pos, est, mst_splits(d));
+    launch_mst_root(d, ctx->stream);
     launch_rebuild_edges(d, ctx->stream, pos, vel, p->n_d);
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -911,7 +939,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
         if (st.steps_accepted + st.steps_rejected >= p.max_steps) { rc = MSTAR_E_MAXSTEPS; break; }
         if (fresh) {
             if (since_rebuild >= p.rebuild_every) {
-                if ((rc = rebuild(ctx, &p))) break;
+                if ((rc = rebuild_queued(ctx, &p))) break;
                 st.mst_rebuilds++;
                 since_rebuild = 0;
                 just_rebuilt = true;
@@ -928,7 +956,19 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
         launch_commit(d, ctx->stream, 1, 0);
         if ((rc = read_ctl(ctx))) break;
         const Ctl &c = *ctx->h_ctl;
-        if (just_rebuilt) { st.topo_changes += c.topo; just_rebuilt = false; }
+        if (just_rebuilt && c.tree_bad) {
+            // the queued Boruvka rounds did not finish the new tree, so the
+            // step ran on the old one and was not committed: rebuild with the
+            // host check and repeat the step with the same H
+            if ((rc = rebuild(ctx, &p))) break;
+            if ((rc = prepare_start(ctx, &p, true, true, &st.force_evals))) break;
+            continue;
+        }
+        if (just_rebuilt) {
+            st.topo_changes += c.topo;
+            just_rebuilt = false;
+            ctx->mst_rounds_est = c.mst_rounds;
+        }
         st.eps_last = c.eps;
         H = c.H;
         if (!c.accepted) {

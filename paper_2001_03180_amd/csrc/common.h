@@ -87,6 +87,8 @@ struct Ctl {               // device control block, read back once per GBS step
     int32_t clipped;
     int32_t coincident;    // a zero-length MST edge was found
     int32_t topo;          // the last rebuild changed the tree
+    int32_t tree_bad;      // the last rebuild's Boruvka rounds did not finish: the old tree is kept
+    int32_t mst_rounds;    // Boruvka rounds of the last finished build
 };
 
 struct SysScal {           // start-of-step scalars of the integrated state

@@ -575,7 +575,8 @@ void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gb
 // of m |v|^2 of the new start state for T.
 __global__ __launch_bounds__(kWG) void k_commit(Dev d, int from_extrap, int slot) {
     __shared__ double sh[kWG];
-    if (from_extrap && !d.ctl->accepted) return;
+    // a step taken while a rebuild had not finished its tree is repeated
+    if (from_extrap && (!d.ctl->accepted || d.ctl->tree_bad)) return;
     const int n = d.n;
     const int v = blockIdx.x * kWG + threadIdx.x;
     const size_t o = (size_t)slot * n + v;
@@ -765,6 +766,7 @@ __global__ void k_set_sys(Dev d, double t, double B, double w, double r0, double
         y.vcm[0] = v0; y.vcm[1] = v1; y.vcm[2] = v2;
     }
     d.ctl->coincident = 0;
+    d.ctl->tree_bad = 0;
 }
 void launch_set_sys(const Dev &d, hipStream_t s, double t, double B, double w, const double *rcm, const double *vcm,
                     int set_com) {

@@ -424,6 +424,14 @@ __global__ __launch_bounds__(kFinWG) void k_mst_finish(Dev d) {
     extern __shared__ int lds[];
     __shared__ int sh[kFinWG];
     __shared__ int any;
+    // rounds launched without a host check may not have finished the tree:
+    // then nothing is changed and the old tree stays (tree_bad)
+    const int fin = *d.done;
+    if (threadIdx.x == 0) {
+        d.ctl->tree_bad = fin ? 0 : 1;
+        if (fin) d.ctl->mst_rounds = *d.rounds;
+    }
+    if (!fin) return;
     const int n = d.n;
     const int root = *d.root;
     int *par = LDS ? lds : d.parent_new;          // n
@@ -646,7 +654,7 @@ __device__ d4 sep_rule(int i, int j, const int32_t *par, const int32_t *lev, con
 __global__ __launch_bounds__(kWG) void k_rebuild_edges(Dev d, const d4 *rho, const d4 *ups, int nd) {
     const int n = d.n;
     const int u = blockIdx.x * kWG + threadIdx.x;
-    if (u >= n) return;
+    if (u >= n || d.ctl->tree_bad) return;
     const int q = d.parent_new[u];
     d4 X{0.0, 0.0, 0.0, 0.0}, V{0.0, 0.0, 0.0, 0.0};
     if (q >= 0) {
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(kWG) void k_rebuild_edges(Dev d, const d4 *rho, con
 __global__ __launch_bounds__(kWG) void k_swap_tree(Dev d) {
     const int n = d.n;
     const int u = blockIdx.x * kWG + threadIdx.x;
-    if (u >= n) return;
+    if (u >= n || d.ctl->tree_bad) return;
     d.X0[u] = d.tsC[u];
     d.V0[u] = d.tsD[u];
     d.parent[u] = d.parent_new[u];
