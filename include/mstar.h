@@ -49,12 +49,15 @@ extern "C" {
 #define MSTAR_W_TIME_TOL 1     /* t_end not met within t_tol after max_time_iter clipped steps */
 
 #define MSTAR_DEVICE_PTRS 1u   /* array arguments are device pointers */
+#define MSTAR_EAGER 2u         /* mstar_integrate*: launch each GBS step attempt's kernels from
+                                  the host instead of replaying the attempt as a captured HIP
+                                  graph (same kernels, same order, identical results) */
 
 /* Parameters of the method.  struct_size must be sizeof(mstar_params);
  * mstar_params_default fills every field. */
 typedef struct {
     uint32_t struct_size;
-    uint32_t flags;         /* MSTAR_DEVICE_PTRS */
+    uint32_t flags;         /* MSTAR_DEVICE_PTRS | MSTAR_EAGER */
     double G;               /* gravitational constant (Sec. 2.1) */
     double eta;             /* GBS tolerance eta_GBS, eq. gbs-criterion; default 1e-12 */
     double alpha, beta, gamma; /* time-transformation triplet, eq. ttl; default LogH (1,0,0) */

@@ -67,6 +67,10 @@ struct mstar_ctx {
     hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
+    // one GBS step attempt of mstar_integrate* captured as a graph
+    hipGraphExec_t s_exec = nullptr;
+    std::string s_key;                 // what the captured launches depend on
+    int ws_gen = 0;                    // bumped whenever device buffers move
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
     bool ext_on = false;               // an external field applies to the running integration
     ExtField h_ext{};                  // host copy of that field
@@ -136,6 +140,7 @@ int ensure(mstar_ctx *ctx, int n) {
     }
     HIPCK(hipStreamSynchronize(ctx->stream));
     free_workspace(ctx);
+    ++ctx->ws_gen;
     const int cap = std::max(n, 64);
     const size_t N = (size_t)cap;
     const int nib = (cap + 63) / 64, nkwg = (cap + kWG - 1) / kWG;
@@ -191,6 +196,7 @@ int ensure_ttl(mstar_ctx *ctx) {
         d.opart = nullptr; d.Opart = nullptr; d.wpart = nullptr;
         return rc;
     }
+    ++ctx->ws_gen;
     return MSTAR_OK;
 }
 
@@ -207,6 +213,7 @@ int ensure_ext(mstar_ctx *ctx) {
         d.ext = nullptr; d.fext = nullptr; d.fpart = nullptr; d.bpart = nullptr;
         return rc;
     }
+    ++ctx->ws_gen;
     return MSTAR_OK;
 }
 
@@ -698,6 +705,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
     if (ctx->h_bargs) (void)hipHostFree(ctx->h_bargs);
     if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
+    if (ctx->s_exec) (void)hipGraphExecDestroy(ctx->s_exec);
     for (hipEvent_t e : ctx->b_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -831,7 +839,7 @@ int mstar_leapfrog(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr, params))) return rc;
     if ((rc = load_state(ctx, params, n, parent, X, V, scal))) return rc;
     if ((rc = prepare_start(ctx, params, true, false, nullptr))) return rc;
-    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params));
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params), 0);
     const int nl[1] = {nsub};
     if ((rc = run_divisions(ctx, params, nl, 1, nullptr))) return rc;
     launch_commit(ctx->d, ctx->stream, 0, 0);
@@ -852,7 +860,7 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     if ((rc = load_bodies(ctx, flags, n, m, nullptr, nullptr, params))) return rc;
     if ((rc = load_state(ctx, params, n, parent, X, V, scal))) return rc;
     if ((rc = prepare_start(ctx, params, true, true, nullptr))) return rc;
-    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params));
+    launch_set_h(ctx->d, ctx->stream, H, 0.0, 0, ttl_of(params), 0);
     int nl[16];
     for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
     if ((rc = run_divisions(ctx, params, nl, params->k_fix, nullptr))) return rc;
@@ -868,6 +876,59 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
 }
 
 }  // extern "C"
+
+// One GBS step attempt after the start state is prepared: the step length
+// (from ctl->h_next, clipped to t_end), all divisions, extrapolation, the
+// accept decision and the commit.
+int enqueue_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const int *nl, int64_t *nforce) {
+    const Dev &d = ctx->d;
+    launch_set_h(d, ctx->stream, 0.0, t_end, 1, ttl_of(p), 1);
+    int rc = run_divisions(ctx, p, nl, p->k_fix, nforce);
+    if (rc) return rc;
+    launch_extrapolate(d, ctx->stream, p->k_fix, ttl_of(p), kBase, ctx->ext_on);
+    launch_control(d, ctx->stream, p->k_fix, p->eta, p->a_gbs, p->f_min, p->f_max);
+    launch_commit(d, ctx->stream, 1, 0);
+    HIPCK(hipGetLastError());
+    return MSTAR_OK;
+}
+
+// The same attempt replayed from a captured graph (about 60 kernel launches
+// become one), recaptured when anything its launches depend on changes: the
+// parameters, t_end, N, the external-field switch or the device buffers.
+// MSTAR_EAGER, or force-kernel profiling, launches it from the host instead.
+int run_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const int *nl, int64_t *nforce) {
+    if ((p->flags & MSTAR_EAGER) || ctx->prof) return enqueue_attempt(ctx, p, t_end, nl, nforce);
+    // everything the captured kernel arguments are made of
+    const double kd[] = {p->G, p->eta, p->alpha, p->beta, p->gamma, p->a_gbs, p->f_min, p->f_max, t_end};
+    const int ki[] = {p->k_fix, p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0};
+    std::string key((const char *)kd, sizeof kd);
+    key.append((const char *)ki, sizeof ki);
+    if (!ctx->s_exec || key != ctx->s_key) {
+        if (ctx->s_exec) (void)hipGraphExecDestroy(ctx->s_exec);
+        ctx->s_exec = nullptr;
+        ctx->s_key.clear();
+        (void)force_cap(ctx, p->n_d);   // occupancy query outside the capture
+        hipGraph_t graph = nullptr;
+        HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        const int lrc = enqueue_attempt(ctx, p, t_end, nl, nullptr);
+        const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+        if (lrc || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(ctx, MSTAR_E_DEVICE, "step graph capture failed: %s", hipGetErrorString(ec));
+        }
+        const hipError_t ei = hipGraphInstantiate(&ctx->s_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            ctx->s_exec = nullptr;
+            return fail(ctx, MSTAR_E_DEVICE, "step graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        ctx->s_key = key;
+    }
+    HIPCK(hipGraphLaunch(ctx->s_exec, ctx->stream));
+    if (nforce)
+        for (int k = 0; k < p->k_fix; ++k) *nforce += nl[k];
+    return MSTAR_OK;
+}
 
 // The driver (Sec. 2.4); with rec_H, the fictitious step of every accepted
 // step is recorded and the run stops after max_acc accepted steps.
@@ -932,6 +993,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     int halvings = 0, since_rebuild = 0, since_resync = 0;
     bool fresh = false;   // the start state was just prepared
     bool just_rebuilt = false;
+    bool h_on_dev = false;   // ctl->h_next already holds H
     int nl[16];
     for (int k = 0; k < p.k_fix; ++k) nl[k] = 2 * (k + 1);
     double t_now = t0;
@@ -949,12 +1011,10 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             if ((rc = prepare_start(ctx, &p, resync, true, &st.force_evals))) break;
             fresh = false;
         }
-        launch_set_h(d, ctx->stream, H, t_end, 1, ttl_of(&p));
-        if ((rc = run_divisions(ctx, &p, nl, p.k_fix, &st.force_evals))) break;
-        launch_extrapolate(d, ctx->stream, p.k_fix, ttl_of(&p), kBase, ctx->ext_on);
-        launch_control(d, ctx->stream, p.k_fix, p.eta, p.a_gbs, p.f_min, p.f_max);
-        launch_commit(d, ctx->stream, 1, 0);
+        if (!h_on_dev) launch_put_hnext(d, ctx->stream, H);
+        if ((rc = run_attempt(ctx, &p, t_end, nl, &st.force_evals))) break;
         if ((rc = read_ctl(ctx))) break;
+        h_on_dev = true;   // every branch below continues with H = ctl->h_next
         const Ctl &c = *ctx->h_ctl;
         if (just_rebuilt && c.tree_bad) {
             // the queued Boruvka rounds did not finish the new tree, so the
@@ -962,6 +1022,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             // host check and repeat the step with the same H
             if ((rc = rebuild(ctx, &p))) break;
             if ((rc = prepare_start(ctx, &p, true, true, &st.force_evals))) break;
+            h_on_dev = false;   // control overwrote h_next; the repeat uses H
             continue;
         }
         if (just_rebuilt) {

@@ -332,8 +332,9 @@ void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, do
 // must not pass t_end (nor may the step point away from it); otherwise
 // ds = g (t_end - t).  With TTL also dw/dt at the start state from the
 // partials of the start-state force reduction.
-__global__ void k_set_h(Dev d, double H, double t_end, int clip, Ttl tr) {
+__global__ void k_set_h(Dev d, double H, double t_end, int clip, Ttl tr, int from_ctl) {
     Ctl &c = *d.ctl;
+    if (from_ctl) H = c.h_next;   // the step proposed by the previous attempt (or set by k_put_hnext)
     {   // T of the start state from the per-workgroup partials left by the commit
         const double *tp = d.Tpart + (size_t)kBaseSlot * d.nkwg4;
         double t = 0.0;
@@ -361,9 +362,14 @@ __global__ void k_set_h(Dev d, double H, double t_end, int clip, Ttl tr) {
     c.t_est = d.sys->t + H / gk;
 }
 
-void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr) {
-    k_set_h<<<1, 1, 0, s>>>(d, H, t_end, clip, tr);
+void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr, int from_ctl) {
+    k_set_h<<<1, 1, 0, s>>>(d, H, t_end, clip, tr, from_ctl);
 }
+
+// Proposed step of the next attempt, for a driver whose attempt reads it from
+// the control block (a replayed graph cannot take it as an argument).
+__global__ void k_put_hnext(Dev d, double H) { d.ctl->h_next = H; }
+void launch_put_hnext(const Dev &d, hipStream_t s, double H) { k_put_hnext<<<1, 1, 0, s>>>(d, H); }
 
 // In-place Aitken-Neville tableau over KF divisions n_k = 2(k+1); on return
 // p[k] = T_{k,k}.

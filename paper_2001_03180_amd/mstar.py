@@ -20,6 +20,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_COINCIDENT, E_NOCONV, E_MAXSTEPS,
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 W_TIME_TOL = 1
 DEVICE_PTRS = 1
+EAGER = 2
 
 
 class Params(C.Structure):
@@ -270,7 +271,7 @@ class Context:
         scal = np.array(scal, dtype=np.float64) if not _is_torch(scal) else scal.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(parent, np.int32, (n,)), _Arg(X, np.float64, (n, 3), True),
              _Arg(V, np.float64, (n, 3), True), _Arg(scal, np.float64, (9,), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         self._check(lib().mstar_leapfrog(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, a[3].ptr,
                                          a[4].ptr, float(H), int(nsub)))
         return X, V, scal
@@ -284,7 +285,7 @@ class Context:
         scal = np.array(scal, dtype=np.float64) if not _is_torch(scal) else scal.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(parent, np.int32, (n,)), _Arg(X, np.float64, (n, 3), True),
              _Arg(V, np.float64, (n, 3), True), _Arg(scal, np.float64, (9,), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         acc, eps, hn = C.c_int32(), C.c_double(), C.c_double()
         self._check(lib().mstar_gbs_step(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, a[3].ptr,
                                          a[4].ptr, float(H), C.cast(C.pointer(acc), C.c_void_p),
@@ -298,7 +299,7 @@ class Context:
         x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
         v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         st = Stats()
         st.struct_size = C.sizeof(Stats)
         rc = lib().mstar_integrate(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), float(t_end),
@@ -315,7 +316,7 @@ class Context:
         x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
         v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         pts = np.ascontiguousarray(np.zeros((0, 5)) if points is None else np.asarray(points, dtype=np.float64)
                                    .reshape(-1, 5))
         e = External()
@@ -352,7 +353,7 @@ class Context:
         record array of BATCH_STATS_DTYPE (per-system status and counters)."""
         p = p or params()
         off, n_sys, te, t0a, x, v, a = self._batch_args(offsets, m, x, v, t_end, t0, True)
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         st = np.zeros(max(n_sys, 0), dtype=BATCH_STATS_DTYPE)
         self._check(lib().mstar_integrate_batch(
             self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
@@ -379,7 +380,7 @@ class Context:
         """Time every launch shape on this batch (x, v untouched), keep and return the fastest."""
         p = p or params()
         off, n_sys, te, t0a, x, v, a = self._batch_args(offsets, m, x, v, t_end, t0, False)
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         c = BatchConfig()
         self._check(lib().mstar_batch_autotune(
             self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
@@ -395,7 +396,7 @@ class Context:
         x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
         v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         H = np.zeros(int(max_accepted))
         k = C.c_int64()
         st = Stats()
@@ -414,7 +415,7 @@ class Context:
         x = np.array(x, dtype=np.float64) if not _is_torch(x) else x.clone()
         v = np.array(v, dtype=np.float64) if not _is_torch(v) else v.clone()
         a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3), True), _Arg(v, np.float64, (n, 3), True)]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         t = C.c_double()
         self._check(lib().mstar_replay(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0), len(H),
                                        C.c_void_p(H.ctypes.data), C.byref(t)))
@@ -428,7 +429,7 @@ class Context:
         H = np.ascontiguousarray(H, dtype=np.float64)
         a = [_Arg(m, np.float64, (n,)), _Arg(x0, np.float64, (n, 3)), _Arg(v0, np.float64, (n, 3)),
              _Arg(gx, np.float64, (n, 3)), _Arg(gv, np.float64, (n, 3))]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         if p.flags:
             import torch
             gx0 = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
@@ -446,7 +447,7 @@ class Context:
         p = p or params()
         n = len(m)
         a = [_Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3)), _Arg(w, np.float64, (n, 3))]
-        p.flags = _mode(*a)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
         if p.flags:
             import torch
             out = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
