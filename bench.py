@@ -51,7 +51,10 @@ BATCH_ETA = 1e-12
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
 # valid only for the force-kernel sources with this hash.
 FORCE_TRAFFIC = {"sha256": "5b8f31bf1b5fe41179ab371d93b3a576cf1e5cffe0a7c9d9f0335f3c79b10985",
-                 "fetch_bytes": 12840207.0, "write_bytes": 8406907.0}
+                 "fetch_bytes": 12840207.0, "write_bytes": 8406907.0,
+                 # executed FP64 flops per directed pair, 64 (ADD + MUL + TRANS + 2 FMA)_F64 over
+                 # 64 TRANS_F64 (rocprofv3 SQ_INSTS_VALU_*_F64 counters of the same kernel)
+                 "exec_flops_per_pair": 27.05}
 
 
 def force_traffic():
@@ -64,6 +67,11 @@ def force_traffic():
     if h.hexdigest() != FORCE_TRAFFIC["sha256"]:
         return None
     return FORCE_TRAFFIC["fetch_bytes"] + FORCE_TRAFFIC["write_bytes"]
+
+
+def force_exec_flops_per_pair():
+    """Executed FP64 flops per pair if the kernel is the one measured, else None."""
+    return FORCE_TRAFFIC["exec_flops_per_pair"] if force_traffic() is not None else None
 
 
 def cpu_baseline(m, x, v, eta, threads):
@@ -470,6 +478,12 @@ def main():
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "executed": None if force_exec_flops_per_pair() is None else {
+                "flops_per_pair": force_exec_flops_per_pair(),
+                "tflops": force_exec_flops_per_pair() * launch_pairs_per_s / 1e12,
+                "frac_of_peak": force_exec_flops_per_pair() * launch_pairs_per_s / 1e12 / PEAK_FP64_TFLOPS,
+                "note": "FP64 VALU flops as executed, rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64",
+            },
             "issue_ceiling": {
                 "fma_cycles_per_wave_op": fma_cyc,
                 "rsq_cycles_per_wave_op": rsq_cyc,
