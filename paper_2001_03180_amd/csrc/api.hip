@@ -70,6 +70,9 @@ struct mstar_ctx {
     // one GBS step attempt of mstar_integrate* captured as a graph
     hipGraphExec_t s_exec = nullptr;
     std::string s_key;                 // what the captured launches depend on
+    // the rebuild and start-state force after an accepted step, captured likewise
+    hipGraphExec_t r_exec = nullptr;
+    std::string r_key;
     int ws_gen = 0;                    // bumped whenever device buffers move
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
     bool ext_on = false;               // an external field applies to the running integration
@@ -706,6 +709,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     if (ctx->h_bargs) (void)hipHostFree(ctx->h_bargs);
     if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
     if (ctx->s_exec) (void)hipGraphExecDestroy(ctx->s_exec);
+    if (ctx->r_exec) (void)hipGraphExecDestroy(ctx->r_exec);
     for (hipEvent_t e : ctx->b_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
@@ -896,6 +900,33 @@ int enqueue_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const i
 // become one), recaptured when anything its launches depend on changes: the
 // parameters, t_end, N, the external-field switch or the device buffers.
 // MSTAR_EAGER, or force-kernel profiling, launches it from the host instead.
+template <class F>
+int replay_graph(mstar_ctx *ctx, hipGraphExec_t &exec, std::string &have, const std::string &key, F enqueue) {
+    if (!exec || key != have) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        have.clear();
+        prepare_tree_launches();
+        hipGraph_t graph = nullptr;
+        HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        const int lrc = enqueue();
+        const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+        if (lrc || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(ctx, MSTAR_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            exec = nullptr;
+            return fail(ctx, MSTAR_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        have = key;
+    }
+    HIPCK(hipGraphLaunch(exec, ctx->stream));
+    return MSTAR_OK;
+}
+
 int run_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const int *nl, int64_t *nforce) {
     if ((p->flags & MSTAR_EAGER) || ctx->prof) return enqueue_attempt(ctx, p, t_end, nl, nforce);
     // everything the captured kernel arguments are made of
@@ -903,30 +934,38 @@ int run_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const int *
     const int ki[] = {p->k_fix, p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0};
     std::string key((const char *)kd, sizeof kd);
     key.append((const char *)ki, sizeof ki);
-    if (!ctx->s_exec || key != ctx->s_key) {
-        if (ctx->s_exec) (void)hipGraphExecDestroy(ctx->s_exec);
-        ctx->s_exec = nullptr;
-        ctx->s_key.clear();
-        (void)force_cap(ctx, p->n_d);   // occupancy query outside the capture
-        hipGraph_t graph = nullptr;
-        HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-        const int lrc = enqueue_attempt(ctx, p, t_end, nl, nullptr);
-        const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
-        if (lrc || ec != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return fail(ctx, MSTAR_E_DEVICE, "step graph capture failed: %s", hipGetErrorString(ec));
-        }
-        const hipError_t ei = hipGraphInstantiate(&ctx->s_exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            ctx->s_exec = nullptr;
-            return fail(ctx, MSTAR_E_DEVICE, "step graph instantiation failed: %s", hipGetErrorString(ei));
-        }
-        ctx->s_key = key;
-    }
-    HIPCK(hipGraphLaunch(ctx->s_exec, ctx->stream));
+    (void)force_cap(ctx, p->n_d);   // occupancy query outside any capture
+    int rc = replay_graph(ctx, ctx->s_exec, ctx->s_key, key,
+                          [&]() { return enqueue_attempt(ctx, p, t_end, nl, nullptr); });
+    if (rc) return rc;
     if (nforce)
         for (int k = 0; k < p->k_fix; ++k) *nforce += nl[k];
+    return MSTAR_OK;
+}
+
+// Start of a step after an accepted one: the queued MST rebuild (when due)
+// and the start-state force.  Replayed from a graph when no re-derivation of
+// the Cartesian caches is due (that one clears memory, which stays out of
+// graphs), keyed like the attempt plus the queued round count.
+int prepare_step(mstar_ctx *ctx, const mstar_params *p, bool rebuild_due, bool resync, int64_t *nforce) {
+    if ((p->flags & MSTAR_EAGER) || ctx->prof || resync || !rebuild_due) {
+        if (rebuild_due) {
+            int rc = rebuild_queued(ctx, p);
+            if (rc) return rc;
+        }
+        return prepare_start(ctx, p, resync, true, nforce);
+    }
+    const double kd[] = {p->G, p->alpha, p->beta, p->gamma};
+    const int ki[] = {p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, ctx->mst_rounds_est};
+    std::string key((const char *)kd, sizeof kd);
+    key.append((const char *)ki, sizeof ki);
+    (void)force_cap(ctx, p->n_d);
+    int rc = replay_graph(ctx, ctx->r_exec, ctx->r_key, key, [&]() {
+        int r = rebuild_queued(ctx, p);
+        return r ? r : prepare_start(ctx, p, false, true, nullptr);
+    });
+    if (rc) return rc;
+    if (nforce) ++*nforce;
     return MSTAR_OK;
 }
 
@@ -1000,15 +1039,15 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     for (;;) {
         if (st.steps_accepted + st.steps_rejected >= p.max_steps) { rc = MSTAR_E_MAXSTEPS; break; }
         if (fresh) {
-            if (since_rebuild >= p.rebuild_every) {
-                if ((rc = rebuild_queued(ctx, &p))) break;
+            const bool due = since_rebuild >= p.rebuild_every;
+            if (due) {
                 st.mst_rebuilds++;
                 since_rebuild = 0;
                 just_rebuilt = true;
             }
             const bool resync = since_resync >= kResyncEvery;
             if (resync) since_resync = 0;
-            if ((rc = prepare_start(ctx, &p, resync, true, &st.force_evals))) break;
+            if ((rc = prepare_step(ctx, &p, due, resync, &st.force_evals))) break;
             fresh = false;
         }
         if (!h_on_dev) launch_put_hnext(d, ctx->stream, H);

@@ -195,6 +195,7 @@ void launch_ext(const Dev &d, hipStream_t s, const SlotList &sl, int at_start);
 void launch_ext_minv(const Dev &d, hipStream_t s);
 void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr, int from_ctl);
 void launch_put_hnext(const Dev &d, hipStream_t s, double H);
+void prepare_tree_launches();   // one-time runtime settings of the tree kernels (before any capture)
 void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot, bool ex);
 void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max);
 void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot);

@@ -578,6 +578,20 @@ void launch_mst_init(const Dev &d, hipStream_t s, const d4 *pos, int root_in) {
     k_mst_init<<<1, kTreeWG, 0, s>>>(d, pos, root_in);
 }
 
+// Dynamic LDS limit of the single-workgroup tree kernels, raised once per
+// device to the largest size their launches request (150 KiB), so that
+// launches themselves make no other runtime call (they may be captured).
+static void tree_lds_limits() {
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+    (void)hipFuncSetAttribute((const void *)k_bor_merge<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_mst_finish<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    done[dev] = true;
+}
+
+void prepare_tree_launches() { tree_lds_limits(); }
+
 // `rounds` Boruvka rounds (each a no-op once one component is left).
 void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, int nsplit) {
     const int jchunk = (d.n + nsplit - 1) / nsplit;
@@ -586,8 +600,7 @@ void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, i
         k_bor_vreduce<<<(d.n + kWG / 4 - 1) / (kWG / 4), kWG, 0, s>>>(d, nsplit);
         const size_t lds = (sizeof(unsigned long long) + 4 * sizeof(int)) * (size_t)d.n;
         if (lds <= 150 * 1024) {
-            (void)hipFuncSetAttribute((const void *)k_bor_merge<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds);
+            tree_lds_limits();
             k_bor_merge<true><<<1, kTreeWG, lds, s>>>(d);
         } else {
             k_bor_merge<false><<<1, kTreeWG, 0, s>>>(d);
@@ -598,8 +611,7 @@ void launch_mst_rounds(const Dev &d, hipStream_t s, const d4 *pos, int rounds, i
 void launch_mst_root(const Dev &d, hipStream_t s) {
     const size_t lds = sizeof(int) * (4 * (size_t)d.n + 1);
     if (lds <= 150 * 1024 && d.n <= 16 * kFinWG) {
-        (void)hipFuncSetAttribute((const void *)k_mst_finish<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+        tree_lds_limits();
         k_mst_finish<true><<<1, kFinWG, lds, s>>>(d);
     } else {
         k_mst_finish<false><<<1, kFinWG, 0, s>>>(d);
