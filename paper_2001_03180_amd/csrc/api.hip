@@ -73,6 +73,7 @@ struct mstar_ctx {
     // the rebuild and start-state force after an accepted step, captured likewise
     hipGraphExec_t r_exec = nullptr;
     std::string r_key;
+    bool no_graph = false;             // the stream could not be captured: launch eagerly
     int ws_gen = 0;                    // bumped whenever device buffers move
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
     bool ext_on = false;               // an external field applies to the running integration
@@ -900,26 +901,34 @@ int enqueue_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const i
 // become one), recaptured when anything its launches depend on changes: the
 // parameters, t_end, N, the external-field switch or the device buffers.
 // MSTAR_EAGER, or force-kernel profiling, launches it from the host instead.
+// Capture `enqueue` once per key and replay it.  A stream that cannot be
+// captured (the caller's stream is given to mstar_create) makes the context
+// launch eagerly from then on: the graph is an optimisation only.
 template <class F>
 int replay_graph(mstar_ctx *ctx, hipGraphExec_t &exec, std::string &have, const std::string &key, F enqueue) {
+    if (ctx->no_graph) return enqueue();
     if (!exec || key != have) {
         if (exec) (void)hipGraphExecDestroy(exec);
         exec = nullptr;
         have.clear();
         prepare_tree_launches();
         hipGraph_t graph = nullptr;
-        HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->no_graph = true;
+            return enqueue();
+        }
         const int lrc = enqueue();
         const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
-        if (lrc || ec != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return fail(ctx, MSTAR_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
-        }
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
+        hipError_t ei = hipErrorUnknown;
+        if (!lrc && ec == hipSuccess) ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (lrc) return lrc;
+        if (ei != hipSuccess) {   // nothing ran: launch the same work eagerly
             exec = nullptr;
-            return fail(ctx, MSTAR_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+            (void)hipGetLastError();
+            ctx->no_graph = true;
+            return enqueue();
         }
         have = key;
     }
