@@ -102,7 +102,10 @@ const char *mstar_strerror(int code);
 
 /* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
  * to enqueue work on, or NULL for a stream owned by the context.  Device
- * scratch is allocated on demand and kept until mstar_destroy.
+ * scratch is allocated on demand and kept until mstar_destroy.  The
+ * integration calls capture their GBS step attempts on this stream as HIP
+ * graphs and replay them (unless MSTAR_EAGER); a stream that cannot be
+ * captured makes the context launch directly instead.
  * Errors: MSTAR_E_INVAL (bad device), MSTAR_E_DEVICE, MSTAR_E_NOMEM. */
 int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream);
 
