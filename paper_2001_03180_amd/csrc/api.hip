@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -75,6 +76,7 @@ struct mstar_ctx {
     std::string r_key;
     bool no_graph = false;             // the stream could not be captured: launch eagerly
     int ws_gen = 0;                    // bumped whenever device buffers move
+    int mst_spare = 1;                 // Boruvka rounds queued beyond the previous build's count
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
     bool ext_on = false;               // an external field applies to the running integration
     ExtField h_ext{};                  // host copy of that field
@@ -253,7 +255,6 @@ bool ttl_on(const mstar_params *p) { return p->beta != 0.0; }
 
 constexpr int kBase = kBaseSlot;     // slot of the start state
 constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
-constexpr int kMstSpareRounds = 1;   // Boruvka rounds queued beyond the previous build's count
 
 // Resident force workgroups on the whole chip (queried once per N_d kind).
 int force_cap(mstar_ctx *ctx, int nd) {
@@ -567,7 +568,7 @@ int rebuild_queued(mstar_ctx *ctx, const mstar_params *p) {
     const d4 *pos = d.P + (size_t)kBase * d.n;
     const d4 *vel = d.Vt + (size_t)kBase * d.n;
     const int maxr = mst_max_rounds(d);
-    const int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est + kMstSpareRounds, maxr) : maxr;
+    const int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est + ctx->mst_spare, maxr) : maxr;
     launch_mst_init(d, ctx->stream, pos, -1);
     launch_mst_rounds(d, ctx->stream, pos, est, mst_splits(d));
     launch_mst_root(d, ctx->stream);
@@ -673,6 +674,12 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
     } else {
         if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return MSTAR_E_DEVICE; }
         ctx->own_stream = true;
+    }
+    // spare Boruvka rounds of a queued rebuild (MSTAR_MST_SPARE_ROUNDS, 0..8;
+    // 0 makes the repeat-the-step path of an unfinished rebuild frequent)
+    if (const char *e = std::getenv("MSTAR_MST_SPARE_ROUNDS")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= 8) ctx->mst_spare = v;
     }
     if (hipHostMalloc((void **)&ctx->h_blk, sizeof(CtlBlock), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
@@ -965,7 +972,7 @@ int prepare_step(mstar_ctx *ctx, const mstar_params *p, bool rebuild_due, bool r
         return prepare_start(ctx, p, resync, true, nforce);
     }
     const double kd[] = {p->G, p->alpha, p->beta, p->gamma};
-    const int ki[] = {p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, ctx->mst_rounds_est};
+    const int ki[] = {p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, ctx->mst_rounds_est, ctx->mst_spare};
     std::string key((const char *)kd, sizeof kd);
     key.append((const char *)ki, sizeof ki);
     (void)force_cap(ctx, p->n_d);
@@ -1042,6 +1049,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     bool fresh = false;   // the start state was just prepared
     bool just_rebuilt = false;
     bool h_on_dev = false;   // ctl->h_next already holds H
+    bool last_resync = false;   // the current step's start re-derived the Cartesian caches
     int nl[16];
     for (int k = 0; k < p.k_fix; ++k) nl[k] = 2 * (k + 1);
     double t_now = t0;
@@ -1056,6 +1064,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             }
             const bool resync = since_resync >= kResyncEvery;
             if (resync) since_resync = 0;
+            last_resync = resync;
             if ((rc = prepare_step(ctx, &p, due, resync, &st.force_evals))) break;
             fresh = false;
         }
@@ -1069,7 +1078,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             // step ran on the old one and was not committed: rebuild with the
             // host check and repeat the step with the same H
             if ((rc = rebuild(ctx, &p))) break;
-            if ((rc = prepare_start(ctx, &p, true, true, &st.force_evals))) break;
+            if ((rc = prepare_start(ctx, &p, last_resync, true, &st.force_evals))) break;
             h_on_dev = false;   // control overwrote h_next; the repeat uses H
             continue;
         }

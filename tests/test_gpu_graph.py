@@ -80,3 +80,37 @@ def test_graph_ttl_and_device_pointers(ctx, M):
                       torch.tensor(v, device="cuda"), 0.0, 0.05, M.params(**kw))
     assert np.array_equal(g[0].cpu().numpy(), e[0]) and np.array_equal(g[1].cpu().numpy(), e[1])
     assert g[3] == e[3]
+
+
+def test_unfinished_rebuild_repeats_the_step_exactly(M):
+    """A rebuild queued with no spare Borůvka round often does not finish; the
+    step taken on the old tree is then discarded, the tree completed and the
+    step repeated.  The integration must equal the default one bit for bit
+    (only the count of force evaluations grows)."""
+    import os
+    m, x, v = ics.plummer_with_central_mass(256, 501)
+    p = dict(eta=1e-12)
+    ref = M.Context(0)
+    try:
+        say("spare rounds 1 (default), N=257, t=0.5")
+        a = ref.integrate(m, x, v, 0.0, 0.5, M.params(**p))
+    finally:
+        ref.close()
+    os.environ["MSTAR_MST_SPARE_ROUNDS"] = "0"
+    try:
+        c = M.Context(0)
+    finally:
+        del os.environ["MSTAR_MST_SPARE_ROUNDS"]
+    try:
+        say("spare rounds 0, N=257, t=0.5")
+        b = c.integrate(m, x, v, 0.0, 0.5, M.params(**p))
+        e = c.integrate(m, x, v, 0.0, 0.5, M.params(flags=M.EAGER, **p))
+    finally:
+        c.close()
+    assert a[3]["steps_accepted"] > 20
+    # the repeat path ran: each repeat re-evaluates a whole attempt
+    assert b[3]["force_evals"] > a[3]["force_evals"] and e[3]["force_evals"] == b[3]["force_evals"]
+    for r in (b, e):
+        assert np.array_equal(a[0], r[0]) and np.array_equal(a[1], r[1])
+        for k in ("steps_accepted", "steps_rejected", "mst_rebuilds", "t_reached"):
+            assert a[3][k] == r[3][k], k
