@@ -189,13 +189,15 @@ def test_gbs_step_parity(ctx, orc, M, n, seed, H, kf):
         assert np.array_equal(Xg, X) and hn == 0.5 * H
 
 
-def test_gbs_step_parity_full_size(ctx, orc, M):
+@pytest.mark.parametrize("n_stars,seed", [(5000, 301), (10000, 302)])
+def test_gbs_step_parity_full_size(ctx, orc, M, n_stars, seed):
     """One GBS step of the benchmark workload (N_p = 5002, k_fix = 8, eta = 1e-13)
-    in the launch configuration the benchmark times, against the oracle."""
-    m, x, v = ics.plummer_with_binary(5000, 301)
+    in the launch configuration the benchmark times, and of its larger size
+    (N_p = 10002), against the oracle."""
+    m, x, v = ics.plummer_with_binary(n_stars, seed)
     parent, X, V, scal, _ = _state(orc, m, x, v)
     H = 5e-5
-    say(f"gbs_step n=5002 H={H} k_fix=8")
+    say(f"gbs_step n={len(m)} H={H} k_fix=8")
     p = M.params(k_fix=8, eta=1e-13)
     Xg, Vg, sg, acc, eps, hn = ctx.gbs_step(m, parent, X, V, scal, H, p)
     Xo, Vo, so, acco, epso, hno, nf = orc.gbs_step(m, parent, X, V, scal, H,
