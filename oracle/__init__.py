@@ -31,7 +31,7 @@ class Params(C.Structure):
         ("f_min", C.c_double), ("f_max", C.c_double), ("q_first", C.c_double), ("t_tol", C.c_double),
         ("h_init", C.c_double), ("max_steps", C.c_int64), ("k_fix", C.c_int32), ("n_d", C.c_int32),
         ("max_halvings", C.c_int32), ("max_time_iter", C.c_int32), ("rebuild_every", C.c_int32),
-        ("nthreads", C.c_int32),
+        ("nthreads", C.c_int32), ("accept_rule", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -50,7 +50,7 @@ def params(**kw) -> Params:
     """Default parameters (LogH, k_fix = 8, N_d = 2, eta = 1e-12), overridable."""
     p = Params(G=1.0, eta=1e-12, alpha=1.0, beta=0.0, gamma=0.0, omega_mass_max=0.0, a_gbs=0.9,
                f_min=0.1, f_max=4.0, q_first=0.1, t_tol=1e-14, h_init=0.0, max_steps=10**9, k_fix=8,
-               n_d=2, max_halvings=60, max_time_iter=8, rebuild_every=1, nthreads=0)
+               n_d=2, max_halvings=60, max_time_iter=8, rebuild_every=1, nthreads=0, accept_rule=0)
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)

@@ -57,6 +57,9 @@ typedef struct {
     int32_t max_time_iter;
     int32_t rebuild_every; /* accepted steps between MST rebuilds */
     int32_t nthreads;      /* OpenMP threads for the force loop (0 = default) */
+    int32_t accept_rule;   /* READING of eq. gbs-criterion vs Sec. 4.2: 0 judge at k_fix;
+                              1 accept at the first k >= 2 whose eps_k <= eta */
+    int32_t pad_;
 } orc_params;
 
 typedef struct {
@@ -750,15 +753,22 @@ static int gbs_divisions(ostate *y, const orc_params *p, oscratch *s, double H, 
     rc = orc_neville(kf, L, nk, tab, diag);
     if (rc) goto done;
     {
-        double *dS = tab; /* reuse: dS = T_{kf,kf} - T_{kf-1,kf-1} (Sec. 4.2) */
-        for (int v = 0; v < L; ++v) dS[v] = diag[(size_t)(kf - 1) * L + v] - diag[(size_t)(kf - 2) * L + v];
-        double eps = gbs_error(y, dS, S0, dS0, diag + (size_t)(kf - 1) * L, H / (double)nk[kf - 1], p->beta != 0.0);
+        /* dS_k = T_{k,k} - T_{k-1,k-1} (Sec. 4.2); judged at k_fix, or (accept_rule 1,
+         * the serial criterion of Sec. 2.3) at the first k whose eps_k <= eta */
+        double *dS = tab; /* reuse */
+        int k_first = p->accept_rule == 1 ? 2 : kf, kacc = 0;
+        double eps = 0.0;
+        for (int k = k_first; k <= kf; ++k) {
+            for (int v = 0; v < L; ++v) dS[v] = diag[(size_t)(k - 1) * L + v] - diag[(size_t)(k - 2) * L + v];
+            eps = gbs_error(y, dS, S0, dS0, diag + (size_t)(k - 1) * L, H / (double)nk[k - 1], p->beta != 0.0);
+            if (eps <= p->eta) { kacc = k; break; }
+        }
         *eps_out = eps;
-        *accepted = (eps <= p->eta);
+        *accepted = kacc > 0;
         if (*accepted) {
-            apply_incr(y, diag + (size_t)(kf - 1) * L);
+            apply_incr(y, diag + (size_t)(kacc - 1) * L);
             double e = eps > 1e-300 ? eps : 1e-300;
-            double f = p->a_gbs * pow(p->eta / e, 1.0 / (double)(2 * kf - 1));
+            double f = p->a_gbs * pow(p->eta / e, 1.0 / (double)(2 * kacc - 1));
             if (f < p->f_min) f = p->f_min;
             if (f > p->f_max) f = p->f_max;
             *h_next = H * f;
