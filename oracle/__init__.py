@@ -355,16 +355,21 @@ def integrate_rec(m, x, v, t0, t_end, max_accepted, p: Params | None = None):
 
 
 def replay(m, x, v, t0, H, parents, p: Params | None = None):
-    """Frozen-controller replay in MST coordinates: (x, v, t) after len(H) steps."""
+    """Frozen-controller replay in MST coordinates: (x, v, t) after len(H) steps.
+    parents None: the driver's own MST builds and rebuilds."""
     p = p or params()
     m, pm = _d(m)
     x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
     H = np.ascontiguousarray(H, dtype=np.float64)
-    par = np.ascontiguousarray(parents, dtype=np.int32)
-    assert par.shape == (len(H), len(m))
+    if parents is None:
+        pp = None
+    else:
+        par = np.ascontiguousarray(parents, dtype=np.int32)
+        assert par.shape == (len(H), len(m))
+        pp = par.ctypes.data_as(C.POINTER(C.c_int32))
     t = C.c_double()
-    _check(lib().orc_replay(len(m), pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1],
-                            par.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(p), C.byref(t)), "replay")
+    _check(lib().orc_replay(len(m), pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1], pp, C.byref(p),
+                            C.byref(t)), "replay")
     return x, v, t.value
 
 

@@ -1224,10 +1224,14 @@ out:
 /* Replay: initial MST state on parents[0], then for k < nsteps a rebuild onto
  * parents[k] (k > 0) and a GBS step of length H[k]; x, v are replaced by the
  * end state and *t_out is its time.  With the record of orc_integrate_rec
- * this repeats that integration bit for bit. */
+ * this repeats that integration bit for bit.  With parents NULL the trees are
+ * the driver's own: the MST of x rooted nearest the centre of mass at the
+ * start, and the rebuild of Sec. 3.5 before every rebuild_every-th step
+ * after it -- the integration of orc_integrate with its accepted step
+ * lengths given instead of chosen. */
 int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t nsteps, const double *H,
                const int32_t *parents, const orc_params *p, double *t_out) {
-    if (n < 2 || nsteps < 0 || !H || !parents || p->beta != 0.0) return ORC_E_INVAL;
+    if (n < 2 || nsteps < 0 || !H || p->beta != 0.0) return ORC_E_INVAL;
     int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
     int *order = (int *)malloc(sizeof(int) * (size_t)n);
     double *X = (double *)malloc(sizeof(double) * 3 * (size_t)n), *V = (double *)malloc(sizeof(double) * 3 * (size_t)n);
@@ -1236,7 +1240,8 @@ int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t 
     int rc = scratch_alloc(&s, n);
     if (!rc && (!parent || !level || !order || !X || !V)) rc = ORC_E_NOMEM;
     if (rc) goto out;
-    memcpy(parent, parents, sizeof(int) * (size_t)n);
+    if (parents) memcpy(parent, parents, sizeof(int) * (size_t)n);
+    else if ((rc = orc_mst_prim(n, x, orc_root_nearest_com(n, m, x), parent, level, order))) goto out;
     if (orc_tree_levels(n, parent, level, order) < 0) { rc = ORC_E_INVAL; goto out; }
     for (int u = 0; u < n; ++u) {
         int q = parent[u];
@@ -1261,9 +1266,16 @@ int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t 
         if (rc) goto out;
         double T0 = com_frame_velocities(&y, y.V, s.ups, s.vt_old);
         y.B = U0 - T0;
+        int since_rebuild = 0, ch = 0;
         for (int64_t k = 0; k < nsteps && !rc; ++k) {
-            if (k > 0) rc = rebuild_to(&y, p, &s, parents + (size_t)k * (size_t)n);
+            if (parents) {
+                if (k > 0) rc = rebuild_to(&y, p, &s, parents + (size_t)k * (size_t)n);
+            } else if (since_rebuild >= p->rebuild_every) {
+                rc = rebuild(&y, p, &s, &ch);
+                since_rebuild = 0;
+            }
             if (!rc) rc = replay_step(&y, p, &s, H[k], &nf);
+            since_rebuild++;
         }
     }
     if (!rc) {

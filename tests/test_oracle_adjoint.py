@@ -128,3 +128,17 @@ def test_lagrange_weights(orc, kf):
     n = 2.0 * np.arange(1, kf + 1)
     for deg in range(kf):
         assert abs(c @ (1.0 / n ** 2) ** deg - (1.0 if deg == 0 else 0.0)) <= 1e-12 * np.abs(c).sum()
+
+
+def test_replay_with_own_trees_repeats_integration(orc):
+    """Replay without recorded trees (the driver's own MST build and rebuilds,
+    Sec. 3.5) and the recorded step lengths repeats the integration bit for
+    bit, including the end-time clip's last step: the oracle side of the
+    batched systems' replay-mode parity."""
+    import ics
+    for n, seed, t_end in ((24, 9, 0.3), (5, 2, 0.05)):
+        m, x, v = ics.plummer(n, seed)
+        xs, vs, rc, st, H, par = orc.integrate_rec(m, x, v, 0.0, t_end, 1000, orc.params(eta=1e-12))
+        assert rc == 0 and st["t_reached"] == t_end
+        xa, va, ta = orc.replay(m, x, v, 0.0, H, None, orc.params(eta=1e-12))
+        assert np.array_equal(xa, xs) and np.array_equal(va, vs) and ta == st["t_reached"]
