@@ -41,41 +41,63 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 pair-interactions/s at N=5000; batched subsystems/s vs per-system"
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 FLOPS_PER_PAIR = 20
-# FP64 VALU instructions of the force pair loop besides the one hardware
-# 1/sqrt (3 differences, 3 for r^2, 5 for the 1/sqrt refinement, 3 for m/r and
-# m/r^3, 4 accumulations), counted in the gfx950 code of k_force
-LOOP_VALU_PER_PAIR = 18
+# VALU instructions per pair besides the hardware 1/sqrt, counted in the gfx950
+# code of the two force kernels:
+#  pairwise k_force, per directed pair: 3 differences, 3 for r^2, 5 for the
+#  1/sqrt refinement, 3 for m/r and m/r^3, 4 accumulations = 18, one 1/sqrt;
+#  mutual k_force_mut, per unordered pair: 3 + 3 + 5, 2 for r^-3, 2 for the two
+#  masses' factors, 1 for phi, 3 + 3 accumulations into both bodies = 22 FP64,
+#  plus the wave rotation of the j-side sums (6 DPP moves per step of 4 pairs)
+#  and an address add per step = 23.75, one 1/sqrt
+LOOP_VALU_PER_PAIR = {0: 18.0, 1: 23.75}
+LOOP_PAIRS_PER_ITEM = {0: 1, 1: 2}      # directed pairs per loop item (a mutual item serves both bodies)
+KERNEL_NAME = {0: "k_force (pairwise FP64 pair loop)", 1: "k_force_mut (mutual FP64 pair loop)"}
 BATCH_T_END = 1e-2
 BATCH_ETA = 1e-12
 # HBM bytes per k_force launch on this workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
 # valid only for the force-kernel sources with this hash.
-FORCE_TRAFFIC = {"sha256": "5b8f31bf1b5fe41179ab371d93b3a576cf1e5cffe0a7c9d9f0335f3c79b10985",
-                 "fetch_bytes": 12840207.0, "write_bytes": 8406907.0,
-                 # executed FP64 flops per directed pair, 64 (ADD + MUL + TRANS + 2 FMA)_F64 over
-                 # 64 TRANS_F64 (rocprofv3 SQ_INSTS_VALU_*_F64 counters of the same kernel)
-                 "exec_flops_per_pair": 27.05}
+# (per force kernel kind; None where not measured for the current sources)
+FORCE_TRAFFIC = {}
 
 
-def force_traffic():
-    """Measured HBM bytes per force launch if the kernel is the one measured, else None."""
+def _force_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_force.hip", "pair.h"):
+    for f in ("kernels_force.hip", "pair.h", "common.h"):
         with open(os.path.join(ROOT, "paper_2001_03180_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != FORCE_TRAFFIC["sha256"]:
+    return h.hexdigest()
+
+
+def force_traffic(kind):
+    """Measured HBM bytes per force launch if the kernel is the one measured, else None."""
+    t = FORCE_TRAFFIC.get(kind)
+    if not t or t["sha256"] != _force_sources_hash():
         return None
-    return FORCE_TRAFFIC["fetch_bytes"] + FORCE_TRAFFIC["write_bytes"]
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
-def force_exec_flops_per_pair():
-    """Executed FP64 flops per pair if the kernel is the one measured, else None."""
-    return FORCE_TRAFFIC["exec_flops_per_pair"] if force_traffic() is not None else None
+def force_exec_flops_per_pair(kind):
+    """Executed FP64 flops per directed pair if the kernel is the one measured, else None."""
+    return FORCE_TRAFFIC[kind]["exec_flops_per_pair"] if force_traffic(kind) is not None else None
+
+
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(m, x, v, eta, threads):
-    """Oracle GBS steps on the host (bounded sample)."""
+    """Oracle on the host (bounded samples): one GBS step on all threads, and
+    one force evaluation on one thread."""
     import numpy as np
     import oracle
     p = oracle.params(eta=eta, nthreads=threads)
@@ -90,9 +112,15 @@ def cpu_baseline(m, x, v, eta, threads):
     dt = time.perf_counter() - t0
     n = len(m)
     pairs = out[6] * n * (n - 1)
+    t0 = time.perf_counter()
+    oracle.force(m, parent, X, rho, oracle.params(eta=eta, nthreads=1))
+    dt1 = time.perf_counter() - t0
     return dict(value=pairs / dt, unit="pair-interactions/s", cores=threads, kind="oracle",
                 sample=f"one GBS step (k_fix=8: {out[6]} force evaluations) at N_p={n}, "
-                       f"{dt:.1f} s on {threads} OpenMP threads")
+                       f"{dt:.1f} s on {threads} OpenMP threads; one force evaluation on 1 thread in {dt1:.2f} s",
+                one_thread={"value": n * (n - 1) / dt1, "unit": "pair-interactions/s", "cores": 1,
+                            "sample": f"one force evaluation at N_p={n}"},
+                gbs_steps_per_s=1.0 / dt, cpu_model=cpu_model(), nproc=os.cpu_count())
 
 
 def bench_batch(M, ctx, threads, do_cpu, n_single=12, n_cpu=32):
@@ -409,10 +437,25 @@ def main():
     eta = wl["eta"]
     base = dict(eta=eta, k_fix=8, n_d=2)
 
-    # warmup: from the initial conditions (absorbs the first-step halvings)
-    xw, vw, rc, stw = ctx.integrate(m, x, v, 0.0, wl["t_end"], M.params(max_steps=args.warmup, **base),
-                                    allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
-    t1, h1 = stw["t_reached"], stw["h_next"]
+    # warmup from the initial conditions into the step controller's steady
+    # state, whatever --warmup asks: at least that many step attempts, then
+    # chunks of 10 until one chunk is at least 80% accepted (the first-step
+    # halvings are over), continuing with the controller's proposed step
+    allow = (M.OK, M.W_TIME_TOL, M.E_MAXSTEPS)
+    xw, vw, t1, h1 = x, v, 0.0, 0.0
+    warm_att = warm_acc = 0
+    chunk = max(args.warmup, 1)
+    for _ in range(100):
+        xw, vw, rc, stw = ctx.integrate(m, xw, vw, t1, wl["t_end"], M.params(max_steps=chunk, h_init=h1, **base),
+                                        allow=allow)
+        att = stw["steps_accepted"] + stw["steps_rejected"]
+        warm_att += att
+        warm_acc += stw["steps_accepted"]
+        t1, h1 = stw["t_reached"], stw["h_next"]
+        if warm_att >= args.warmup and stw["steps_accepted"] >= 0.8 * att and warm_acc >= 10:
+            break
+        chunk = 10
+    print(f"[bench] warmup: {warm_att} attempts ({warm_acc} accepted) to t={t1:.3e}", file=sys.stderr, flush=True)
     # timed: continue from the warmed-up state with the controller's step
     mt = torch.tensor(m, device="cuda")
     xt = torch.tensor(xw, device="cuda")
@@ -425,11 +468,15 @@ def main():
     wall = time.perf_counter() - t0
     # force-kernel timing: HIP events around every force launch (on the
     # library's stream) over a second pass of the same steps; kept out of the
-    # timed pass because each event pair adds launch gaps
+    # timed pass because each event pair adds launch gaps.  The roofline is
+    # that of the dominant kernel (the one with the most launch time).
     ctx.profile_enable(True)
     ctx.integrate(mt, xt, vt, t1, wl["t_end"], p, allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
-    launches, kern_ms, kern_pairs = ctx.profile_read()
+    all_launches, all_ms, all_pairs = ctx.profile_read()
+    per_kind = {k: ctx.profile_read_kernel(k) for k in (0, 1)}
     ctx.profile_enable(False)
+    kind = max(per_kind, key=lambda k: per_kind[k][1])
+    launches, kern_ms, kern_pairs = per_kind[kind]
     steps_done = st["steps_accepted"] + st["steps_rejected"]
     pairs = st["force_evals"] * n * (n - 1)
     value = pairs / wall
@@ -439,7 +486,7 @@ def main():
     # instruction-mix ceiling of the pair loop at the clock the chip sustains
     fma_cyc, rsq_cyc = ctx.issue_rates()
     n_simd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
-    mix_cycles = LOOP_VALU_PER_PAIR * fma_cyc + rsq_cyc
+    mix_cycles = (LOOP_VALU_PER_PAIR[kind] * fma_cyc + rsq_cyc) / LOOP_PAIRS_PER_ITEM[kind]
     ceiling_pairs = n_simd * 2.4e9 * 64 / mix_cycles
     launch_pairs_per_s = kern_pairs / (kern_ms * 1e-3)
     out = {
@@ -465,29 +512,38 @@ def main():
             "mst_rebuilds": st["mst_rebuilds"],
             "t_start": t1,
             "t_reached": st["t_reached"],
+            "warmup_attempts": warm_att,
+            "warmup_accepted": warm_acc,
         },
+        "gbs_steps_accepted_per_s": st["steps_accepted"] / wall,
+        "gbs_step_attempts_per_s": steps_done / wall,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": force_traffic(),
-            "kernel": "k_force (FP64 pair loop)",
+            "traffic": force_traffic(kind),
+            "kernel": KERNEL_NAME[kind],
             "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
+            "all_force_launches": {"launches": all_launches, "avg_launch_us": all_ms * 1e3 / max(all_launches, 1),
+                                   "tflops_algorithmic": FLOPS_PER_PAIR * all_pairs / (all_ms * 1e-3) / 1e12,
+                                   "by_kernel": {KERNEL_NAME[k]: {"launches": v[0], "ms": v[1]}
+                                                 for k, v in per_kind.items()}},
             "algorithmic_flops_per_pair": FLOPS_PER_PAIR,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "executed": None if force_exec_flops_per_pair() is None else {
-                "flops_per_pair": force_exec_flops_per_pair(),
-                "tflops": force_exec_flops_per_pair() * launch_pairs_per_s / 1e12,
-                "frac_of_peak": force_exec_flops_per_pair() * launch_pairs_per_s / 1e12 / PEAK_FP64_TFLOPS,
-                "note": "FP64 VALU flops as executed, rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64",
+            "executed": None if force_exec_flops_per_pair(kind) is None else {
+                "flops_per_pair": force_exec_flops_per_pair(kind),
+                "tflops": force_exec_flops_per_pair(kind) * launch_pairs_per_s / 1e12,
+                "frac_of_peak": force_exec_flops_per_pair(kind) * launch_pairs_per_s / 1e12 / PEAK_FP64_TFLOPS,
+                "note": "FP64 VALU flops as executed per directed pair, rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64",
             },
             "issue_ceiling": {
                 "fma_cycles_per_wave_op": fma_cyc,
                 "rsq_cycles_per_wave_op": rsq_cyc,
-                "loop_valu_per_pair": LOOP_VALU_PER_PAIR,
+                "loop_valu_per_item": LOOP_VALU_PER_PAIR[kind],
+                "directed_pairs_per_item": LOOP_PAIRS_PER_ITEM[kind],
                 "pairs_per_s": ceiling_pairs,
                 "tflops_algorithmic": FLOPS_PER_PAIR * ceiling_pairs / 1e12,
                 "frac_of_ceiling": launch_pairs_per_s / ceiling_pairs,

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define MSTAR_ABI_VERSION 1
+#define MSTAR_ABI_VERSION 2
 
 #define MSTAR_OK 0
 #define MSTAR_E_INVAL -1       /* invalid argument or parameter */
@@ -73,7 +73,11 @@ typedef struct {
     int32_t max_halvings;   /* consecutive rejections before MSTAR_E_NOCONV; default 60 */
     int32_t max_time_iter;  /* clipped end-time steps before MSTAR_W_TIME_TOL; default 8 */
     int32_t rebuild_every;  /* accepted steps between MST rebuilds (Sec. 3.5); default 1 */
-    int32_t reserved;
+    int32_t accept_rule;    /* where eq. gbs-criterion is judged: 0 (default) at k_fix, the fixed
+                               division count of Sec. 4.2, returning T_{k_fix,k_fix}; 1 at the first
+                               k = 2..k_fix whose error measure eps_k <= eta (the serial rule of
+                               Sec. 2.3), returning T_{k,k} and taking eq. hnext with that k.  All
+                               k_fix divisions are computed either way.  Not in the batched call. */
 } mstar_params;
 
 /* Per-call statistics. */
@@ -206,6 +210,11 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
  * evaluations. */
 int mstar_profile_enable(mstar_ctx *ctx, int enable);
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
+/* The same totals for one force kernel: kind 0 the pairwise kernel (each
+ * directed pair formed by its receiving body), 1 the mutual kernel (each
+ * unordered pair once, applied to both bodies).  Batched launches are not
+ * included.  Errors: MSTAR_E_INVAL for another kind. */
+int mstar_profile_read_kernel(mstar_ctx *ctx, int32_t kind, int64_t *launches, double *kernel_ms, double *pairs);
 
 /* Coordinate round trips (Sec. 3.5): for each of n_sys systems (bodies
  * offsets[s] .. offsets[s+1]-1, 2 <= N <= 512), n_cycles times: build the
@@ -279,6 +288,16 @@ int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_
                           const double *m, double *x, double *v, const double *t0, const double *t_end,
                           mstar_batch_stats *stats);
 
+/* mstar_integrate_batch that also records the fictitious step H of every
+ * accepted step of every system: H [n_sys][rec_cap] (host memory; row s
+ * holds system s's first min(stats[s].steps_accepted, rec_cap) steps, the
+ * rest of the row is unspecified).  The record lets a system be replayed step for step (as
+ * mstar_integrate_record does for one system).  Errors as
+ * mstar_integrate_batch, and MSTAR_E_INVAL for a NULL H or rec_cap < 1. */
+int mstar_integrate_batch_record(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                                 const double *m, double *x, double *v, const double *t0, const double *t_end,
+                                 mstar_batch_stats *stats, int64_t rec_cap, double *H);
+
 /* Read or replace the launch shape used for k_fix (2..8). */
 int mstar_batch_get_config(mstar_ctx *ctx, int32_t k_fix, mstar_batch_config *cfg);
 int mstar_batch_set_config(mstar_ctx *ctx, int32_t k_fix, const mstar_batch_config *cfg);
@@ -319,12 +338,30 @@ int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const do
 
 /* Adjoint of mstar_replay: given the cotangent (gx, gv [n][3], gt) of the end
  * state (x, v, t), returns gx0, gv0 = the gradient of <gx, x> + <gv, v> + gt t
- * with respect to the initial x0, v0.  Checkpoints the state every
+ * with respect to the initial x0, v0, and (gm [n], nullable) with respect to
+ * the masses m, which enter the accelerations, the force function U of the
+ * kicks' time transformation, the kinetic energy T of the drifts' and the
+ * binding energy B = U(x0) - T(v0).  Checkpoints the state every
  * checkpoint_every steps and recomputes each segment (and each step's
  * substep states) during the reverse pass. */
 int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
                          const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
-                         const double *gx, const double *gv, double gt, double *gx0, double *gv0);
+                         const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm);
+
+/* Record and reverse in one call: integrate from (x0, v0) at t0 toward t_end
+ * (mstar_integrate's driver, Sec. 2.4) until n_steps steps are accepted or
+ * t_end is reached, then return the gradient of <gxT, x> + <gvT, v> + gtT t
+ * at the end state with respect to x0, v0 (gx0, gv0 [n][3]) and the masses
+ * (gm [n], nullable), with the step sizes and MST topologies of the recorded
+ * run frozen (as mstar_replay_adjoint).  x0, v0 are not modified; stats
+ * (nullable) receives the forward run's statistics (its steps_accepted is
+ * the number of steps differentiated).  Pointers per params->flags.
+ * Errors: MSTAR_E_INVAL, MSTAR_E_UNSUPPORTED (n > 1024, beta != 0), the
+ * integrator's errors (the gradient is then not computed), device errors. */
+int mstar_integrate_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
+                            const double *v0, double t0, double t_end, int64_t n_steps, int32_t checkpoint_every,
+                            const double *gxT, const double *gvT, double gtT, double *gx0, double *gv0, double *gm,
+                            mstar_stats *stats);
 
 /* Transposed Jacobian of the accelerations applied to w [n][3] (the force
  * Hessian-vector product of the reverse kick): out_i = G sum_{j != i}

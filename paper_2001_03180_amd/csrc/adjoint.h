@@ -25,6 +25,8 @@ struct AdjDev {
     double *Lt, *LB;        // cotangent of t; accumulated cotangent of B
     d4 *Sr, *Sv;            // [kf][n] cotangents of the division start states
     double *St, *SB;        // [kf]
+    double *Sm;             // [kf][n] cotangent of the masses from one division
+    double *Lm;             // [n] cotangent of the masses, accumulated over the reverse pass
     d4 *rst, *vst;          // stored kick / drift inputs
     double *sc;             // [ops][kAdjOpScal]
 };
@@ -36,7 +38,9 @@ void launch_adj_combine(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *
                         d4 *Ov, double *Ot);
 void launch_adj_rev(const AdjDev &d, hipStream_t s);
 void launch_adj_combine_rev(const AdjDev &d, hipStream_t s);
-void launch_adj_finish(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, double *gx, double *gv);
+void launch_adj_finish(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, double *gx, double *gv,
+                       double *gm);
+void launch_adj_zero_n(hipStream_t s, int n, double *p);
 void launch_force_hvp(hipStream_t s, int n, double G, const double *m, const double *x, const double *w,
                       double *out);
 void launch_adj_pack(hipStream_t s, int n, const double *x, d4 *o, double t, double *ot);

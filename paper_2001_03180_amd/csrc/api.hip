@@ -48,6 +48,8 @@ struct mstar_ctx {
     // profiling of the force kernel
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<int> ev_kind;          // force kernel of each event pair: 0 pairwise, 1 mutual
+    std::vector<double> ev_pairs;      // directed pairs of each launch
     size_t ev_used = 0;
     int64_t prof_launches = 0;
     double prof_pairs = 0.0;
@@ -68,6 +70,8 @@ struct mstar_ctx {
     hipGraphExec_t b_exec = nullptr;   // captured reset + batch kernel
     int b_key_kf = 0, b_key_wl = -1, b_key_nwg = 0;
     hipEvent_t b_ev[2] = {nullptr, nullptr};
+    double *b_hrec = nullptr;          // [n_sys][cap] accepted steps of a recording batched call
+    size_t b_hrec_cap = 0;
     // one GBS step attempt of mstar_integrate* captured as a graph
     hipGraphExec_t s_exec = nullptr;
     std::string s_key;                 // what the captured launches depend on
@@ -78,6 +82,10 @@ struct mstar_ctx {
     int ws_gen = 0;                    // bumped whenever device buffers move
     int mst_spare = 1;                 // Boruvka rounds queued beyond the previous build's count
     int force_cap[3] = {0, 0, 0};      // resident force workgroups per chip, by close-pair kernel kind
+    int force_mode = 0;                // 0: mutual kernel where it applies, 1: pairwise only, 2: mutual for any N
+    int mut_wps = 3;                   // waves per SIMD the mutual kernel's work is split for
+    int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
+    int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
     bool ext_on = false;               // an external field applies to the running integration
     ExtField h_ext{};                  // host copy of that field
     // frozen-controller replay and adjoint (kernels_adjoint.hip)
@@ -92,11 +100,19 @@ struct mstar_ctx {
     d4 *sgr = nullptr, *sgv = nullptr;    // states of one checkpoint segment
     double *sgt = nullptr;
     double *a_m = nullptr, *a_c = nullptr, *a_io[4] = {nullptr, nullptr, nullptr, nullptr};
+    double *a_gm = nullptr;               // mass gradient [n]
 };
 
 namespace {
 
 constexpr int kNsplitMax = 32;
+// The mutual force kernel serves N in [kMutMinN, kMutMaxN] (its j-side
+// partials grow as N^2); each of its waves takes at least kMutLmin steps.
+constexpr int kMutMinN = 1024;
+constexpr int kMutMaxN = 20000;
+constexpr int kMutSoloN = 16384;
+constexpr long long kMutLmin = 64;     // >= 64: a j-block is never cut into more than two pieces
+constexpr int kMutMaxW = 128;          // i-side partials per row and launch (bounds the buffers)
 
 int fail(mstar_ctx *c, int code, const char *fmt, ...) {
     if (c) {
@@ -128,11 +144,29 @@ int dalloc(mstar_ctx *ctx, T **p, size_t count) {
     return MSTAR_OK;
 }
 
+// Mutual force kernel geometry for n bodies and the step count L per wave
+// (FLay; L is raised to at least Lmin).
+FLay mut_geometry(int n, long long total_waves_hint, long long Lmin) {
+    FLay f{};
+    f.mut = 1;
+    f.ipl = kMutIPL;
+    f.nb = (n + 63) / 64;
+    f.npr = (f.nb + kMutIPL - 1) / kMutIPL;
+    f.Ec = mut_rs(f, f.npr);
+    // no row (the first is the longest) may span more than kMutMaxW waves
+    const long long row0 = mut_rs(f, 1);
+    Lmin = std::max(Lmin, (row0 + kMutMaxW - 2) / (kMutMaxW - 1));
+    f.L = std::max(Lmin, total_waves_hint > 1 ? (f.Ec + total_waves_hint - 1) / total_waves_hint : Lmin);
+    f.maxw = (int)((row0 + f.L - 1) / f.L) + 1;
+    return f;
+}
+
 void free_workspace(mstar_ctx *ctx) {
     for (void *p : ctx->allocs) (void)hipFree(p);
     ctx->allocs.clear();
     ctx->d = Dev{};
     ctx->cap_n = 0;
+    ctx->mut_cap_n = 0;
 }
 
 int ensure(mstar_ctx *ctx, int n) {
@@ -165,13 +199,24 @@ int ensure(mstar_ctx *ctx, int n) {
     A(d.P, kMaxDiv * N) A(d.Vt, kMaxDiv * N) A(d.dX, kMaxDiv * N) A(d.dV, kMaxDiv * N) A(d.dX1, N) A(d.dV1, N)
     A(d.dP, kMaxDiv * N) A(d.dVt, kMaxDiv * N) A(d.dP1, N) A(d.dVt1, N) A(d.akick, kMaxDiv * N)
     A(d.dscal, kMaxDiv) A(d.dscal1, 1) A(d.part, (size_t)kMaxDiv * kNsplitMax * N)
-    A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, nkwg + 1)
+    A(d.Upart, (size_t)kMaxDiv * nib * kNsplitMax) A(d.Tpart, (size_t)kMaxDiv * (4 * nkwg)) A(d.epspart, (size_t)(nkwg + 1) * kMaxDiv)
     A(d.tsA, N) A(d.tsB, N) A(d.tsC, N) A(d.tsD, N) A(d.tsE, N) A(d.tsF, N) A(d.ancA, N) A(d.ancB, N)
     A(d.bor_w, (size_t)kNsplitMax * N) A(d.bor_j, (size_t)kNsplitMax * N) A(d.comp, N) A(d.ecomp_tmp, N)
     A(d.cw, N) A(d.cidx, N) A(d.tgt, N) A(d.ncomp, 1)
     A(d.deg, N) A(d.off, N + 1) A(d.fill, N) A(d.adj, 2 * N) A(d.arcpos, 2 * N) A(d.nxtA, 2 * N)
     A(d.nxtB, 2 * N) A(d.rkA, 2 * N) A(d.rkB, 2 * N) A(d.cnt, N + 1) A(d.scr, N) A(d.mo, N) A(d.dOm0, N)
     A(ctx->xin, 3 * N) A(ctx->vin, 3 * N) A(ctx->xout, 3 * N)
+    ctx->mut_cap_n = 0;
+    if (ctx->force_mode == 2 || (ctx->force_mode == 0 && cap >= kMutMinN)) {
+        const int mcap = ctx->force_mode == 2 ? cap : std::min(cap, kMutMaxN);
+        const FLay g = mut_geometry(mcap, 1, kMutLmin);
+        d.mip_s = (size_t)g.npr * kMutMaxW * 64 * kMutIPL;   // every launch has maxw <= kMutMaxW
+        d.mjp_s = (size_t)2 * g.npr * mcap;
+        d.mup_s = (size_t)g.npr * kMutMaxW + g.nb;
+        A(d.mip, kMaxDiv * d.mip_s) A(d.mjp, kMaxDiv * d.mjp_s) A(d.mcp, kMaxDiv * (size_t)mcap)
+        A(d.mup, kMaxDiv * d.mup_s)
+        ctx->mut_cap_n = mcap;
+    }
 #undef A
     HIPCK(hipMemsetAsync(d.dX, 0, sizeof(d4) * kMaxDiv * N, ctx->stream));
     HIPCK(hipMemsetAsync(d.dV, 0, sizeof(d4) * kMaxDiv * N, ctx->stream));
@@ -263,6 +308,11 @@ int force_cap(mstar_ctx *ctx, int nd) {
     return ctx->force_cap[k];
 }
 
+// Layout of one force launch over nact evaluations: the mutual kernel where
+// it applies (no TTL function, N_d <= 2, buffers sized for this N), else the
+// pairwise kernel with j-splits sized to fill the chip.
+FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om);
+
 // Number of j-splits of one force launch over `nact` divisions.  The
 // workgroups of a launch all take about the same time, so they run in rounds
 // of `cap` (resident workgroups of the whole chip); the split count is the
@@ -284,6 +334,27 @@ int nsplit_for(const Dev &d, int nact, int cap) {
     return hi;
 }
 
+FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om) {
+    const Dev &d = ctx->d;
+    // the mutual kernel's waves split the launch's pairs evenly, one range per
+    // wave; a single evaluation below kMutSoloN has too few steps to give every
+    // SIMD its waves, and the pairwise kernel is faster there
+    if (!om && nd <= 2 && ctx->force_mode != 1 && d.n <= ctx->mut_cap_n &&
+        (ctx->force_mode == 2 || (d.n >= kMutMinN && (nact > 1 || d.n >= kMutSoloN)))) {
+        FLay f = mut_geometry(d.n, 1, kMutLmin);   // L = the shortest allowed
+        const long long total = (long long)nact * f.Ec;
+        const long long waves = std::max(1, ctx->mut_waves);
+        f.L = std::max(f.L, (total + waves - 1) / waves);
+        f.maxw = (int)((mut_rs(f, 1) + f.L - 1) / f.L) + 1;
+        f.ncorr = nd > 0 ? 1 : 0;
+        return f;
+    }
+    FLay f{};
+    f.mut = 0;
+    f.nparts = force_parts(nsplit_for(d, nact, force_cap(ctx, nd)), nd);
+    return f;
+}
+
 int check_params(mstar_ctx *ctx, const mstar_params *p) {
     if (!p || p->struct_size != sizeof(mstar_params)) return fail(ctx, MSTAR_E_INVAL, "params: bad struct_size");
     if (!(p->G > 0.0) || !std::isfinite(p->G)) return fail(ctx, MSTAR_E_INVAL, "params: G must be > 0");
@@ -298,7 +369,7 @@ int check_params(mstar_ctx *ctx, const mstar_params *p) {
         return fail(ctx, MSTAR_E_INVAL, "params: omega_mass_max must be finite");
     if (!(p->a_gbs > 0.0) || !(p->f_min > 0.0) || !(p->f_max >= p->f_min) || !(p->q_first > 0.0) ||
         !(p->t_tol >= 0.0) || p->max_steps < 1 || p->max_halvings < 0 || p->max_time_iter < 0 ||
-        p->rebuild_every < 0 || !(p->h_init >= 0.0))
+        p->rebuild_every < 0 || !(p->h_init >= 0.0) || p->accept_rule < 0 || p->accept_rule > 1)
         return fail(ctx, MSTAR_E_INVAL, "params: out of range");
     return MSTAR_OK;
 }
@@ -391,7 +462,7 @@ int load_tree(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent) 
     return MSTAR_OK;
 }
 
-int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit, bool om) {
+int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, const FLay &f, bool om) {
     if (ctx->prof) {
         if (ctx->ev_used == ctx->ev.size()) {
             hipEvent_t a, b;
@@ -399,14 +470,22 @@ int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, int nsplit, bool om) 
             HIPCK(hipEventCreate(&b));
             ctx->ev.push_back({a, b});
         }
-        auto &e = ctx->ev[ctx->ev_used++];
+        const size_t k = ctx->ev_used++;
+        auto &e = ctx->ev[k];
         HIPCK(hipEventRecord(e.first, ctx->stream));
-        launch_force(ctx->d, ctx->stream, sl, nd, nsplit, om);
+        launch_force(ctx->d, ctx->stream, sl, nd, f, om);
         HIPCK(hipEventRecord(e.second, ctx->stream));
+        const double pairs = (double)sl.nact * (double)ctx->d.n * (double)(ctx->d.n - 1);
+        if (ctx->ev_kind.size() < ctx->ev.size()) {
+            ctx->ev_kind.resize(ctx->ev.size());
+            ctx->ev_pairs.resize(ctx->ev.size());
+        }
+        ctx->ev_kind[k] = f.mut ? 1 : 0;
+        ctx->ev_pairs[k] = pairs;
         ctx->prof_launches++;
-        ctx->prof_pairs += (double)sl.nact * (double)ctx->d.n * (double)(ctx->d.n - 1);
+        ctx->prof_pairs += pairs;
     } else {
-        launch_force(ctx->d, ctx->stream, sl, nd, nsplit, om);
+        launch_force(ctx->d, ctx->stream, sl, nd, f, om);
     }
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -438,11 +517,10 @@ int prepare_start(mstar_ctx *ctx, const mstar_params *p, bool transform, bool wi
         SlotList sl{};
         sl.nact = 1;
         sl.slot[0] = kBase;
-        const int ns = nsplit_for(d, 1, force_cap(ctx, p->n_d));
-        int rc = prof_force(ctx, sl, p->n_d, ns, ttl_on(p));
+        const FLay f = plan_force(ctx, 1, p->n_d, ttl_on(p));
+        int rc = prof_force(ctx, sl, p->n_d, f, ttl_on(p));
         if (rc) return rc;
-        launch_reduce_start(d, ctx->stream, kBase, p->G, force_parts(ns, p->n_d), d.a0, &d.ctl->U0, ttl_on(p),
-                            ttl_on(p));
+        launch_reduce_start(d, ctx->stream, kBase, p->G, f, d.a0, &d.ctl->U0, ttl_on(p), ttl_on(p));
         if (ctx->ext_on) launch_ext(d, ctx->stream, sl, 1);
         if (nforce) ++*nforce;
     }
@@ -492,11 +570,11 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
         }
         if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p), ctx->ext_on);
         if (!fk.nact) continue;
-        const int ns = nsplit_for(d, fk.nact, force_cap(ctx, p->n_d));
-        int rc = prof_force(ctx, fk, p->n_d, ns, ttl_on(p));
+        const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p));
+        int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p));
         if (rc) return rc;
         if (ctx->ext_on) launch_ext(d, ctx->stream, fk, 0);
-        launch_kick(d, ctx->stream, fk, force_parts(ns, p->n_d), p->G, ttl_of(p), ctx->ext_on);
+        launch_kick(d, ctx->stream, fk, f, p->G, ttl_of(p), ctx->ext_on);
         if (nforce) *nforce += fk.nact;
     }
     HIPCK(hipGetLastError());
@@ -613,6 +691,17 @@ int store_state(mstar_ctx *ctx, uint32_t flags, int64_t n, double *X, double *V,
     return MSTAR_OK;
 }
 
+// Neville-Aitken extrapolation, error test and step control of one attempt
+// (Sec. 2.3, 4.2): judged at k_fix, or (accept_rule 1) at the first order
+// whose error passes, whose extrapolation is then the result.
+void enqueue_extrapolation(mstar_ctx *ctx, const mstar_params *p, bool ex) {
+    const Dev &d = ctx->d;
+    const int rule = p->accept_rule == 1 ? 1 : 0;
+    launch_extrapolate(d, ctx->stream, p->k_fix, ttl_of(p), kBase, ex, rule);
+    launch_control(d, ctx->stream, p->k_fix, p->eta, p->a_gbs, p->f_min, p->f_max, rule);
+    if (rule == 1) launch_extrap_pick(d, ctx->stream, p->k_fix, ex);
+}
+
 }  // namespace
 
 extern "C" {
@@ -641,6 +730,7 @@ void mstar_params_default(mstar_params *p) {
     p->max_halvings = 60;
     p->max_time_iter = 8;
     p->rebuild_every = 1;
+    p->accept_rule = 0;
 }
 
 const char *mstar_strerror(int code) {
@@ -681,6 +771,17 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         const int v = std::atoi(e);
         if (v >= 0 && v <= 8) ctx->mst_spare = v;
     }
+    // force kernel choice (MSTAR_FORCE_KERNEL = pairwise | mutual; default:
+    // the mutual kernel for N in [kMutMinN, kMutMaxN]) and the waves per SIMD
+    // its work is split for (MSTAR_MUT_WPS, 1..8)
+    if (const char *e = std::getenv("MSTAR_FORCE_KERNEL")) {
+        if (!strcmp(e, "pairwise")) ctx->force_mode = 1;
+        else if (!strcmp(e, "mutual")) ctx->force_mode = 2;
+    }
+    if (const char *e = std::getenv("MSTAR_MUT_WPS")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 8) ctx->mut_wps = v;
+    }
     if (hipHostMalloc((void **)&ctx->h_blk, sizeof(CtlBlock), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         mstar_destroy(ctx);
@@ -694,6 +795,9 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         mstar_destroy(ctx);
         return MSTAR_E_DEVICE;
     }
+    // resident waves of the mutual kernel: mut_wps per SIMD (4 per CU), the same
+    // number on every SIMD, within the kernel's occupancy
+    ctx->mut_waves = std::max(1, std::min(force_mut_blocks_per_cu() / 4, ctx->mut_wps)) * 4 * ctx->num_cu;
     for (auto &c : ctx->bcfg) {
         memset(&c, 0, sizeof c);
         c.struct_size = sizeof(mstar_batch_config);
@@ -714,6 +818,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     for (void *p : ctx->a_allocs) (void)hipFree(p);
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
+    if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
     if (ctx->h_bargs) (void)hipHostFree(ctx->h_bargs);
     if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
     if (ctx->s_exec) (void)hipGraphExecDestroy(ctx->s_exec);
@@ -754,6 +859,26 @@ int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, dou
     if (launches) *launches = ctx->prof_launches;
     if (kernel_ms) *kernel_ms = tot;
     if (pairs) *pairs = ctx->prof_pairs;
+    return MSTAR_OK;
+}
+
+int mstar_profile_read_kernel(mstar_ctx *ctx, int32_t kind, int64_t *launches, double *kernel_ms, double *pairs) {
+    if (!ctx || kind < 0 || kind > 1) return MSTAR_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    int64_t nl = 0;
+    double tot = 0.0, pr = 0.0;
+    for (size_t k = 0; k < ctx->ev_used; ++k) {
+        if (ctx->ev_kind[k] != kind) continue;
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
+        tot += ms;
+        pr += ctx->ev_pairs[k];
+        ++nl;
+    }
+    if (launches) *launches = nl;
+    if (kernel_ms) *kernel_ms = tot;
+    if (pairs) *pairs = pr;
     return MSTAR_OK;
 }
 
@@ -817,11 +942,10 @@ int mstar_force(mstar_ctx *ctx, const mstar_params *params, int64_t n, const dou
     SlotList sl{};
     sl.nact = 1;
     sl.slot[0] = kBase;
-    const int ns = nsplit_for(d, 1, force_cap(ctx, params->n_d));
     const bool om = ttl_on(params);
-    if ((rc = prof_force(ctx, sl, params->n_d, ns, om))) return rc;
-    launch_reduce_start(d, ctx->stream, kBase, params->G, force_parts(ns, params->n_d), d.a0, &d.ctl->U0, om,
-                        false);
+    const FLay f = plan_force(ctx, 1, params->n_d, om);
+    if ((rc = prof_force(ctx, sl, params->n_d, f, om))) return rc;
+    launch_reduce_start(d, ctx->stream, kBase, params->G, f, d.a0, &d.ctl->U0, om, false);
     launch_unpack3(ctx->stream, d.a0, ctx->xout, (int)n);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, acc, ctx->xout, sizeof(double) * 3 * n))) return rc;
@@ -876,8 +1000,7 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
     int nl[16];
     for (int k = 0; k < params->k_fix; ++k) nl[k] = 2 * (k + 1);
     if ((rc = run_divisions(ctx, params, nl, params->k_fix, nullptr))) return rc;
-    launch_extrapolate(ctx->d, ctx->stream, params->k_fix, ttl_of(params), kBase, false);
-    launch_control(ctx->d, ctx->stream, params->k_fix, params->eta, params->a_gbs, params->f_min, params->f_max);
+    enqueue_extrapolation(ctx, params, false);
     launch_commit(ctx->d, ctx->stream, 1, 0);
     HIPCK(hipGetLastError());
     if ((rc = store_state(ctx, flags, n, X, V, scal))) return rc;
@@ -897,8 +1020,7 @@ int enqueue_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const i
     launch_set_h(d, ctx->stream, 0.0, t_end, 1, ttl_of(p), 1);
     int rc = run_divisions(ctx, p, nl, p->k_fix, nforce);
     if (rc) return rc;
-    launch_extrapolate(d, ctx->stream, p->k_fix, ttl_of(p), kBase, ctx->ext_on);
-    launch_control(d, ctx->stream, p->k_fix, p->eta, p->a_gbs, p->f_min, p->f_max);
+    enqueue_extrapolation(ctx, p, ctx->ext_on);
     launch_commit(d, ctx->stream, 1, 0);
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -947,7 +1069,7 @@ int run_attempt(mstar_ctx *ctx, const mstar_params *p, double t_end, const int *
     if ((p->flags & MSTAR_EAGER) || ctx->prof) return enqueue_attempt(ctx, p, t_end, nl, nforce);
     // everything the captured kernel arguments are made of
     const double kd[] = {p->G, p->eta, p->alpha, p->beta, p->gamma, p->a_gbs, p->f_min, p->f_max, t_end};
-    const int ki[] = {p->k_fix, p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0};
+    const int ki[] = {p->k_fix, p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, p->accept_rule};
     std::string key((const char *)kd, sizeof kd);
     key.append((const char *)ki, sizeof ki);
     (void)force_cap(ctx, p->n_d);   // occupancy query outside any capture
@@ -1162,6 +1284,7 @@ int ensure_batch(mstar_ctx *ctx, int64_t n_sys, int64_t n_tot) {
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     ctx->b_allocs.clear();
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
+    if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
     ctx->h_bstat = nullptr;
     if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
     ctx->b_exec = nullptr;
@@ -1203,6 +1326,7 @@ int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const i
     if (rc) return rc;
     if (ttl_on(p)) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: beta != 0 (TTL) is not implemented");
     if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: n_d > 2 is not implemented");
+    if (p->accept_rule != 0) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: accept_rule 1 is not implemented");
     if (p->k_fix > kBatchMaxKF)
         return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: k_fix > %d is not implemented", kBatchMaxKF);
     if (n_sys < 1 || !off || !t_end) return fail(ctx, MSTAR_E_INVAL, "batch: need n_sys >= 1, offsets and t_end");
@@ -1234,7 +1358,7 @@ int check_config(mstar_ctx *ctx, const mstar_batch_config *c) {
 // system results to ctx->h_bstat; kernel time (reset + persistent kernel).
 int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &cfg, int32_t n_sys,
               const int64_t *off, const double *md, double *xd, double *vd, const double *t0, const double *t_end,
-              double *kernel_ms) {
+              double *kernel_ms, double *hrec = nullptr, int64_t hrec_cap = 0) {
     const int kf = p->k_fix;
     const int wl = cfg.wave_lanes;
     const int wmax = wl > 0 ? cfg.wave_max_n : 0;
@@ -1270,6 +1394,8 @@ int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &c
     a.t0 = t0 ? ctx->b_t0 : nullptr;
     a.t_end = ctx->b_te;
     a.stat = ctx->b_stat;
+    a.hrec = hrec;
+    a.hrec_cap = hrec ? hrec_cap : 0;
     a.p.G = p->G;
     a.p.eta = p->eta;
     a.p.alpha = p->alpha;
@@ -1338,17 +1464,34 @@ int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &c
 
 extern "C" {
 
-int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
-                          const double *m, double *x, double *v, const double *t0, const double *t_end,
-                          mstar_batch_stats *stats) {
+static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                                const double *m, double *x, double *v, const double *t0, const double *t_end,
+                                mstar_batch_stats *stats, int64_t rec_cap, double *H) {
     if (!ctx) return MSTAR_E_INVAL;
     ctx->err.clear();
     int64_t n_tot = 0;
     int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot);
     if (rc) return rc;
     if (!m || !x || !v || !stats) return fail(ctx, MSTAR_E_INVAL, "batch: null array");
+    if (H && (rec_cap < 1 || rec_cap > ((int64_t)1 << 40) / n_sys))
+        return fail(ctx, MSTAR_E_INVAL, "batch_record: bad record capacity");
     (void)hipSetDevice(ctx->device);
     if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
+    double *hrec = nullptr;
+    if (H) {   // device record of the accepted steps, kept in the context
+        const size_t need = (size_t)n_sys * (size_t)rec_cap;
+        if (need > ctx->b_hrec_cap) {
+            if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
+            ctx->b_hrec = nullptr;
+            ctx->b_hrec_cap = 0;
+            if (hipMalloc((void **)&ctx->b_hrec, sizeof(double) * need) != hipSuccess) {
+                ctx->b_hrec = nullptr;
+                return fail(ctx, MSTAR_E_NOMEM, "batch_record: device allocation failed");
+            }
+            ctx->b_hrec_cap = need;
+        }
+        hrec = ctx->b_hrec;
+    }
     const uint32_t flags = params->flags;
     const double *md = m;
     double *xd = x, *vd = v;
@@ -1361,10 +1504,17 @@ int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_
         vd = ctx->b_v;
     }
     double ms = 0.0;
-    if ((rc = batch_run(ctx, params, ctx->bcfg[params->k_fix], n_sys, offsets, md, xd, vd, t0, t_end, &ms))) return rc;
+    if ((rc = batch_run(ctx, params, ctx->bcfg[params->k_fix], n_sys, offsets, md, xd, vd, t0, t_end, &ms, hrec,
+                        rec_cap)))
+        return rc;
     if (!is_dev(flags)) {
         HIPCK(hipMemcpyAsync(x, ctx->b_x, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
         HIPCK(hipMemcpyAsync(v, ctx->b_v, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCK(hipStreamSynchronize(ctx->stream));
+    }
+    if (H) {
+        HIPCK(hipMemcpyAsync(H, hrec, sizeof(double) * (size_t)n_sys * (size_t)rec_cap, hipMemcpyDeviceToHost,
+                             ctx->stream));
         HIPCK(hipStreamSynchronize(ctx->stream));
     }
     memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
@@ -1379,6 +1529,19 @@ int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_
         ctx->prof_batch_ms += ms;
     }
     return MSTAR_OK;
+}
+
+int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                          const double *m, double *x, double *v, const double *t0, const double *t_end,
+                          mstar_batch_stats *stats) {
+    return integrate_batch_impl(ctx, params, n_sys, offsets, m, x, v, t0, t_end, stats, 0, nullptr);
+}
+
+int mstar_integrate_batch_record(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
+                                 const double *m, double *x, double *v, const double *t0, const double *t_end,
+                                 mstar_batch_stats *stats, int64_t rec_cap, double *H) {
+    if (!H) return fail(ctx, MSTAR_E_INVAL, "batch_record: H is NULL");
+    return integrate_batch_impl(ctx, params, n_sys, offsets, m, x, v, t0, t_end, stats, rec_cap, H);
 }
 
 int mstar_batch_get_config(mstar_ctx *ctx, int32_t k_fix, mstar_batch_config *cfg) {
@@ -1485,6 +1648,7 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     if ((rc = A(&m_, N)) || (rc = A(&c_, K)) || (rc = A(&d.B, 1)) || (rc = A(&d.Er, K * N)) || (rc = A(&d.Ev, K * N)) ||
         (rc = A(&d.Et, K)) || (rc = A(&d.Lr, N)) || (rc = A(&d.Lv, N)) || (rc = A(&d.Lt, 1)) || (rc = A(&d.LB, 1)) ||
         (rc = A(&d.Sr, K * N)) || (rc = A(&d.Sv, K * N)) || (rc = A(&d.St, K)) || (rc = A(&d.SB, K)) ||
+        (rc = A(&d.Sm, K * N)) || (rc = A(&d.Lm, N)) || (rc = A(&ctx->a_gm, N)) ||
         (rc = A(&d.rst, kicks * N)) || (rc = A(&d.vst, drifts * N)) || (rc = A(&d.sc, ops * kAdjOpScal)) ||
         (rc = A(&ctx->Yr, N)) || (rc = A(&ctx->Yv, N)) || (rc = A(&ctx->Yt, 1)) || (rc = A(&ctx->cpr, CP * N)) ||
         (rc = A(&ctx->cpv, CP * N)) || (rc = A(&ctx->cpt, CP)) || (rc = A(&ctx->sgr, SG * N)) ||
@@ -1593,7 +1757,7 @@ int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const do
 
 int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
                          const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
-                         const double *gx, const double *gv, double gt, double *gx0, double *gv0) {
+                         const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm) {
     if (!ctx) return MSTAR_E_INVAL;
     ctx->err.clear();
     if (checkpoint_every < 1 || !gx || !gv || !gx0 || !gv0 || !std::isfinite(gt))
@@ -1621,6 +1785,7 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     launch_adj_pack(s, (int)n, (const double *)gxd, d.Lr, gt, d.Lt);
     launch_adj_pack(s, (int)n, (const double *)gvd, d.Lv, 0.0, nullptr);
     launch_adj_zero(s, d.LB);
+    launch_adj_zero_n(s, (int)n, d.Lm);
     // reverse pass, one checkpoint segment at a time
     for (int64_t seg = ncp - 1; seg >= 0 && n_steps > 0; --seg) {
         const int64_t j0 = seg * C, j1 = std::min(n_steps, j0 + C);
@@ -1638,12 +1803,46 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             launch_adj_combine_rev(d, s);
         }
     }
-    launch_adj_finish(d, s, ctx->cpr, ctx->cpv, ctx->a_io[2], ctx->a_io[3]);
+    launch_adj_finish(d, s, ctx->cpr, ctx->cpv, ctx->a_io[2], ctx->a_io[3], gm ? ctx->a_gm : nullptr);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, gx0, ctx->a_io[2], sizeof(double) * 3 * n))) return rc;
     if ((rc = out_copy(ctx, flags, gv0, ctx->a_io[3], sizeof(double) * 3 * n))) return rc;
+    if (gm && (rc = out_copy(ctx, flags, gm, ctx->a_gm, sizeof(double) * n))) return rc;
     HIPCK(hipStreamSynchronize(s));
     return MSTAR_OK;
+}
+
+int mstar_integrate_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
+                            const double *v0, double t0, double t_end, int64_t n_steps, int32_t checkpoint_every,
+                            const double *gxT, const double *gvT, double gtT, double *gx0, double *gv0, double *gm,
+                            mstar_stats *stats) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    if (!params || n < 2 || n > kAdjMaxN || !m || !x0 || !v0 || n_steps < 1 || checkpoint_every < 1 || !gxT ||
+        !gvT || !gx0 || !gv0 || !std::isfinite(gtT))
+        return fail(ctx, n > kAdjMaxN ? MSTAR_E_UNSUPPORTED : MSTAR_E_INVAL, "integrate_adjoint: bad arguments");
+    if (ttl_on(params)) return fail(ctx, MSTAR_E_UNSUPPORTED, "integrate_adjoint: beta != 0 (TTL) is not implemented");
+    (void)hipSetDevice(ctx->device);
+    // forward: the integrator, recording the accepted steps, on copies of x0, v0
+    const size_t b3 = sizeof(double) * 3 * (size_t)n;
+    std::vector<double> hx(3 * (size_t)n), hv(3 * (size_t)n), hm((size_t)n);
+    const hipMemcpyKind k = is_dev(params->flags) ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    HIPCK(hipMemcpy(hx.data(), x0, b3, k));
+    HIPCK(hipMemcpy(hv.data(), v0, b3, k));
+    HIPCK(hipMemcpy(hm.data(), m, sizeof(double) * n, k));
+    mstar_params ph = *params;
+    ph.flags &= ~MSTAR_DEVICE_PTRS;
+    std::vector<double> H((size_t)n_steps);
+    int64_t nrec = 0;
+    mstar_stats st{};
+    st.struct_size = sizeof(mstar_stats);
+    int rc = integrate_impl(ctx, &ph, n, hm.data(), hx.data(), hv.data(), t0, t_end, &st, n_steps, H.data(), &nrec);
+    if (stats) *stats = st;
+    if (rc < 0) return rc;
+    // reverse: the adjoint of the recorded steps from the caller's x0, v0
+    const int rc2 = mstar_replay_adjoint(ctx, params, n, m, x0, v0, t0, nrec, H.data(), checkpoint_every, gxT, gvT,
+                                         gtT, gx0, gv0, gm);
+    return rc2 ? rc2 : rc;
 }
 
 int mstar_force_hvp(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x,

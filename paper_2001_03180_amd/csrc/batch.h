@@ -31,6 +31,8 @@ struct BatchArgs {
     double *x, *v;            // [N_total][3], read at t0 and overwritten with the end state
     const double *t0, *t_end; // [n_sys]
     BatchStat *stat;          // [n_sys]
+    double *hrec;             // [n_sys][hrec_cap] fictitious step of every accepted step (nullptr: none)
+    int64_t hrec_cap;
     BatchParams p;
 };
 

@@ -24,6 +24,8 @@ constexpr int kForceWaves = 4;     // waves per force workgroup (same i-block, s
 constexpr int kForceIPL = 1;       // i-bodies per lane in the force kernel (2 and 4 measured slower)
 constexpr int kTreeWG = 1024;      // single-workgroup tree kernels
 constexpr int kMaxNd = 4;          // largest closeness N_d of eq. LCA on the GPU path
+constexpr int kMutIPL = 4;         // i-bodies per lane of the mutual force kernel (one row = 64 kMutIPL bodies)
+constexpr bool kMutJReg = true;    // mutual kernel: j-side sums rotate through registers (else LDS atomic adds)
 
 // Deterministic sum of a block of values held one per thread (fixed tree).
 template <int NT>
@@ -89,6 +91,8 @@ struct Ctl {               // device control block, read back once per GBS step
     int32_t topo;          // the last rebuild changed the tree
     int32_t tree_bad;      // the last rebuild's Boruvka rounds did not finish: the old tree is kept
     int32_t mst_rounds;    // Boruvka rounds of the last finished build
+    int32_t kacc;          // order k whose extrapolation was accepted (0: rejected)
+    int32_t pad_;
 };
 
 struct SysScal {           // start-of-step scalars of the integrated state
@@ -169,18 +173,104 @@ struct Dev {
     int32_t *deg, *off, *fill, *adj, *arcpos, *nxtA, *nxtB, *rkA, *rkB;
     int32_t *cnt;
     double *scr;                // misc scalar scratch
+    // mutual (i < j) force kernel output (allocated when N suits that kernel)
+    d4 *mip;                    // [slot][rows][maxw][64 kMutIPL] i-side partials, one per wave and row
+    d4 *mjp;                    // [slot][2][rows][n] j-side partials, one per row (two if a wave split the block)
+    d4 *mcp;                    // [slot][n] close-pair corrections
+    double *mup;                // [slot][rows * maxw + nib] potential partials
+    size_t mip_s, mjp_s, mup_s; // per-slot strides
 };
+
+// ------------------------------------------------- force output layout
+// Where one launch of the force kernel leaves the force on each body.
+//  mut = 0 (pairwise kernel): nparts partial rows part[slot][k][n].
+//  mut = 1 (mutual kernel, each unordered pair once): the bodies form rows of
+//  64 ipl (the i-bodies one wave holds); row P pairs with the 64-body j-blocks
+//  J >= ipl P.  The pair work of all nact evaluations of the launch is one
+//  sequence of steps (eval, row, j-block, step), cut into equal ranges of L
+//  steps, one per wave.  A wave leaves one i-side partial per row it touches
+//  and one j-side partial per j-block; a j-block cut between two waves leaves
+//  two (pieces 0 and 1).  Every partial is written exactly once per launch.
+struct FLay {
+    int mut;
+    int nparts;                 // mut = 0
+    int nb, npr, ipl, maxw;     // mut = 1: 64-blocks, rows, i-bodies per lane, i-side partials per row
+    int ncorr;                  // mut = 1: 1 if the close-pair correction partial exists (N_d > 0)
+    int pad;
+    long long Ec, L;            // mut = 1: steps per evaluation, steps per wave
+};
+
+// Steps of the rows before row P: a row P has one half j-block (32 steps: the
+// diagonal block of its first i-block) and 64 steps for every later j-block.
+__host__ __device__ inline long long mut_rs(const FLay &f, long long P) {
+    return 32 * P + 64 * P * (long long)(f.nb - 1) - 32LL * f.ipl * P * (P - 1);
+}
+__host__ __device__ inline int mut_cost(const FLay &f, int P, int J) { return J == f.ipl * P ? 32 : 64; }
+__host__ __device__ inline long long mut_js(const FLay &f, int P, int J) {
+    return J == f.ipl * P ? 0 : 32 + 64LL * (J - f.ipl * P - 1);
+}
+
+// Sum of the force partials of body v (eval ea of the launch, division slot
+// `slot`): the items with index = t (mod nt), in a fixed order.
+__device__ inline void force_sum(const Dev &d, const d4 *part, const FLay &f, int slot, int ea, int v, int t, int nt,
+                                 double &x, double &y, double &z) {
+    const int n = d.n;
+    if (!f.mut) {
+        for (int k = t; k < f.nparts; k += nt) {
+            const d4 e = part[(size_t)k * n + v];
+            x = x + e.x; y = y + e.y; z = z + e.z;
+        }
+        return;
+    }
+    const int rowb = 64 * f.ipl;
+    const int P = v / rowb;
+    const long long base = (long long)ea * f.Ec;
+    const long long wf = (base + mut_rs(f, P)) / f.L, wl = (base + mut_rs(f, P + 1) - 1) / f.L;
+    const int nw = (int)(wl - wf + 1);
+    const d4 *ip = d.mip + (size_t)slot * d.mip_s + ((size_t)P * f.maxw) * rowb + (v - rowb * P);
+    for (int k = t; k < nw; k += nt) {
+        const d4 e = ip[(size_t)k * rowb];
+        x = x + e.x; y = y + e.y; z = z + e.z;
+    }
+    const int J = v / 64;
+    const d4 *jp = d.mjp + (size_t)slot * d.mjp_s + v;
+    for (int Q = t; Q <= P; Q += nt) {
+        const d4 e = jp[(size_t)Q * n];
+        x = x + e.x; y = y + e.y; z = z + e.z;
+        const long long st = base + mut_rs(f, Q) + mut_js(f, Q, J);
+        if (st / f.L != (st + mut_cost(f, Q, J) - 1) / f.L) {
+            const d4 e2 = jp[((size_t)f.npr + Q) * n];
+            x = x + e2.x; y = y + e2.y; z = z + e2.z;
+        }
+    }
+    if (f.ncorr && t == 0) {
+        const d4 e = d.mcp[(size_t)slot * n + v];
+        x = x + e.x; y = y + e.y; z = z + e.z;
+    }
+}
+
+// The potential partials of one launch for division slot `slot`:
+// U = G/2 * sum of the *cnt values at the returned address.
+__device__ inline const double *force_upart(const Dev &d, const FLay &f, int slot, int *cnt) {
+    if (!f.mut) {
+        *cnt = d.nfb * f.nparts;
+        return d.Upart + (size_t)slot * d.nib * d.nsplit_max;
+    }
+    *cnt = f.npr * f.maxw + (f.ncorr ? f.nb : 0);
+    return d.mup + (size_t)slot * d.mup_s;
+}
 
 // ---------------------------------------------------------------- launches
 // kernels_force.hip
-void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, int nsplit, bool om);
-// Partial sums per i-block written by launch_force: the nsplit j-splits plus
-// one close-pair correction block when N_d > 0.  Kick and start reduction
-// take this count.
+void launch_force(const Dev &d, hipStream_t s, const SlotList &sl, int nd, const FLay &f, bool om);
+// Partial sums per i-block written by the pairwise kernel: the nsplit
+// j-splits plus one close-pair correction block when N_d > 0.
 inline int force_parts(int nsplit, int nd) { return nsplit + (nd > 0 ? 1 : 0); }
-// Resident force workgroups per CU (occupancy of the force kernel).
+// Resident force workgroups per CU (occupancy of the pairwise force kernel).
 int force_blocks_per_cu(int nd);
-void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, int nsplit, d4 *acc_out,
+// Resident 64-thread workgroups per CU of the mutual force kernel.
+int force_mut_blocks_per_cu();
+void launch_reduce_start(const Dev &d, hipStream_t s, int slot, double G, const FLay &f, d4 *acc_out,
                          double *U_out, bool om, bool with_w);
 // kernels_step.hip
 void launch_div_init(const Dev &d, hipStream_t s, int ndiv, int base_slot);
@@ -190,14 +280,19 @@ struct Ttl {
     double alpha, beta, gamma;
 };
 void launch_drift(const Dev &d, hipStream_t s, const SlotList &sl, Ttl tr, bool ex);
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr, bool ex);
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, const FLay &f, double G, Ttl tr, bool ex);
 void launch_ext(const Dev &d, hipStream_t s, const SlotList &sl, int at_start);
 void launch_ext_minv(const Dev &d, hipStream_t s);
 void launch_set_h(const Dev &d, hipStream_t s, double H, double t_end, int clip, Ttl tr, int from_ctl);
 void launch_put_hnext(const Dev &d, hipStream_t s, double H);
 void prepare_tree_launches();   // one-time runtime settings of the tree kernels (before any capture)
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot, bool ex);
-void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max);
+// rule 0: error at k_fix and the outputs T_{kf,kf}; rule 1: errors of every
+// order k = 2..kf only (the outputs follow from launch_extrap_pick once the
+// control has chosen the order).
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base_slot, bool ex, int rule = 0);
+void launch_extrap_pick(const Dev &d, hipStream_t s, int kf, bool ex);
+void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max,
+                    int rule = 0);
 void launch_commit(const Dev &d, hipStream_t s, int from_extrap, int slot);
 void launch_state_from_cartesian(const Dev &d, hipStream_t s, const double *x, const double *v);
 void launch_com_frame(const Dev &d, hipStream_t s, int with_T);

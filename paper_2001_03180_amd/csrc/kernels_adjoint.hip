@@ -100,7 +100,7 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
 }
 
 struct LamA {
-    double x, y, z;
+    double x, y, z, w;
 };
 
 // LDS of one division workgroup.  Between kicks, pos / la hold the j-bodies
@@ -157,10 +157,12 @@ __device__ __forceinline__ void accel_part(const AdjShared &S, int jb, int je, i
 
 // Partial acceleration (without G) and transposed-Jacobian product
 // sum_j M(d_ij) (m_i w_j - m_j w_i) (without G) of body i over j in [jb, je).
+// Also phi_i = sum_j m_j / r_ij and the mass term sum_j (w_j . d_ij) / r_ij^3
+// (d a_j / d m_i applied to w_j, without G and sign).
 __device__ __forceinline__ void accel_hvp_part(const AdjShared &S, int jb, int je, int i, const d4 &r, double mi,
                                                const LamA &wi, double &ax, double &ay, double &az, double &hx,
-                                               double &hy, double &hz) {
-    ax = ay = az = hx = hy = hz = 0.0;
+                                               double &hy, double &hz, double &ph, double &gm) {
+    ax = ay = az = hx = hy = hz = ph = gm = 0.0;
     for (int j = jb; j < je; ++j) {
         const d4 pj = S.pos[j];
         const LamA wj = S.la[j];
@@ -176,6 +178,8 @@ __device__ __forceinline__ void accel_hvp_part(const AdjShared &S, int jb, int j
         ax = fma(s, dx, ax);
         ay = fma(s, dy, ay);
         az = fma(s, dz, az);
+        ph = fma(mj, y, ph);
+        gm = fma(fma(dz, wj.z, fma(dy, wj.y, dx * wj.x)), y3, gm);   // d = 0 for the self pair
         const double m_i = self ? 0.0 : mi;   // the self pair contributes nothing
         const double qx = m_i * wj.x - mj * wi.x, qy = m_i * wj.y - mj * wi.y, qz = m_i * wj.z - mj * wi.z;
         const double dq = fma(dz, qz, fma(dy, qy, dx * qx));
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
         lv = d4{ck * b.x, ck * b.y, ck * b.z, 0.0};
     }
     const double lt = ck * *d.Lt;
-    double lB = 0.0;
+    double lB = 0.0, lm = 0.0;
     int rb = 0;
     for (int s = nsub; s >= 0; --s) {
         // reverse drift s: r' = r + dt v, t' = t + dt, dt = ds / (alpha (T(v) + B) + gamma)
@@ -364,6 +368,9 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
             const double lT = ldt * (-(dt / g) * al);
             lB = lB + lT;
             if (L.live) {
+                // T = sum m_i |v_i - v_bar|^2 / 2: dT/dm_i = |v_i - v_bar|^2 / 2 (sum m (v - v_bar) = 0)
+                const double cx = v.x - bx, cy = v.y - by, cz = v.z - bz;
+                lm = lm + lT * (0.5 * ((cx * cx + cy * cy) + cz * cz));
                 lv = d4{lv.x + dt * lr.x + lT * (mi * (v.x - bx)), lv.y + dt * lr.y + lT * (mi * (v.y - by)),
                         lv.z + dt * lr.z + lT * (mi * (v.z - bz)), 0.0};
             }
@@ -374,22 +381,22 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
             const double *o = d.sc + (size_t)(ob + 2 * (s - 1) + 1) * kAdjOpScal;
             const double dt = o[0], g = o[1];
             const d4 r = L.live ? d.rst[(size_t)(kb + s - 1) * n + L.b] : d4{0.0, 0.0, 0.0, 0.0};
-            const LamA wi{dt * lv.x, dt * lv.y, dt * lv.z};
+            const LamA wi{dt * lv.x, dt * lv.y, dt * lv.z, 0.0};
             if (L.lead) {
                 S.pos[L.b] = d4{r.x, r.y, r.z, mi};
                 S.la[L.b] = wi;
             }
             __syncthreads();
-            double ax = 0.0, ay = 0.0, az = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
-            if (L.live) accel_hvp_part(S, L.jb, L.je, L.b, r, mi, wi, ax, ay, az, hx, hy, hz);
+            double ax = 0.0, ay = 0.0, az = 0.0, hx = 0.0, hy = 0.0, hz = 0.0, ph = 0.0, gq = 0.0;
+            if (L.live) accel_hvp_part(S, L.jb, L.je, L.b, r, mi, wi, ax, ay, az, hx, hy, hz, ph, gq);
             // lambda_dt = sum_i lambda_v,i . a_i, from the per-thread partials
             double s1[1] = {L.live ? (lv.x * (d.G * ax) + lv.y * (d.G * ay)) + lv.z * (d.G * az) : 0.0};
             wave_partials<1>(s1, S.red, rb);
             if (L.T > 1) {
                 __syncthreads();   // every j-loop has finished reading pos / la
                 if (L.live) {
-                    S.pos[L.q * n + L.b] = d4{ax, ay, az, 0.0};
-                    S.la[L.q * n + L.b] = LamA{hx, hy, hz};
+                    S.pos[L.q * n + L.b] = d4{ax, ay, az, ph};
+                    S.la[L.q * n + L.b] = LamA{hx, hy, hz, gq};
                 }
             }
             __syncthreads();
@@ -400,23 +407,26 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
                 for (int q = 1; q < L.T; ++q) {
                     const d4 u = S.pos[q * n + L.b];
                     const LamA w = S.la[q * n + L.b];
-                    a = d4{a.x + u.x, a.y + u.y, a.z + u.z, 0.0};
-                    hh = LamA{hh.x + w.x, hh.y + w.y, hh.z + w.z};
+                    a = d4{a.x + u.x, a.y + u.y, a.z + u.z, a.w + u.w};
+                    hh = LamA{hh.x + w.x, hh.y + w.y, hh.z + w.z, hh.w + w.w};
                 }
-                ax = a.x; ay = a.y; az = a.z;
-                hx = hh.x; hy = hh.y; hz = hh.z;
+                ax = a.x; ay = a.y; az = a.z; ph = a.w;
+                hx = hh.x; hy = hh.y; hz = hh.z; gq = hh.w;
             }
             ax = d.G * ax; ay = d.G * ay; az = d.G * az;
             hx = d.G * hx; hy = d.G * hy; hz = d.G * hz;
             const double lU = s1[0] * (-(dt / g) * al);
             if (L.live) {
                 lr = d4{lr.x + lU * (mi * ax) + hx, lr.y + lU * (mi * ay) + hy, lr.z + lU * (mi * az) + hz, 0.0};
+                // dU/dm_i = G phi_i; a_j depends on m_i through G m_i d_ji / r^3
+                lm = lm + (lU * (d.G * ph) - d.G * gq);
             }
         }
     }
     if (L.lead) {
         d.Sr[(size_t)k * n + L.b] = lr;
         d.Sv[(size_t)k * n + L.b] = lv;
+        d.Sm[(size_t)k * n + L.b] = lm;
     }
     if (threadIdx.x == 0) {
         d.St[k] = lt;
@@ -441,6 +451,9 @@ __global__ void k_adj_combine_rev(AdjDev d) {
         }
         d.Lr[i] = d4{rx, ry, rz, 0.0};
         d.Lv[i] = d4{vx, vy, vz, 0.0};
+        double mm = d.Lm[i];
+        for (int k = 0; k < d.kf; ++k) mm = mm + d.Sm[(size_t)k * n + i];
+        d.Lm[i] = mm;
     }
     if (i == 0) {
         double tt = keep * *d.Lt, bb = 0.0;
@@ -456,7 +469,7 @@ __global__ void k_adj_combine_rev(AdjDev d) {
 // Gradient with respect to the initial state: the chain through
 // B = U(r0) - T(v0) added to the propagated cotangent.  One workgroup.
 __global__ __launch_bounds__(kAdjMaxN) void k_adj_finish(AdjDev d, const d4 *Yr, const d4 *Yv, double *gx,
-                                                         double *gv) {
+                                                         double *gv, double *gm) {
     __shared__ AdjShared S;
     const Lay L = layout(d);
     const int n = d.n;
@@ -482,6 +495,10 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_finish(AdjDev d, const d4 *Yr,
         gv[3 * L.b] = b.x - lB * (mi * (v.x - bx));
         gv[3 * L.b + 1] = b.y - lB * (mi * (v.y - by));
         gv[3 * L.b + 2] = b.z - lB * (mi * (v.z - bz));
+        if (gm) {   // B = U(r0) - T(v0): dB/dm_i = G phi_i - |v_i - v_bar|^2 / 2
+            const double cx = v.x - bx, cy = v.y - by, cz = v.z - bz;
+            gm[L.b] = d.Lm[L.b] + lB * (d.G * ph - 0.5 * ((cx * cx + cy * cy) + cz * cz));
+        }
     }
 }
 
@@ -528,6 +545,10 @@ __global__ void k_adj_unpack(int n, const d4 *a, double *x) {
 __global__ void k_adj_zero(double *p) {
     if (threadIdx.x == 0) *p = 0.0;
 }
+__global__ void k_adj_zero_n(int n, double *p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
 __global__ void k_adj_copy(int n, const d4 *a, const d4 *b, const double *t, d4 *oa, d4 *ob, double *ot) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -557,9 +578,11 @@ void launch_adj_rev(const AdjDev &d, hipStream_t s) { k_adj_rev<<<d.kf, threads_
 void launch_adj_combine_rev(const AdjDev &d, hipStream_t s) {
     k_adj_combine_rev<<<(d.n + 255) / 256, 256, 0, s>>>(d);
 }
-void launch_adj_finish(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, double *gx, double *gv) {
-    k_adj_finish<<<1, threads_for(d), 0, s>>>(d, Yr, Yv, gx, gv);
+void launch_adj_finish(const AdjDev &d, hipStream_t s, const d4 *Yr, const d4 *Yv, double *gx, double *gv,
+                       double *gm) {
+    k_adj_finish<<<1, threads_for(d), 0, s>>>(d, Yr, Yv, gx, gv, gm);
 }
+void launch_adj_zero_n(hipStream_t s, int n, double *p) { k_adj_zero_n<<<(n + 255) / 256, 256, 0, s>>>(n, p); }
 void launch_force_hvp(hipStream_t s, int n, double G, const double *m, const double *x, const double *w,
                       double *out) {
     k_force_hvp<<<(n + 127) / 128, 128, 0, s>>>(n, G, m, x, w, out);

@@ -954,6 +954,7 @@ __device__ __forceinline__ void run_system(SysLDS<KF, L, G> &S, const BatchArgs 
             } else {
                 S.acc += 1;
                 S.h_last = S.H;
+                if (A.hrec && S.acc <= A.hrec_cap) A.hrec[(size_t)sys * A.hrec_cap + (S.acc - 1)] = S.H;
                 S.halvings = 0;
                 S.since_rebuild += 1;
                 S.fresh = 1;

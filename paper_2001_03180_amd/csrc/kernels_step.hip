@@ -199,7 +199,7 @@ void launch_ext_minv(const Dev &d, hipStream_t s) { k_ext_minv<<<1, kTreeWG, 0, 
 // and per-workgroup partials of sum m_i f_i . (v_i_old + v_i_new)/2 give the
 // work on B, which the next drift scales by dt.
 template <bool OM, bool EX>
-__global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, double G, Ttl tr) {
+__global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, FLay fl, double G, Ttl tr) {
     __shared__ double sh[8][kWG / 64];
     __shared__ d4 ra[kWG], rc[OM ? kWG : 1];
     const int ai = blockIdx.y;
@@ -215,10 +215,9 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     const d4 *pp = d.part + prow;
     d4 sa{0.0, 0.0, 0.0, 0.0}, so = sa;
     if (live) {
-        for (int sp = part; sp < nsplit; sp += 4) {
-            const d4 t = pp[(size_t)sp * n + v];
-            sa.x = sa.x + t.x; sa.y = sa.y + t.y; sa.z = sa.z + t.z;
-            if constexpr (OM) {
+        force_sum(d, pp, fl, slot, ai, v, part, 4, sa.x, sa.y, sa.z);
+        if constexpr (OM) {   // the TTL kernel is always the pairwise one
+            for (int sp = part; sp < fl.nparts; sp += 4) {
                 const d4 t3 = d.opart[prow + (size_t)sp * n + v];
                 so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
             }
@@ -235,8 +234,8 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     }
     ra[threadIdx.x] = sa;
     if constexpr (OM) rc[threadIdx.x] = so;
-    const double *up = d.Upart + (size_t)slot * d.nib * d.nsplit_max;
-    const int cnt = d.nfb * nsplit;
+    int cnt = 0;
+    const double *up = force_upart(d, fl, slot, &cnt);
     double u = 0.0;
     for (int k = threadIdx.x; k < cnt; k += kWG) u = u + up[k];
     const double U = 0.5 * G * block_sum1<kWG>(u, sh[0]);   // its barrier also publishes ra, rc
@@ -320,11 +319,11 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, int nsplit, do
     }
 }
 
-void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, int nsplit, double G, Ttl tr, bool ex) {
+void launch_kick(const Dev &d, hipStream_t s, const SlotList &sl, const FLay &f, double G, Ttl tr, bool ex) {
     dim3 grid((d.n + kWG / 4 - 1) / (kWG / 4), sl.nact);
-    if (ex) k_kick<false, true><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
-    else if (tr.beta != 0.0) k_kick<true, false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
-    else k_kick<false, false><<<grid, kWG, 0, s>>>(d, sl, nsplit, G, tr);
+    if (ex) k_kick<false, true><<<grid, kWG, 0, s>>>(d, sl, f, G, tr);
+    else if (tr.beta != 0.0) k_kick<true, false><<<grid, kWG, 0, s>>>(d, sl, f, G, tr);
+    else k_kick<false, false><<<grid, kWG, 0, s>>>(d, sl, f, G, tr);
 }
 
 // Step length of this attempt with the end-time clip of Sec. 2.4: the
@@ -440,6 +439,159 @@ __device__ __forceinline__ void extrap3(const d4 *arr, int n, int v, d4 &out, do
     ez = z[KF - 1] - z[KF - 2];
 }
 
+// The outputs T_{ko,ko} (ko = kout, 1-based) of every extrapolated variable
+// except the scalars' error groups: edge vectors, edge velocities and the
+// carried positions and velocities, and the scalar increments.
+template <int KF>
+__device__ __forceinline__ void pick3(const d4 *arr, int n, int v, int ko, d4 &out) {
+    double x[KF], y[KF], z[KF];
+    load_col<KF>(arr, n, v, x, y, z);
+    neville<KF>(x); neville<KF>(y); neville<KF>(z);
+    out = d4{x[0], y[0], z[0], 0.0};
+#pragma unroll
+    for (int k = 1; k < KF; ++k)
+        if (k == ko - 1) out = d4{x[k], y[k], z[k], 0.0};
+}
+
+// Second pass of the earliest-k acceptance (accept_rule 1): the outputs at
+// the order k_acc the control chose (T_{k_acc,k_acc} of every variable).
+template <int KF>
+__global__ __launch_bounds__(kWG) void k_extrap_pick(Dev d, int with_ext) {
+    const int n = d.n;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const int ko = d.ctl->kacc > 0 ? d.ctl->kacc : KF;
+    if (v < n) {
+        d4 o;
+        pick3<KF>(d.dX, n, v, ko, o); d.dX1[v] = o;
+        pick3<KF>(d.dV, n, v, ko, o); d.dV1[v] = o;
+        pick3<KF>(d.dP, n, v, ko, o); d.dP1[v] = o;
+        pick3<KF>(d.dVt, n, v, ko, o); d.dVt1[v] = o;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double pt[KF], rx[KF], ry[KF], rz[KF], pw[KF], pb[KF], ux[KF], uy[KF], uz[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const DivScal q = d.dscal[k];
+            pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2]; pw[k] = q.dwn;
+            pb[k] = q.dBn; ux[k] = q.dvcm[0]; uy[k] = q.dvcm[1]; uz[k] = q.dvcm[2];
+        }
+        neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz); neville<KF>(pw);
+        if (with_ext) { neville<KF>(pb); neville<KF>(ux); neville<KF>(uy); neville<KF>(uz); }
+        DivScal out{};
+#pragma unroll
+        for (int k = 0; k < KF; ++k)
+            if (k == ko - 1) {
+                out.tau = pt[k];
+                out.dw = pw[k];
+                out.drcm[0] = rx[k]; out.drcm[1] = ry[k]; out.drcm[2] = rz[k];
+                if (with_ext) {
+                    out.dB = pb[k];
+                    out.dvcm[0] = ux[k]; out.dvcm[1] = uy[k]; out.dvcm[2] = uz[k];
+                }
+            }
+        *d.dscal1 = out;
+    }
+}
+
+// Error measure of eq. gbs-criterion for every order k = 2..KF (the
+// earliest-k acceptance, accept_rule 1): per workgroup, the maximum over its
+// bodies' edge groups of |T_kk - T_{k-1,k-1}| / |S0 + (H/n_k) S'(s0)| into
+// epspart[(k-1) * parts + block]; block 0 adds the scalar groups.  Outputs
+// are written by k_extrap_pick once the order is chosen.
+template <int KF>
+__global__ __launch_bounds__(kWG) void k_extrap_allk(Dev d, Ttl tr, int with_ext) {
+    __shared__ double sh[kWG];
+    const int n = d.n;
+    const int v = blockIdx.x * kWG + threadIdx.x;
+    const int parts = d.nkwg + 1;
+    const Ctl &c = *d.ctl;
+    const double H = c.H;
+    const double gd = (tr.alpha * (c.T0 + d.sys->B) + tr.beta * d.sys->w) + tr.gamma;
+    const double gk = (tr.alpha * c.U0 + tr.beta * c.Om0) + tr.gamma;
+    double ek[KF];
+#pragma unroll
+    for (int k = 0; k < KF; ++k) ek[k] = 0.0;
+    if (v < n) {
+        const int p = d.parent[v];
+        if (p >= 0) {
+            double x[KF], y[KF], z[KF], a[KF], b[KF], e[KF];
+            load_col<KF>(d.dX, n, v, x, y, z);
+            load_col<KF>(d.dV, n, v, a, b, e);
+            neville<KF>(x); neville<KF>(y); neville<KF>(z);
+            neville<KF>(a); neville<KF>(b); neville<KF>(e);
+            const d4 X0 = d.X0[v], V0 = d.V0[v];
+            d4 av = d.a0[v], ap = d.a0[p];
+            if (with_ext) {
+                const d4 fv = d.fext[(size_t)kBaseSlot * n + v], fp = d.fext[(size_t)kBaseSlot * n + p];
+                av.x = av.x + fv.x; av.y = av.y + fv.y; av.z = av.z + fv.z;
+                ap.x = ap.x + fp.x; ap.y = ap.y + fp.y; ap.z = ap.z + fp.z;
+            }
+#pragma unroll
+            for (int k = 1; k < KF; ++k) {
+                const double hn = H / (double)(2 * (k + 1));
+                const double ex = group_err(x[k] - x[k - 1], y[k] - y[k - 1], z[k] - z[k - 1], X0.x + hn * (V0.x / gd),
+                                            X0.y + hn * (V0.y / gd), X0.z + hn * (V0.z / gd));
+                const double ev = group_err(a[k] - a[k - 1], b[k] - b[k - 1], e[k] - e[k - 1],
+                                            V0.x + hn * ((av.x - ap.x) / gk), V0.y + hn * ((av.y - ap.y) / gk),
+                                            V0.z + hn * ((av.z - ap.z) / gk));
+                ek[k] = fmax_nan(ex, ev);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 1; k < KF; ++k) {
+        sh[threadIdx.x] = ek[k];
+        __syncthreads();
+        for (int s = kWG / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) sh[threadIdx.x] = fmax_nan(sh[threadIdx.x], sh[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d.epspart[(size_t)(k - 1) * parts + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double pt[KF], rx[KF], ry[KF], rz[KF], pw[KF], pb[KF], ux[KF], uy[KF], uz[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const DivScal q = d.dscal[k];
+            pt[k] = q.tau; rx[k] = q.drcm[0]; ry[k] = q.drcm[1]; rz[k] = q.drcm[2]; pw[k] = q.dwn;
+            pb[k] = q.dBn; ux[k] = q.dvcm[0]; uy[k] = q.dvcm[1]; uz[k] = q.dvcm[2];
+        }
+        neville<KF>(pt); neville<KF>(rx); neville<KF>(ry); neville<KF>(rz); neville<KF>(pw);
+        double F[4] = {0.0, 0.0, 0.0, 0.0};
+        if (with_ext) {
+            neville<KF>(pb); neville<KF>(ux); neville<KF>(uy); neville<KF>(uz);
+            const d4 *fp = d.fpart + (size_t)kBaseSlot * d.nkwg4;
+            for (int k = 0; k < d.nkwg; ++k) {
+                const d4 t = fp[k];
+                F[0] = F[0] + t.x; F[1] = F[1] + t.y; F[2] = F[2] + t.z; F[3] = F[3] + t.w;
+            }
+        }
+        const SysScal &y = *d.sys;
+#pragma unroll
+        for (int k = 1; k < KF; ++k) {
+            const double hn = H / (double)(2 * (k + 1));
+            const double et = group_err(pt[k] - pt[k - 1], 0.0, 0.0, y.t + hn * (1.0 / gd), 0.0, 0.0);
+            const double er = group_err2(rx[k] - rx[k - 1], ry[k] - ry[k - 1], rz[k] - rz[k - 1],
+                                         y.rcm[0] + hn * (y.vcm[0] / gd), y.rcm[1] + hn * (y.vcm[1] / gd),
+                                         y.rcm[2] + hn * (y.vcm[2] / gd), y.rcm[0] + rx[k], y.rcm[1] + ry[k],
+                                         y.rcm[2] + rz[k]);
+            double es = fmax_nan(et, er);
+            if (tr.beta != 0.0)
+                es = fmax_nan(es, group_err(pw[k] - pw[k - 1], 0.0, 0.0, y.w + hn * (c.dw0 / gk), 0.0, 0.0));
+            if (with_ext) {
+                const double Minv = d.ext->Minv;
+                es = fmax_nan(es, group_err(pb[k] - pb[k - 1], 0.0, 0.0, y.B + hn * (-F[3] / gk), 0.0, 0.0));
+                es = fmax_nan(es, group_err2(ux[k] - ux[k - 1], uy[k] - uy[k - 1], uz[k] - uz[k - 1],
+                                             y.vcm[0] + hn * (F[0] * Minv / gk), y.vcm[1] + hn * (F[1] * Minv / gk),
+                                             y.vcm[2] + hn * (F[2] * Minv / gk), y.vcm[0] + ux[k], y.vcm[1] + uy[k],
+                                             y.vcm[2] + uz[k]));
+            }
+            d.epspart[(size_t)(k - 1) * parts + d.nkwg] = es;
+        }
+    }
+}
+
 template <int KF>
 __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base, int with_ext) {
     __shared__ double sh[kWG];
@@ -541,8 +693,18 @@ __global__ __launch_bounds__(kWG) void k_extrapolate(Dev d, Ttl tr, int base, in
     }
 }
 
-void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base, bool ex) {
+void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base, bool ex, int rule) {
     const int nb = (d.n + kWG - 1) / kWG;
+    if (rule == 1) {
+        switch (kf) {
+#define KFC(K) case K: k_extrap_allk<K><<<nb, kWG, 0, s>>>(d, tr, ex ? 1 : 0); break;
+            KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
+            KFC(15) KFC(16)
+#undef KFC
+            default: break;
+        }
+        return;
+    }
     switch (kf) {
 #define KFC(K) case K: k_extrapolate<K><<<nb, kWG, 0, s>>>(d, tr, base, ex ? 1 : 0); break;
         KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
@@ -552,16 +714,39 @@ void launch_extrapolate(const Dev &d, hipStream_t s, int kf, Ttl tr, int base, b
     }
 }
 
+void launch_extrap_pick(const Dev &d, hipStream_t s, int kf, bool ex) {
+    const int nb = (d.n + kWG - 1) / kWG;
+    switch (kf) {
+#define KFC(K) case K: k_extrap_pick<K><<<nb, kWG, 0, s>>>(d, ex ? 1 : 0); break;
+        KFC(2) KFC(3) KFC(4) KFC(5) KFC(6) KFC(7) KFC(8) KFC(9) KFC(10) KFC(11) KFC(12) KFC(13) KFC(14)
+        KFC(15) KFC(16)
+#undef KFC
+        default: break;
+    }
+}
+
 // Accept iff eps <= eta; next step per eq. hnext with the clamps, or H/2.
-__global__ void k_control(Dev d, int kf, int nparts, double eta, double a_gbs, double f_min, double f_max) {
+// rule 0: eps of order kf (Sec. 4.2); rule 1: the first order k = 2..kf
+// whose eps_k <= eta (eq. hnext then uses that k); k_acc records the order.
+__global__ void k_control(Dev d, int kf, int nparts, double eta, double a_gbs, double f_min, double f_max, int rule) {
     Ctl &c = *d.ctl;
     double eps = 0.0;
-    for (int k = 0; k < nparts; ++k) eps = fmax_nan(eps, d.epspart[k]);
+    int kacc = 0;
+    for (int k = rule == 1 ? 2 : kf; k <= kf; ++k) {
+        const double *ep = d.epspart + (rule == 1 ? (size_t)(k - 2) * nparts : 0);
+        eps = 0.0;
+        for (int q = 0; q < nparts; ++q) eps = fmax_nan(eps, ep[q]);
+        if (eps <= eta) {
+            kacc = k;
+            break;
+        }
+    }
     c.eps = eps;
-    c.accepted = (eps <= eta) ? 1 : 0;
+    c.kacc = kacc;
+    c.accepted = kacc > 0 ? 1 : 0;
     if (c.accepted) {
         const double e = eps > 1e-300 ? eps : 1e-300;
-        double f = a_gbs * pow(eta / e, 1.0 / (double)(2 * kf - 1));
+        double f = a_gbs * pow(eta / e, 1.0 / (double)(2 * kacc - 1));
         if (f < f_min) f = f_min;
         if (f > f_max) f = f_max;
         c.h_next = c.H * f;
@@ -570,9 +755,10 @@ __global__ void k_control(Dev d, int kf, int nparts, double eta, double a_gbs, d
     }
 }
 
-void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max) {
+void launch_control(const Dev &d, hipStream_t s, int kf, double eta, double a_gbs, double f_min, double f_max,
+                    int rule) {
     const int nb = (d.n + kWG - 1) / kWG;
-    k_control<<<1, 1, 0, s>>>(d, kf, nb + 1, eta, a_gbs, f_min, f_max);
+    k_control<<<1, 1, 0, s>>>(d, kf, nb + 1, eta, a_gbs, f_min, f_max, rule);
 }
 
 // Commit the extrapolated increments (if the step was accepted) or the end

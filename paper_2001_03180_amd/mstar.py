@@ -30,7 +30,7 @@ class Params(C.Structure):
         ("a_gbs", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double), ("q_first", C.c_double),
         ("t_tol", C.c_double), ("h_init", C.c_double), ("max_steps", C.c_int64), ("k_fix", C.c_int32),
         ("n_d", C.c_int32), ("max_halvings", C.c_int32), ("max_time_iter", C.c_int32),
-        ("rebuild_every", C.c_int32), ("reserved", C.c_int32),
+        ("rebuild_every", C.c_int32), ("accept_rule", C.c_int32),
     ]
 
 
@@ -97,8 +97,13 @@ EXPORTS = {
                                        C.POINTER(C.c_double)]),
     "mstar_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
+    "mstar_profile_read_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                            C.POINTER(C.c_double)]),
     "mstar_integrate_batch": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_integrate_batch_record": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_int64, C.c_void_p]),
     "mstar_batch_get_config": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BatchConfig)]),
     "mstar_batch_set_config": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(BatchConfig)]),
     "mstar_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int32, C.c_void_p, C.c_void_p,
@@ -110,7 +115,11 @@ EXPORTS = {
                                C.c_double, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
     "mstar_replay_adjoint": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
-                                       C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+                                       C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mstar_integrate_adjoint": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_void_p,
+                                          C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(Stats)]),
     "mstar_force_hvp": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
 }
@@ -361,6 +370,20 @@ class Context:
             C.c_void_p(st.ctypes.data)))
         return x, v, st
 
+    def integrate_batch_record(self, offsets, m, x, v, t_end, rec_cap, t0=None, p: Params | None = None):
+        """integrate_batch that also records every system's accepted fictitious
+        steps: (x, v, stats, H) with H[s, :stats['steps_accepted'][s]] valid."""
+        p = p or params()
+        off, n_sys, te, t0a, x, v, a = self._batch_args(offsets, m, x, v, t_end, t0, True)
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
+        st = np.zeros(max(n_sys, 0), dtype=BATCH_STATS_DTYPE)
+        H = np.full((max(n_sys, 0), int(rec_cap)), np.nan)
+        self._check(lib().mstar_integrate_batch_record(
+            self._h, C.byref(p), n_sys, C.c_void_p(off.ctypes.data), a[0].ptr, a[1].ptr, a[2].ptr,
+            None if t0a is None else C.c_void_p(t0a.ctypes.data), C.c_void_p(te.ctypes.data),
+            C.c_void_p(st.ctypes.data), int(rec_cap), C.c_void_p(H.ctypes.data)))
+        return x, v, st, H
+
     def batch_config(self, k_fix=8):
         c = BatchConfig()
         self._check(lib().mstar_batch_get_config(self._h, int(k_fix), C.byref(c)))
@@ -421,26 +444,55 @@ class Context:
                                        C.c_void_p(H.ctypes.data), C.byref(t)))
         return x, v, t.value
 
-    def replay_adjoint(self, m, x0, v0, t0, H, gx, gv, gt=0.0, checkpoint_every=50, p: Params | None = None):
+    def _grad_outputs(self, p, a, n, with_mass):
+        if p.flags & DEVICE_PTRS:
+            import torch
+            dev = a[1].obj.device
+            gx0 = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            gv0 = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            gm = torch.empty((n,), dtype=torch.float64, device=dev) if with_mass else None
+        else:
+            gx0, gv0 = np.empty((n, 3)), np.empty((n, 3))
+            gm = np.empty(n) if with_mass else None
+        o = [_Arg(gx0, np.float64, writable=True), _Arg(gv0, np.float64, writable=True)]
+        om = _Arg(gm, np.float64, writable=True) if with_mass else None
+        return gx0, gv0, gm, o, om
+
+    def replay_adjoint(self, m, x0, v0, t0, H, gx, gv, gt=0.0, checkpoint_every=50, p: Params | None = None,
+                       with_mass=False):
         """Gradient of <gx, x> + <gv, v> + gt t (end state of the replay) with
-        respect to x0, v0: (gx0, gv0)."""
+        respect to x0, v0: (gx0, gv0), and the masses (gm) with with_mass."""
         p = p or params()
         n = len(m)
         H = np.ascontiguousarray(H, dtype=np.float64)
         a = [_Arg(m, np.float64, (n,)), _Arg(x0, np.float64, (n, 3)), _Arg(v0, np.float64, (n, 3)),
              _Arg(gx, np.float64, (n, 3)), _Arg(gv, np.float64, (n, 3))]
         p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
-        if p.flags:
-            import torch
-            gx0 = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
-            gv0 = torch.empty((n, 3), dtype=torch.float64, device=a[1].obj.device)
-        else:
-            gx0, gv0 = np.empty((n, 3)), np.empty((n, 3))
-        o = [_Arg(gx0, np.float64, writable=True), _Arg(gv0, np.float64, writable=True)]
+        gx0, gv0, gm, o, om = self._grad_outputs(p, a, n, with_mass)
         self._check(lib().mstar_replay_adjoint(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0),
                                                len(H), C.c_void_p(H.ctypes.data), int(checkpoint_every),
-                                               a[3].ptr, a[4].ptr, float(gt), o[0].ptr, o[1].ptr))
-        return gx0, gv0
+                                               a[3].ptr, a[4].ptr, float(gt), o[0].ptr, o[1].ptr,
+                                               om.ptr if om else None))
+        return (gx0, gv0, gm) if with_mass else (gx0, gv0)
+
+    def integrate_adjoint(self, m, x0, v0, t0, t_end, n_steps, gxT, gvT, gtT=0.0, checkpoint_every=50,
+                          p: Params | None = None, with_mass=True):
+        """Integrate n_steps accepted steps (or to t_end) and return the gradient
+        of <gxT, x> + <gvT, v> + gtT t at the end with respect to x0, v0 and
+        the masses: (gx0, gv0, gm, stats) (gm None without with_mass)."""
+        p = p or params()
+        n = len(m)
+        a = [_Arg(m, np.float64, (n,)), _Arg(x0, np.float64, (n, 3)), _Arg(v0, np.float64, (n, 3)),
+             _Arg(gxT, np.float64, (n, 3)), _Arg(gvT, np.float64, (n, 3))]
+        p.flags = (p.flags & ~DEVICE_PTRS) | _mode(*a)
+        gx0, gv0, gm, o, om = self._grad_outputs(p, a, n, with_mass)
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().mstar_integrate_adjoint(self._h, C.byref(p), n, a[0].ptr, a[1].ptr, a[2].ptr, float(t0),
+                                           float(t_end), int(n_steps), int(checkpoint_every), a[3].ptr, a[4].ptr,
+                                           float(gtT), o[0].ptr, o[1].ptr, om.ptr if om else None, C.byref(st))
+        self._check(rc, (OK, W_TIME_TOL))
+        return gx0, gv0, gm, st.as_dict()
 
     def force_hvp(self, m, x, w, p: Params | None = None):
         """out_i = G sum_j M(d_ij)(m_i w_j - m_j w_i): the transposed Jacobian of the accelerations times w."""
@@ -499,4 +551,10 @@ class Context:
         """(force launches, summed force-kernel ms, directed pairs) since enable."""
         L, ms, pairs = C.c_int64(), C.c_double(), C.c_double()
         self._check(lib().mstar_profile_read(self._h, C.byref(L), C.byref(ms), C.byref(pairs)))
+        return L.value, ms.value, pairs.value
+
+    def profile_read_kernel(self, kind):
+        """The same for one force kernel: kind 0 pairwise, 1 mutual."""
+        L, ms, pairs = C.c_int64(), C.c_double(), C.c_double()
+        self._check(lib().mstar_profile_read_kernel(self._h, int(kind), C.byref(L), C.byref(ms), C.byref(pairs)))
         return L.value, ms.value, pairs.value

@@ -33,10 +33,11 @@ def test_library_exports_every_declared_symbol():
 def test_abi_version_and_defaults():
     import paper_2001_03180_amd as M
     lib = M.lib()
-    assert lib.mstar_abi_version() == 1
+    assert lib.mstar_abi_version() == 2
     p = M.params()
     assert p.struct_size == ctypes.sizeof(M.Params)
     assert (p.k_fix, p.n_d, p.eta, p.alpha, p.beta, p.gamma) == (8, 2, 1e-12, 1.0, 0.0, 0.0)
+    assert p.accept_rule == 0
     assert lib.mstar_strerror(-6) == b"GBS step did not converge"
 
 
@@ -44,14 +45,14 @@ def test_struct_layout_matches_header(tmp_path):
     import paper_2001_03180_amd as M
     src = tmp_path / "s.c"
     src.write_text('#include "mstar.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(mstar_params), sizeof(mstar_stats),'
-                   ' offsetof(mstar_params, k_fix), offsetof(mstar_stats, t_reached), offsetof(mstar_params, max_steps));'
-                   'return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mstar_params), sizeof(mstar_stats),'
+                   ' offsetof(mstar_params, k_fix), offsetof(mstar_stats, t_reached), offsetof(mstar_params, max_steps),'
+                   ' offsetof(mstar_params, accept_rule));return 0;}\n')
     exe = tmp_path / "s"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(M.Params), ctypes.sizeof(M.Stats), M.Params.k_fix.offset, M.Stats.t_reached.offset,
-            M.Params.max_steps.offset]
+            M.Params.max_steps.offset, M.Params.accept_rule.offset]
     assert [int(g) for g in got] == want
 
 
