@@ -1,0 +1,171 @@
+"""The rest of the C ABI against the oracle: the earliest-k acceptance
+(params.accept_rule = 1, reading of eq. gbs-criterion vs Sec. 4.2) and the
+mass gradient of the adjoint (mstar_replay_adjoint's gm and
+mstar_integrate_adjoint, which records and reverses in one call).
+
+* accept_rule 1: one GBS step and short free integrations against the
+  oracle with the same rule (states 1e-12 of the scale for a step, 1e-10 for
+  integrations; the accepted order is visible as eq. hnext's exponent).
+* gm: the directional derivative <gm, dm> against central differences (with
+  one Richardson step) of the oracle's replay of the same recorded steps with
+  the masses perturbed, the replay being the exact discrete map in MST
+  coordinates (1e-6 relative); against the same differences of the GPU
+  replay; integrate_adjoint equal bit for bit to integrate_record followed
+  by replay_adjoint; device pointers equal to host arrays.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import ics
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-abi] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_03180_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2001_03180_amd as M
+    return M
+
+
+def _state(orc, m, x, v):
+    parent, X, V, scal = orc.build_state(m, x, v)
+    rho = orc.deconstruct(parent, X)
+    _, _, U, _, _ = orc.force(m, parent, X, rho)
+    vt = v - (m[:, None] * v).sum(0) / m.sum()
+    scal[1] = U - 0.5 * (m * (vt ** 2).sum(1)).sum()
+    return parent, X, V, scal
+
+
+@pytest.mark.parametrize("n,seed,H,eta", [(32, 101, 0.05, 1e-8), (32, 101, 0.2, 1e-6), (200, 9, 0.02, 1e-9),
+                                          (1001, 201, 0.005, 1e-10)])
+def test_gbs_step_accept_rule_one(ctx, orc, M, n, seed, H, eta):
+    if n == 1001:
+        m, x, v = ics.plummer_with_central_mass(1000, seed)
+    else:
+        m, x, v = ics.plummer(n, seed)
+    parent, X, V, scal = _state(orc, m, x, v)
+    say(f"gbs_step accept_rule=1 n={n} H={H} eta={eta}")
+    Xg, Vg, sg, acc, eps, hn = ctx.gbs_step(m, parent, X, V, scal, H, M.params(eta=eta, accept_rule=1))
+    Xo, Vo, so, acco, epso, hno, _ = orc.gbs_step(m, parent, X, V, scal, H, orc.params(eta=eta, accept_rule=1))
+    assert acc == acco
+    eps_tol = 1e-3 * epso + 5e-13
+    assert abs(eps - epso) <= eps_tol, (eps, epso)
+    if acc:
+        assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
+        assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+        # h_next ~ eps^(-1/(2k-1)) with k >= 2 (the order chosen shows in it)
+        assert abs(hn - hno) <= (eps_tol / epso / 3 + 1e-14) * hno
+
+
+@pytest.mark.parametrize("n,eta,t_end", [(32, 1e-10, 0.2), (200, 1e-9, 0.02)])
+def test_integrate_accept_rule_one(ctx, orc, M, n, eta, t_end):
+    m, x, v = ics.plummer(n, 3)
+    say(f"integrate accept_rule=1 n={n} eta={eta} t_end={t_end}")
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=eta, accept_rule=1))
+    xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, t_end, orc.params(eta=eta, accept_rule=1))
+    assert rc == rco == 0
+    assert st["steps_accepted"] == sto["steps_accepted"] and st["steps_rejected"] == sto["steps_rejected"]
+    R = np.abs(xo - (m[:, None] * xo).sum(0) / m.sum()).max()
+    Vs = np.abs(vo - (m[:, None] * vo).sum(0) / m.sum()).max()
+    assert np.abs(xg - xo).max() <= 1e-10 * R and np.abs(vg - vo).max() <= 1e-10 * Vs
+
+
+def test_batch_rejects_accept_rule_one(ctx, M):
+    off, mb, xb, vb = ics.batch_subsystems(n_sys=2, seed=401, n_max=8)
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_batch(off, mb, xb, vb, 1e-4, p=M.params(accept_rule=1))
+    assert e.value.code == M.E_UNSUPPORTED
+
+
+def _objective(x, v, gx, gv):
+    return float(np.sum(gx * x) + np.sum(gv * v))
+
+
+@pytest.mark.parametrize("n,steps", [(16, 10), (64, 20)])
+def test_mass_gradient_vs_oracle_differences(ctx, orc, M, n, steps):
+    m, x, v = ics.plummer_with_central_mass(n - 1, 40 + n)
+    xs, vs, rc, st, H, par = orc.integrate_rec(m, x, v, 0.0, 10.0, steps, orc.params(eta=1e-12))
+    assert rc == 0 and len(H) == steps
+    rng = np.random.default_rng(n)
+    gx, gv = rng.standard_normal((2, n, 3))
+    say(f"mass gradient n={n} steps={steps}")
+    ax, av, gm = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.0, 4, with_mass=True)
+    dm = m * rng.standard_normal(n)
+
+    def J_orc(h):
+        xo, vo, _ = orc.replay(m + h * dm, x, v, 0.0, H, par, orc.params(eta=1e-12))
+        return _objective(xo, vo, gx, gv)
+
+    def J_gpu(h):
+        xg, vg, _ = ctx.replay(m + h * dm, x, v, 0.0, H)
+        return _objective(xg, vg, gx, gv)
+
+    h = 1e-5
+    for J, what in ((J_orc, "oracle"), (J_gpu, "gpu")):
+        d1 = (J(h) - J(-h)) / (2 * h)
+        d2 = (J(h / 2) - J(-h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        got = float(np.sum(gm * dm))
+        scale = np.linalg.norm(gm) * np.linalg.norm(dm)
+        say(f"  {what}: <gm, dm> = {got:.12e}, differences {fd:.12e}")
+        assert abs(got - fd) <= 1e-6 * scale, (what, got, fd)
+    # the position / velocity gradients are unchanged by asking for gm
+    bx, bv = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.0, 4)
+    assert np.array_equal(ax, bx) and np.array_equal(av, bv)
+
+
+def test_integrate_adjoint_records_and_reverses(ctx, orc, M):
+    import torch
+    m, x, v = ics.plummer_with_central_mass(63, 77)
+    n = len(m)
+    rng = np.random.default_rng(5)
+    gx, gv = rng.standard_normal((2, n, 3))
+    p = M.params(eta=1e-12)
+    say("integrate_adjoint n=64, 25 steps")
+    ax, av, gm, st = ctx.integrate_adjoint(m, x, v, 0.0, 10.0, 25, gx, gv, 0.3, checkpoint_every=7, p=p)
+    assert st["steps_accepted"] == 25
+    xr, vr, rc, st2, H = ctx.integrate_record(m, x, v, 0.0, 10.0, 25, M.params(eta=1e-12))
+    bx, bv, bm = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.3, 7, with_mass=True)
+    assert np.array_equal(ax, bx) and np.array_equal(av, bv) and np.array_equal(gm, bm)
+    # device pointers
+    T = lambda a: torch.tensor(a, device="cuda")
+    dx, dv, dgm, _ = ctx.integrate_adjoint(T(m), T(x), T(v), 0.0, 10.0, 25, T(gx), T(gv), 0.3, checkpoint_every=7,
+                                           p=M.params(eta=1e-12))
+    assert np.array_equal(dx.cpu().numpy(), ax) and np.array_equal(dgm.cpu().numpy(), gm)
+    # the gradient against the oracle's tangent-linear model of the GPU's record
+    dxx, dvv = rng.standard_normal((2, 4, n, 3))
+    _, _, _, Dx, Dv, Dt = orc.replay_tlm(m, x, v, 0.0, H, dxx, dvv, orc.params(eta=1e-12))
+    for q in range(4):
+        lhs = np.sum(gx * Dx[q]) + np.sum(gv * Dv[q]) + 0.3 * Dt[q]
+        rhs = np.sum(ax * dxx[q]) + np.sum(av * dvv[q])
+        scale = np.linalg.norm(gx) * np.linalg.norm(Dx[q]) + np.linalg.norm(gv) * np.linalg.norm(Dv[q])
+        assert abs(lhs - rhs) <= 1e-9 * scale
+
+
+def test_integrate_adjoint_errors(ctx, M):
+    m, x, v = ics.plummer(8, 1)
+    g = np.zeros((8, 3))
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_adjoint(m, x, v, 0.0, 1.0, 0, g, g)
+    assert e.value.code == M.E_INVAL
+    with pytest.raises(M.MstarError) as e:
+        ctx.integrate_adjoint(m, x, v, 0.0, 1.0, 5, g, g, p=M.params(beta=1.0, omega_mass_max=1.0))
+    assert e.value.code == M.E_UNSUPPORTED

@@ -1,0 +1,96 @@
+"""Free integrations of the benchmark workloads on the GPU against the oracle,
+with the energy gates of the method's accuracy claim (|dE/E| ~ 1e-14, paper
+abstract and Sec. 5).
+
+Workloads (ics.workload): plummer1000_bh (N_p = 1001, eta = 1e-13),
+plummer5000_binary (N_p = 5002, eta = 1e-13; the benchmark workload) and
+plummer10000_binary (N_p = 10002), each from t = 0 to an end time inside its
+predictability horizon: two oracle runs whose initial conditions differ by one
+ulp in one coordinate end within 1e-11 of each other there (measured: 3e-14
+at t = 0.2 for N_p = 1001, 67 accepted steps; the binary workloads below).
+
+Gates (positions relative to max|r - r_cm|, velocities to max|v - v_cm|):
+  * end state 1e-10, the end times within 2e-14 of the interval;
+  * |dE/E| of the GPU run <= 1e-13 and within 1e-13 of the oracle's;
+  * the binary's internal state (separation and relative velocity) relative
+    to its own size: reported, and gated at 1e-8 (the binary takes about ten
+    of the run's steps per orbit, so its phase carries the integration error
+    itself; the gate is loose on purpose, its value is printed).
+Accepted-step counts are reported: two correct runs whose error measures sit
+near eta can take different step sequences (the 1-ulp oracle pair above took
+67 and 70 steps) while their states agree to rounding.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import ics
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-int] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_03180_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2001_03180_amd as M
+    return M
+
+
+def _energy(orc, m, x, v):
+    return orc.diagnostics(m, x, v)["E"]
+
+
+CASES = [("plummer1000_bh", 0.2), ("plummer5000_binary", 0.003), ("plummer10000_binary", 0.001)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,t_end", CASES, ids=[c[0] for c in CASES])
+def test_free_integration_parity_with_energy(ctx, orc, M, name, t_end):
+    m, x, v, wl = ics.workload(name)
+    eta = wl["eta"]
+    say(f"{name}: n={len(m)} eta={eta} t_end={t_end} (GPU)")
+    t0 = time.perf_counter()
+    xg, vg, rc, st = ctx.integrate(m, x, v, 0.0, t_end, M.params(eta=eta))
+    tg = time.perf_counter() - t0
+    say(f"{name}: GPU {st['steps_accepted']}+{st['steps_rejected']} steps in {tg:.2f} s; oracle ...")
+    t0 = time.perf_counter()
+    xo, vo, rco, sto = orc.integrate(m, x, v, 0.0, t_end, orc.params(eta=eta, nthreads=0))
+    say(f"{name}: oracle {sto['steps_accepted']}+{sto['steps_rejected']} steps in {time.perf_counter() - t0:.1f} s")
+    assert rc == rco == 0
+    assert abs(st["t_reached"] - sto["t_reached"]) <= 2e-14 * t_end
+    rc_ = (m[:, None] * xo).sum(0) / m.sum()
+    vc_ = (m[:, None] * vo).sum(0) / m.sum()
+    ex = np.abs(xg - xo).max() / np.abs(xo - rc_).max()
+    ev = np.abs(vg - vo).max() / np.abs(vo - vc_).max()
+    E0 = _energy(orc, m, x, v)
+    dEg = (_energy(orc, m, xg, vg) - E0) / E0
+    dEo = (_energy(orc, m, xo, vo) - E0) / E0
+    line = (f"{name}: state |dx|/R={ex:.2e} |dv|/V={ev:.2e}; dE/E gpu={dEg:.2e} oracle={dEo:.2e} "
+            f"diff={abs(dEg - dEo):.2e}")
+    if name.endswith("binary"):
+        rg, ro = xg[-1] - xg[-2], xo[-1] - xo[-2]
+        ug, uo = vg[-1] - vg[-2], vo[-1] - vo[-2]
+        br = np.linalg.norm(rg - ro) / np.linalg.norm(ro)
+        bv = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        line += f"; binary |dr|/r={br:.2e} |du|/u={bv:.2e}"
+        assert br <= 1e-8 and bv <= 1e-8, line
+    say(line)
+    assert ex <= 1e-10 and ev <= 1e-10, line
+    assert abs(dEg) <= 1e-13 and abs(dEg - dEo) <= 1e-13, line

@@ -78,6 +78,16 @@ def test_mst_parity(ctx, orc, name, make):
     assert root3 == ro and np.array_equal(parent3, po) and np.array_equal(level3, lo)
 
 
+def _edge_rel_ok(Xg, Xo, tol=1e-12):
+    """Every MST edge against its own length (a hard binary's edge is ~1e-4 of
+    the cluster's size), with a floor of 1e-16 of the longest edge for rows
+    at the rounding level (the root row is zero)."""
+    lo = np.linalg.norm(Xo, axis=1)
+    d = np.linalg.norm(Xg - Xo, axis=1)
+    bad = d > tol * lo + 1e-16 * lo.max()
+    return not bad.any(), float((d / np.maximum(lo, 1e-300))[lo > 0].max())
+
+
 def _state(orc, m, x, v):
     parent, X, V, scal = orc.build_state(m, x, v)
     rho = orc.deconstruct(parent, X)
@@ -123,6 +133,78 @@ def test_force_parity(ctx, orc, M, name, n, seed, nd):
     assert abs(U - Uo) <= 1e-13 * Uo
 
 
+@pytest.fixture(scope="module")
+def ctx_kinds():
+    """One context per force kernel (MSTAR_FORCE_KERNEL is read when a context
+    is created): the pairwise kernel, and the mutual (i < j) kernel at any N."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_03180_amd as M
+    old = os.environ.get("MSTAR_FORCE_KERNEL")
+    out = {}
+    try:
+        for kind in ("pairwise", "mutual"):
+            os.environ["MSTAR_FORCE_KERNEL"] = kind
+            out[kind] = M.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("MSTAR_FORCE_KERNEL", None)
+        else:
+            os.environ["MSTAR_FORCE_KERNEL"] = old
+    yield out
+    for c in out.values():
+        c.close()
+
+
+KIND_CASES = [("plummer32", 32, 101), ("plummer65_ragged", 65, 3), ("plummer200_ragged", 200, 7),
+              ("plummer1001", 1001, 201), ("binary5002", 5002, 301)]
+
+
+@pytest.mark.parametrize("name,n,seed", KIND_CASES, ids=[c[0] for c in KIND_CASES])
+@pytest.mark.parametrize("nd", [0, 2])
+@pytest.mark.parametrize("kind", ["pairwise", "mutual"])
+def test_force_parity_kernels(ctx_kinds, orc, M, kind, name, n, seed, nd):
+    """Both force kernels against the oracle at sizes with full and ragged
+    64-body blocks (the mutual kernel's rows of 256 bodies, its diagonal
+    blocks and padding), each result bitwise reproducible."""
+    if n == 5002:
+        m, x, v = ics.plummer_with_binary(n - 2, seed)
+    elif n == 1001:
+        m, x, v = ics.plummer_with_central_mass(1000, seed)
+    else:
+        m, x, v = ics.plummer(n, seed)
+    parent, X, V, scal, rho = _state(orc, m, x, v)
+    say(f"force kernel={kind} {name} n={n} nd={nd}")
+    c = ctx_kinds[kind]
+    p = M.params(n_d=nd)
+    acc, U = c.force(m, rho, parent, X, p)
+    acc2, U2 = c.force(m, rho, parent, X, p)
+    assert np.array_equal(acc, acc2) and U == U2
+    ao, _, Uo, _, _ = orc.force(m, parent, X, rho, orc.params(n_d=nd, nthreads=0))
+    err = np.abs(acc - ao).max(1) / _scale(m, rho)
+    assert err.max() <= 1e-13, err.max()
+    assert abs(U - Uo) <= 1e-13 * Uo
+
+
+@pytest.mark.parametrize("kind", ["pairwise", "mutual"])
+def test_gbs_step_parity_kernels(ctx_kinds, orc, M, kind):
+    """A GBS step (72 + 1 force evaluations, lane-packed launches of 1..5
+    evaluations, each split over waves differently) with either kernel."""
+    m, x, v = ics.plummer(300, 17)
+    parent, X, V, scal, _ = _state(orc, m, x, v)
+    say(f"gbs_step kernel={kind} n=300")
+    p = M.params(k_fix=8, eta=1e-12)
+    Xg, Vg, sg, acc, eps, hn = ctx_kinds[kind].gbs_step(m, parent, X, V, scal, 0.002, p)
+    Xo, Vo, so, acco, epso, hno, nf = orc.gbs_step(m, parent, X, V, scal, 0.002, orc.params(k_fix=8, eta=1e-12))
+    eps_tol = 1e-3 * epso + 5e-13
+    assert abs(eps - epso) <= eps_tol, (eps, epso)
+    assert acc == acco == 1
+    assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
+    assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+
+
 def test_force_close_pairs_matter(ctx, orc, M):
     """A tight pair far from the origin: the MST path sum keeps digits that the
     Cartesian difference loses; GPU and oracle both use the path sum."""
@@ -154,6 +236,9 @@ def test_leapfrog_parity(ctx, orc, M, n, seed, H, nsub):
     Xo, Vo, so, nf = orc.leapfrog(m, parent, X, V, scal, H, nsub)
     assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
     assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+    for a, b in ((Xg, Xo), (Vg, Vo)):
+        ok, worst = _edge_rel_ok(a, b)
+        assert ok, worst
     assert abs(sg[0] - so[0]) <= 1e-13 * abs(so[0])
     np.testing.assert_allclose(sg[3:6], so[3:6], atol=1e-15)
 
@@ -182,6 +267,9 @@ def test_gbs_step_parity(ctx, orc, M, n, seed, H, kf):
     if acc and acco:
         assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
         assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
+        for a, b in ((Xg, Xo), (Vg, Vo)):
+            ok, worst = _edge_rel_ok(a, b)
+            assert ok, worst
         assert abs(sg[0] - so[0]) <= 1e-14 * abs(so[0]) + 1e-16
         # h_next ~ eps^(-1/(2k-1)): relative spread <= |d eps / eps| / (2k - 1)
         assert abs(hn - hno) <= (eps_tol / epso / (2 * kf - 1) + 1e-14) * hno
@@ -209,6 +297,13 @@ def test_gbs_step_parity_full_size(ctx, orc, M, n_stars, seed):
     assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(Xo).max()
     assert np.abs(Vg - Vo).max() <= 1e-12 * np.abs(Vo).max()
     assert abs(sg[0] - so[0]) <= 1e-14 * abs(so[0]) + 1e-16
+    # every edge against its own length, the binary's (the last two bodies) shown
+    b = len(m) - 1
+    for a, o, what in ((Xg, Xo, "X"), (Vg, Vo, "V")):
+        ok, worst = _edge_rel_ok(a, o)
+        rb = np.linalg.norm(a[b] - o[b]) / np.linalg.norm(o[b]) if parent[b] >= 0 else 0.0
+        say(f"  per-edge worst relative {what}: {worst:.2e}; binary edge {rb:.2e}")
+        assert ok, worst
 
 
 def _rel_state_err(xg, vg, xo, vo, m):
