@@ -92,7 +92,7 @@ def lib():
             "orc_sdiv": (C.c_double, [C.c_int, C.c_int, I]),
             "orc_integrate_rec": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats),
                                             C.c_int64, D, I, I64]),
-            "orc_replay": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, I, P, D]),
+            "orc_replay": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, I, P, D, D]),
             "orc_force_tlm": (C.c_int, [C.c_int, D, D, C.c_double, C.c_int, D, D, D, D, D, C.c_int]),
             "orc_lagrange_weights": (None, [C.c_int, D]),
             "orc_replay_tlm": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, P, C.c_int, D, D, D, D]),
@@ -354,9 +354,10 @@ def integrate_rec(m, x, v, t0, t_end, max_accepted, p: Params | None = None):
     return x, v, rc, st.as_dict(), H[:k.value].copy(), par[:k.value].copy()
 
 
-def replay(m, x, v, t0, H, parents, p: Params | None = None):
+def replay(m, x, v, t0, H, parents, p: Params | None = None, times=False):
     """Frozen-controller replay in MST coordinates: (x, v, t) after len(H) steps.
-    parents None: the driver's own MST builds and rebuilds."""
+    parents None: the driver's own MST builds and rebuilds.  times=True adds
+    the time after every step: (x, v, t, t_steps)."""
     p = p or params()
     m, pm = _d(m)
     x = np.array(x, dtype=np.float64, order="C"); v = np.array(v, dtype=np.float64, order="C")
@@ -368,9 +369,10 @@ def replay(m, x, v, t0, H, parents, p: Params | None = None):
         assert par.shape == (len(H), len(m))
         pp = par.ctypes.data_as(C.POINTER(C.c_int32))
     t = C.c_double()
+    ts = np.zeros(len(H)) if times else None
     _check(lib().orc_replay(len(m), pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1], pp, C.byref(p),
-                            C.byref(t)), "replay")
-    return x, v, t.value
+                            C.byref(t), _d(ts)[1] if times else None), "replay")
+    return (x, v, t.value, ts) if times else (x, v, t.value)
 
 
 def force_tlm(m, r, dr, G=1.0, nthreads=0):

@@ -1228,9 +1228,10 @@ out:
  * the driver's own: the MST of x rooted nearest the centre of mass at the
  * start, and the rebuild of Sec. 3.5 before every rebuild_every-th step
  * after it -- the integration of orc_integrate with its accepted step
- * lengths given instead of chosen. */
+ * lengths given instead of chosen.  t_steps (nullable, nsteps values)
+ * receives the time after each step. */
 int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t nsteps, const double *H,
-               const int32_t *parents, const orc_params *p, double *t_out) {
+               const int32_t *parents, const orc_params *p, double *t_out, double *t_steps) {
     if (n < 2 || nsteps < 0 || !H || p->beta != 0.0) return ORC_E_INVAL;
     int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
     int *order = (int *)malloc(sizeof(int) * (size_t)n);
@@ -1275,6 +1276,7 @@ int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t 
                 since_rebuild = 0;
             }
             if (!rc) rc = replay_step(&y, p, &s, H[k], &nf);
+            if (!rc && t_steps) t_steps[k] = y.t;
             since_rebuild++;
         }
     }

@@ -142,3 +142,15 @@ def test_replay_with_own_trees_repeats_integration(orc):
         assert rc == 0 and st["t_reached"] == t_end
         xa, va, ta = orc.replay(m, x, v, 0.0, H, None, orc.params(eta=1e-12))
         assert np.array_equal(xa, xs) and np.array_equal(va, vs) and ta == st["t_reached"]
+
+
+def test_replay_step_times_are_the_prefix_replays(orc):
+    """The per-step times of a replay are the end times of the replays of
+    its prefixes, bit for bit (not monotonic at the end: the end-time clip
+    of Sec. 2.4 may step back after an overshoot)."""
+    m, x, v = ics.plummer(16, 5)
+    xs, vs, st, H, par, p = _rec(orc, m, x, v, 0.2, 60)
+    xr, vr, tr, ts = orc.replay(m, x, v, 0.0, H, None, p, times=True)
+    assert len(ts) == len(H) and ts[-1] == tr and np.all(np.diff(ts[:-3]) > 0)
+    for k in (1, len(H) // 3, len(H) - 1):
+        assert orc.replay(m, x, v, 0.0, H[:k], None, p)[2] == ts[k - 1]
