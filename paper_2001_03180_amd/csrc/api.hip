@@ -1284,7 +1284,6 @@ int ensure_batch(mstar_ctx *ctx, int64_t n_sys, int64_t n_tot) {
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     ctx->b_allocs.clear();
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
-    if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
     ctx->h_bstat = nullptr;
     if (ctx->b_exec) (void)hipGraphExecDestroy(ctx->b_exec);
     ctx->b_exec = nullptr;

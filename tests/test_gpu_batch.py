@@ -9,7 +9,10 @@ that follows a flipped decision (check_counts).  Launch shapes (tile width,
 the N cut between whole-workgroup and single-wave systems, workgroups per
 CU, graph or plain launch) do not change a single bit of the result:
 zero-padded lanes add exact zeros to every butterfly sum, and every per-body
-quantity is computed by the same instruction sequence.
+quantity is computed by the same instruction sequence.  Replay mode
+(check_replay) removes the step decisions: the oracle repeats the GPU's
+recorded step lengths, and the end states are compared against the oracle's
+own sensitivity to ulp-sized changes of its inputs and step lengths.
 """
 import math
 import sys
@@ -23,6 +26,25 @@ pytestmark = pytest.mark.gpu
 
 T_SHORT = 1e-3      # horizon of the small parity batches
 T_FULL = 1e-2       # horizon of the full 4096-system workload
+
+
+def _replay_time_rel(k_fix=8):
+    """Bound on |t_gpu - t_replay| / t_end when the oracle replays recorded steps.
+
+    A step's time increment is the Neville-Aitken extrapolation to h -> 0
+    (Sec. 2.3) of the division sums over n_k = 2k substeps; each sum carries
+    at most (n_k + 2) u of relative rounding, and the extrapolation weights
+    L_k of the sequence x_k = 1/n_k^2 (sum |L_k| = 119 at k_fix = 8) amplify
+    it to sum_k |L_k| (n_k + 2) u of the step.  Nothing clips the replayed
+    time to t_end, so two correct runs can differ by twice that, summed over
+    the steps: about 4.1e-13 of the interval."""
+    n = [2.0 * k for k in range(1, k_fix + 1)]
+    x = [1.0 / (v * v) for v in n]
+    L = [math.prod(xj / (xj - xi) for j, xj in enumerate(x) if j != i) for i, xi in enumerate(x)]
+    return 2.0 * sum(abs(l) * (v + 2.0) for l, v in zip(L, n)) * np.finfo(float).eps / 2
+
+
+REPLAY_TIME_REL = _replay_time_rel()
 
 
 def say(msg):
@@ -115,13 +137,129 @@ def check_counts(st, s, sto):
         assert abs(a - b) <= max(5, 0.1 * b), (s, k, a, b)
 
 
+def _ulp_sensitivity(orc, ms, xs, vs, H, xr, vr, ts, p):
+    """How far the oracle's own replay moves under ulp-sized perturbations of
+    two kinds: one input coordinate moved by one ulp (a position, then a
+    velocity), and every step length moved by one ulp up or down at random
+    (seeded; two draws).  The second kind stands for what two correct
+    implementations do differently at every step: each step's extrapolated
+    increments carry rounding amplified by the extrapolation weights, and in
+    well-conditioned systems (a planet-like system of 38 steps) these
+    per-step differences, not the start state's, dominate the end.  Returns
+    the largest relative end-state change, the largest change of the end
+    energy relative to the initial energy, and the largest change of the time
+    after any step (ts: the unperturbed times).  Close eccentric pairs
+    amplify the state change to ~1e-11 over 1e-3 time units, mostly as a
+    phase shift along their orbits; since the time runs slower near each
+    pericentre, a phase shift moves the time after a step back and forth by
+    an amount that is largest somewhere inside the run, not necessarily at
+    its end."""
+    n = len(ms)
+    E0 = orc.diagnostics(ms, xs, vs)["E"]
+    Er = orc.diagnostics(ms, xr, vr)["E"]
+    ws, we, wt = 0.0, 0.0, 0.0
+    for j in range(4):
+        x2, v2, H2 = xs.copy(), vs.copy(), H
+        if j == 0:
+            x2[0, 0] = np.nextafter(x2[0, 0], np.inf)
+        elif j == 1:
+            v2[n // 2, 1] = np.nextafter(v2[n // 2, 1], np.inf)
+        else:
+            up = np.random.default_rng(j).integers(0, 2, len(H)) == 1
+            H2 = np.where(up, np.nextafter(H, np.inf), np.nextafter(H, -np.inf))
+        xp, vp, _, tp = orc.replay(ms, x2, v2, 0.0, H2, None, p, times=True)
+        ws = max(ws, *rel_err(xp, vp, xr, vr, ms))
+        we = max(we, abs((orc.diagnostics(ms, xp, vp)["E"] - Er) / E0))
+        wt = max(wt, float(np.abs(tp - ts).max(initial=0.0)))
+    return ws, we, wt
+
+
+def check_replay(orc, off, m, x, v, xg, vg, st, H, t_end, systems, eta=1e-12, threads=16):
+    """Replay mode (no step decisions): the oracle integrates each system with
+    the GPU's recorded accepted step lengths and its own MST builds and
+    rebuilds.  The two runs round differently at every step, so their end
+    states can differ by what the replay map makes of ulp-level changes.
+    Each system's state error may not exceed ten times the oracle's own
+    change under ulp-sized perturbations (_ulp_sensitivity), with a
+    floor of 1e-12 of the system's extent and velocity spread; the end
+    energies (relative to the initial one) agree to ten times the energy
+    change under the same perturbations, with a floor of 1e-13; the end
+    times agree to ten times the largest time change under them after any
+    step, with a floor of REPLAY_TIME_REL of the interval.  Returns per-system (state error,
+    |dE/E| GPU, |dE/E| replay, state, energy and time sensitivities)."""
+    import concurrent.futures as cf
+
+    def one(s):
+        o, e = int(off[s]), int(off[s + 1])
+        ms, xs, vs = m[o:e], x[o:e], v[o:e]
+        k = int(st["steps_accepted"][s])
+        assert st["status"][s] == 0 and k <= H.shape[1], (s, st["status"][s], k)
+        p = orc.params(eta=eta, nthreads=1)
+        xr, vr, tr, ts = orc.replay(ms, xs, vs, 0.0, H[s, :k], None, p, times=True)
+        ex, ev = rel_err(xg[o:e], vg[o:e], xr, vr, ms)
+        E0 = orc.diagnostics(ms, xs, vs)["E"]
+        dg = (orc.diagnostics(ms, xg[o:e], vg[o:e])["E"] - E0) / E0
+        dr = (orc.diagnostics(ms, xr, vr)["E"] - E0) / E0
+        return (s, max(ex, ev), dg, dr, tr - st["t_reached"][s]) + \
+            _ulp_sensitivity(orc, ms, xs, vs, H[s, :k], xr, vr, ts, p)
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+        out = list(pool.map(one, systems))
+    for s, err, dg, dr, dt, sens, sens_e, sens_t in out:
+        assert err <= max(1e-12, 10.0 * sens), (s, err, sens)
+        assert abs(dg - dr) <= max(1e-13, 10.0 * sens_e), (s, dg, dr, sens_e)
+        assert abs(dt) <= max(REPLAY_TIME_REL * abs(t_end), 10.0 * sens_t), (s, dt, sens_t)
+    return [(s, err, dg, dr, sens) for s, err, dg, dr, dt, sens, sens_e, sens_t in out]
+
+
 def test_batch_parity_small(ctx, orc, M, small):
+    """All 40 systems: replay mode (the batch kernel's arithmetic, free of
+    step decisions, against the oracle's own rounding sensitivity), then
+    free mode against the oracle's own integration: 1e-10 for every system whose accepted and rejected step
+    counts equal the oracle's; where a decision differed, the difference
+    is reported together with the size of the integration error itself."""
     off, m, x, v = small
-    say(f"batch of {len(off) - 1} systems, t_end={T_SHORT}")
-    xg, vg, st = ctx.integrate_batch(off, m, x, v, T_SHORT, p=M.params(eta=1e-12))
-    worst, via_ref = check_vs_oracle(orc, off, m, x, v, xg, vg, st, T_SHORT, range(len(off) - 1))
-    say(f"worst relative state error vs oracle {worst:.2e}; checked against the reference: {via_ref}")
-    assert len(via_ref) <= 8
+    n_sys = len(off) - 1
+    say(f"batch of {n_sys} systems, t_end={T_SHORT}, recording the accepted steps")
+    xg, vg, st, H = ctx.integrate_batch_record(off, m, x, v, T_SHORT, 4096, p=M.params(eta=1e-12))
+    xb, vb, stb = ctx.integrate_batch(off, m, x, v, T_SHORT, p=M.params(eta=1e-12))
+    assert np.array_equal(xg, xb) and np.array_equal(vg, vb) and np.array_equal(st, stb)   # recording is passive
+    rep = check_replay(orc, off, m, x, v, xg, vg, st, H, T_SHORT, range(n_sys))
+    say(f"replay mode: worst state error {max(r[1] for r in rep):.2e} (worst error / ulp sensitivity "
+        f"{max(r[1] / max(r[4], 1e-300) for r in rep):.2f}), worst |dE/E gpu - replay| "
+        f"{max(abs(r[2] - r[3]) for r in rep):.2e}")
+    flips = []
+    for s in range(n_sys):
+        o, e = int(off[s]), int(off[s + 1])
+        xo, vo, rco, sto = orc.integrate(m[o:e], x[o:e], v[o:e], 0.0, T_SHORT, orc.params(eta=1e-12))
+        assert rco == 0 and abs(st["t_reached"][s] - sto["t_reached"]) <= 2e-14 * T_SHORT
+        ex, ev = rel_err(xg[o:e], vg[o:e], xo, vo, m[o:e])
+        same = (st["steps_accepted"][s], st["steps_rejected"][s]) == (sto["steps_accepted"], sto["steps_rejected"])
+        if same:
+            assert ex <= 1e-10 and ev <= 1e-10, (s, ex, ev)
+        else:
+            flips.append(s)
+            say(f"system {s} N={e - o}: steps gpu {st['steps_accepted'][s]}+{st['steps_rejected'][s]} oracle "
+                f"{sto['steps_accepted']}+{sto['steps_rejected']}: free-mode difference {max(ex, ev):.1e}")
+            assert ex <= 1e-10, (s, ex)
+    say(f"free mode: {n_sys - len(flips)} of {n_sys} systems took the oracle's step sequence; flips {flips}")
+
+
+def test_record_buffer_survives_growth(ctx, M, small):
+    """A recording call, then calls on larger batches (the context grows its
+    batch buffers), then a recording call again: the record buffer belongs to
+    the recording calls alone and the repeated record is identical."""
+    off, m, x, v = small
+    o8, m8, x8, v8 = sub_batch(off, m, x, v, list(range(8)))
+    p = M.params(eta=1e-12)
+    first = ctx.integrate_batch_record(o8, m8, x8, v8, T_SHORT, 512, p=p)
+    full = ics.batch_subsystems()
+    for k in (300, 600):
+        o2, m2, x2, v2 = sub_batch(*full, list(range(k)))
+        ctx.integrate_batch(o2, m2, x2, v2, 2e-4, p=p)
+    again = ctx.integrate_batch_record(o8, m8, x8, v8, T_SHORT, 512, p=p)
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
 
 
 def test_batch_matches_single_system_path(ctx, M, small):
@@ -290,12 +428,19 @@ def test_full_workload_sampled(ctx, orc, M):
     xg, vg, st = ctx.integrate_batch(off, m, x, v, T_FULL, p=M.params(eta=1e-12))
     assert np.all(st["status"] == M.OK), np.unique(st["status"], return_counts=True)
     assert np.all(np.abs(st["t_reached"] - T_FULL) <= 1e-14 * T_FULL)
+    # 64 systems spread over N (every 64th by size) and 8 hierarchical triples,
+    # replayed by the oracle with the recorded step lengths
+    xr, vr, str_, H = ctx.integrate_batch_record(off, m, x, v, T_FULL, 8192, p=M.params(eta=1e-12))
+    assert np.array_equal(xr, xg) and np.array_equal(vr, vg)
     order = np.argsort(sizes, kind="stable")
-    triple = int(np.nonzero(sizes == 3)[0][0])
-    sample = [int(order[-1]), int(order[len(order) // 2]), int(order[0]), triple]
-    say(f"oracle on systems {sample} (N={[int(sizes[s]) for s in sample]})")
-    worst, via_ref = check_vs_oracle(orc, off, m, x, v, xg, vg, st, T_FULL, sample)
-    say(f"worst relative state error vs oracle {worst:.2e}; checked against the reference: {via_ref}")
+    triples = [int(s) for s in np.nonzero(sizes == 3)[0][:8]]
+    sample = sorted(set(int(order[k]) for k in range(0, len(order), 64)) | set(triples))
+    say(f"oracle replay of {len(sample)} systems (N {int(sizes[sample].min())}..{int(sizes[sample].max())}, "
+        f"{len(triples)} triples)")
+    rep = check_replay(orc, off, m, x, v, xg, vg, st, H, T_FULL, sample)
+    say(f"replay mode: worst state error {max(r[1] for r in rep):.2e} (worst error / ulp sensitivity "
+        f"{max(r[1] / max(r[4], 1e-300) for r in rep):.2f}), worst |dE/E gpu - replay| "
+        f"{max(abs(r[2] - r[3]) for r in rep):.2e}")
     dE = np.empty(len(sizes))
     for s in range(len(sizes)):
         o, e = int(off[s]), int(off[s + 1])
