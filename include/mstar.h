@@ -203,6 +203,27 @@ int mstar_gbs_step(mstar_ctx *ctx, const mstar_params *params, int64_t n, const 
                    const int32_t *parent, double *X, double *V, double *scal, double H,
                    int32_t *accepted, double *eps, double *h_next);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid it): mstar_force without a
+ * context and without any allocation, host copy or synchronisation.  The
+ * work is only enqueued on hip_stream (a hipStream_t; NULL: the null stream)
+ * of the current device; outputs are valid once that stream has reached this
+ * point.  m [n], rho [n][3], parent [n] (int32), X [n][3] are device
+ * pointers read by the enqueued kernels, acc [n][3] and U (one double) device
+ * pointers written by them; parent, X, rho and the result as mstar_force
+ * (params->n_d 0..4, params->beta must be 0; params->flags is ignored).  The
+ * library keeps its intermediate results in a fixed device array of about
+ * 6 MB per device (allocated with the library's code object, not by the
+ * call), so n is limited to MSTAR_NOALLOC_MAX_N, and calls that overlap on one
+ * device (different streams or host threads) race on that array.  Errors:
+ * MSTAR_E_INVAL (NULL pointers, bad params, n < 2 or n > MSTAR_NOALLOC_MAX_N),
+ * MSTAR_E_UNSUPPORTED (n_d > 4, beta != 0), MSTAR_E_DEVICE.  A parent array
+ * that is not one rooted tree cannot be reported synchronously: acc and U
+ * are then NaN. */
+#define MSTAR_NOALLOC_MAX_N 8192
+int mstar_force_noalloc(void *hip_stream, const mstar_params *params, int64_t n, const double *m, const double *rho,
+                        const int32_t *parent, const double *X, double *acc, double *U);
+
 /* Force-kernel timing for measurement: when enabled, every force-kernel
  * launch is bracketed by HIP events on the context stream; the totals cover
  * all launches since the last reset.  A batched call counts as one launch

@@ -122,6 +122,8 @@ EXPORTS = {
                                           C.POINTER(Stats)]),
     "mstar_force_hvp": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
+    "mstar_force_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
@@ -199,6 +201,25 @@ def _mode(*args):
         torch.cuda.synchronize()
         return DEVICE_PTRS
     return 0
+
+
+NOALLOC_MAX_N = 8192
+
+
+def force_noalloc(m, rho, parent, X, acc, U, p: Params | None = None, stream=None):
+    """mstar_force_noalloc on device tensors (m [n], rho [n,3], parent [n] int32,
+    X [n,3] inputs; acc [n,3] and U [1] outputs, all on the current device):
+    enqueues the evaluation on `stream` (a torch.cuda.Stream, default the
+    current stream) without allocating; returns the status code."""
+    import torch
+    p = p or params()
+    n = len(m)
+    a = [_Arg(m, np.float64, (n,)), _Arg(rho, np.float64, (n, 3)), _Arg(parent, np.int32, (n,)),
+         _Arg(X, np.float64, (n, 3)), _Arg(acc, np.float64, (n, 3), True), _Arg(U, np.float64, (1,), True)]
+    if not all(x.dev for x in a):
+        raise TypeError("force_noalloc takes device tensors only")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    return lib().mstar_force_noalloc(C.c_void_p(s), C.byref(p), n, *(x.ptr for x in a))
 
 
 class Context:
