@@ -31,7 +31,7 @@ class Params(C.Structure):
         ("f_min", C.c_double), ("f_max", C.c_double), ("q_first", C.c_double), ("t_tol", C.c_double),
         ("h_init", C.c_double), ("max_steps", C.c_int64), ("k_fix", C.c_int32), ("n_d", C.c_int32),
         ("max_halvings", C.c_int32), ("max_time_iter", C.c_int32), ("rebuild_every", C.c_int32),
-        ("nthreads", C.c_int32), ("accept_rule", C.c_int32), ("pad_", C.c_int32),
+        ("nthreads", C.c_int32), ("accept_rule", C.c_int32), ("mst_method", C.c_int32),
     ]
 
 
@@ -50,7 +50,8 @@ def params(**kw) -> Params:
     """Default parameters (LogH, k_fix = 8, N_d = 2, eta = 1e-12), overridable."""
     p = Params(G=1.0, eta=1e-12, alpha=1.0, beta=0.0, gamma=0.0, omega_mass_max=0.0, a_gbs=0.9,
                f_min=0.1, f_max=4.0, q_first=0.1, t_tol=1e-14, h_init=0.0, max_steps=10**9, k_fix=8,
-               n_d=2, max_halvings=60, max_time_iter=8, rebuild_every=1, nthreads=0, accept_rule=0)
+               n_d=2, max_halvings=60, max_time_iter=8, rebuild_every=1, nthreads=0, accept_rule=0,
+               mst_method=0)
     for k, v in kw.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -73,6 +74,7 @@ def lib():
         sig = {
             "orc_root_nearest_com": (C.c_int, [C.c_int, D, D]),
             "orc_mst_prim": (C.c_int, [C.c_int, D, C.c_int, I, I, I]),
+            "orc_mst_dc": (C.c_int, [C.c_int, D, C.c_int, C.c_int, I, I, I, I, I]),
             "orc_chain_build": (C.c_int, [C.c_int, D, I, I, I]),
             "orc_rebuild_cycles": (C.c_int, [C.c_int, D, D, D, C.c_int, C.c_int64, C.c_int, D, D, D]),
             "orc_tree_levels": (C.c_int, [C.c_int, I, I, I]),
@@ -136,6 +138,21 @@ def mst(x, root):
     order, po = _i(np.empty(n, dtype=np.int32))
     _check(lib().orc_mst_prim(n, px, int(root), pp, pl, po), "mst")
     return parent, level, order
+
+
+def mst_dc(x, root, mcap=0):
+    """Divide-and-conquer spanning tree (Sec. 3.3) rooted at `root`, groups of at
+    most mcap bodies (0: ceil(sqrt(N))): returns (parent, level, order, part, nparts)."""
+    x, px = _d(x)
+    n = x.shape[0]
+    parent, pp = _i(np.empty(n, dtype=np.int32))
+    level, pl = _i(np.empty(n, dtype=np.int32))
+    order, po = _i(np.empty(n, dtype=np.int32))
+    part, pq = _i(np.empty(n, dtype=np.int32))
+    npart = np.zeros(1, dtype=np.int32)
+    _check(lib().orc_mst_dc(n, px, int(root), int(mcap), pp, pl, po, pq,
+                            npart.ctypes.data_as(C.POINTER(C.c_int32))), "mst_dc")
+    return parent, level, order, part, int(npart[0])
 
 
 def chain(x):

@@ -59,7 +59,7 @@ typedef struct {
     int32_t nthreads;      /* OpenMP threads for the force loop (0 = default) */
     int32_t accept_rule;   /* READING of eq. gbs-criterion vs Sec. 4.2: 0 judge at k_fix;
                               1 accept at the first k >= 2 whose eps_k <= eta */
-    int32_t pad_;
+    int32_t mst_method;    /* 0: exact MST (Sec. 3.2); 1: divide-and-conquer tree (Sec. 3.3) */
 } orc_params;
 
 typedef struct {
@@ -193,6 +193,213 @@ int orc_tree_levels(int n, const int *parent, int *level, int *order) {
     for (int v = 0; v < n; ++v) order[cnt[level[v]]++] = v;
     free(cnt);
     return root;
+}
+
+/* ---- Divide-and-conquer spanning tree (Sec. 3.3) ----
+ *
+ * The bodies are split into about sqrt(N) groups by an octree; each group's
+ * minimum spanning tree is found, and so is the minimum spanning tree of the
+ * meta-graph whose vertices are the groups and whose edge between two groups
+ * weighs as their lightest connecting edge (the cut property makes that edge
+ * the one to use).  The union of these edges is a spanning tree, rooted and
+ * walked like the exact one.
+ *
+ * READINGS (the octree is not specified):
+ *  - root cell: the axis-aligned cube with lower corner lo = the per-axis
+ *    minimum of the positions and side s = the largest per-axis extent; a
+ *    body's cell coordinates at the finest depth D = ORC_DC_DEPTH are
+ *    (int)((x_c - lo_c) * (2^D / s)), clamped to 2^D - 1 (s = 0: one group);
+ *  - a cell holding more than mcap bodies is split into its eight octants
+ *    unless it is at depth D; every non-empty unsplit cell is one group.
+ *    mcap = ceil(sqrt(N)) gives the ~sqrt(N) groups;
+ *  - groups are numbered depth first, octant (bx, by, bz) as 4 bx + 2 by + bz;
+ *  - the group trees and the meta-graph tree are the unique minimum spanning
+ *    trees under the strict edge order (w, min index, max index).  Pruning
+ *    edges by the cycle property before Prim only removes edges that no
+ *    minimum spanning tree contains, so it cannot change these trees; it is
+ *    left out here.
+ */
+#define ORC_DC_DEPTH 10
+
+/* Cell coordinates of every body at depth ORC_DC_DEPTH (3 ints per body). */
+static void dc_cells(int n, const double *x, int *cc) {
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) { lo[c] = x[c]; hi[c] = x[c]; }
+    for (int i = 1; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            if (x[3 * i + c] < lo[c]) lo[c] = x[3 * i + c];
+            if (x[3 * i + c] > hi[c]) hi[c] = x[3 * i + c];
+        }
+    double side = 0.0;
+    for (int c = 0; c < 3; ++c) if (hi[c] - lo[c] > side) side = hi[c] - lo[c];
+    const int top = (1 << ORC_DC_DEPTH) - 1;
+    const double inv = side > 0.0 ? (double)(1 << ORC_DC_DEPTH) / side : 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) {
+            int k = (int)((x[3 * i + c] - lo[c]) * inv);
+            cc[3 * i + c] = k > top ? top : k;
+        }
+}
+
+/* Octree split of the bodies in `mem` (ascending indices) at `level`: either
+ * one group, or the octants in order. */
+static int dc_split(const int *cc, const int *mem, int cnt, int level, int mcap, int *part, int *np) {
+    if (cnt <= mcap || level == ORC_DC_DEPTH) {
+        for (int k = 0; k < cnt; ++k) part[mem[k]] = *np;
+        (*np)++;
+        return ORC_OK;
+    }
+    int *sub = (int *)malloc(sizeof(int) * (size_t)cnt);
+    if (!sub) return ORC_E_NOMEM;
+    const int bit = ORC_DC_DEPTH - 1 - level;
+    int rc = ORC_OK;
+    for (int oct = 0; oct < 8 && !rc; ++oct) {
+        int m = 0;
+        for (int k = 0; k < cnt; ++k) {
+            const int *c = cc + 3 * mem[k];
+            int o = (((c[0] >> bit) & 1) << 2) | (((c[1] >> bit) & 1) << 1) | ((c[2] >> bit) & 1);
+            if (o == oct) sub[m++] = mem[k];
+        }
+        if (m > 0) rc = dc_split(cc, sub, m, level + 1, mcap, part, np);
+    }
+    free(sub);
+    return rc;
+}
+
+/* Prim's algorithm on the complete graph of the bodies mem[0..cnt) (strict
+ * order on the global indices); appends the cnt - 1 tree edges to (eu, ev). */
+static int dc_prim_group(const double *x, const int *mem, int cnt, int *eu, int *ev, int *ne) {
+    if (cnt < 2) return ORC_OK;
+    char *in = (char *)calloc((size_t)cnt, 1);
+    double *bw = (double *)malloc(sizeof(double) * (size_t)cnt);
+    int *bu = (int *)malloc(sizeof(int) * (size_t)cnt);
+    if (!in || !bw || !bu) { free(in); free(bw); free(bu); return ORC_E_NOMEM; }
+    in[0] = 1;
+    for (int k = 1; k < cnt; ++k) { bw[k] = edge_w(x + 3 * mem[0], x + 3 * mem[k]); bu[k] = mem[0]; }
+    for (int step = 1; step < cnt; ++step) {
+        int pick = -1;
+        for (int k = 0; k < cnt; ++k) {
+            if (in[k]) continue;
+            if (pick < 0 || key_less(bw[k], bu[k], mem[k], bw[pick], bu[pick], mem[pick])) pick = k;
+        }
+        in[pick] = 1;
+        eu[*ne] = bu[pick]; ev[*ne] = mem[pick]; (*ne)++;
+        for (int k = 0; k < cnt; ++k) {
+            if (in[k]) continue;
+            double w = edge_w(x + 3 * mem[pick], x + 3 * mem[k]);
+            if (key_less(w, mem[pick], mem[k], bw[k], bu[k], mem[k])) { bw[k] = w; bu[k] = mem[pick]; }
+        }
+    }
+    free(in); free(bw); free(bu);
+    return ORC_OK;
+}
+
+/* Divide-and-conquer spanning tree rooted at `root` (parents, levels and a
+ * parents-first order), with each body's group in part[] and the number of
+ * groups in *nparts.  mcap <= 0 means ceil(sqrt(n)). */
+int orc_mst_dc(int n, const double *x, int root, int mcap, int *parent, int *level, int *order, int *part,
+               int *nparts) {
+    if (n < 1 || root < 0 || root >= n) return ORC_E_INVAL;
+    if (mcap <= 0) mcap = (int)ceil(sqrt((double)n));
+    int *cc = (int *)malloc(sizeof(int) * 3 * (size_t)n), *all = (int *)malloc(sizeof(int) * (size_t)n);
+    int *eu = (int *)malloc(sizeof(int) * (size_t)n), *ev = (int *)malloc(sizeof(int) * (size_t)n);
+    int *mem = (int *)malloc(sizeof(int) * (size_t)n), *goff = (int *)calloc((size_t)n + 1, sizeof(int));
+    char *inT = (char *)calloc((size_t)n, 1);
+    double *bw = (double *)malloc(sizeof(double) * (size_t)n);
+    int *blo = (int *)malloc(sizeof(int) * (size_t)n), *bhi = (int *)malloc(sizeof(int) * (size_t)n);
+    int *adj = (int *)malloc(sizeof(int) * 2 * (size_t)n), *aoff = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *queue = (int *)malloc(sizeof(int) * (size_t)n);
+    int rc = ORC_OK, np = 0, ne = 0;
+    if (!cc || !all || !eu || !ev || !mem || !goff || !inT || !bw || !blo || !bhi || !adj || !aoff || !queue) {
+        rc = ORC_E_NOMEM;
+        goto out;
+    }
+    /* 1. octree groups */
+    dc_cells(n, x, cc);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    if ((rc = dc_split(cc, all, n, 0, mcap, part, &np))) goto out;
+    *nparts = np;
+    /* members of each group, ascending index */
+    for (int i = 0; i < n; ++i) goff[part[i] + 1]++;
+    for (int g = 0; g < np; ++g) goff[g + 1] += goff[g];
+    {
+        int *fill = (int *)malloc(sizeof(int) * (size_t)np);
+        if (!fill) { rc = ORC_E_NOMEM; goto out; }
+        for (int g = 0; g < np; ++g) fill[g] = goff[g];
+        for (int i = 0; i < n; ++i) mem[fill[part[i]]++] = i;
+        free(fill);
+    }
+    /* 2. each group's minimum spanning tree */
+    for (int g = 0; g < np && !rc; ++g) rc = dc_prim_group(x, mem + goff[g], goff[g + 1] - goff[g], eu, ev, &ne);
+    if (rc) goto out;
+    /* 3. Prim on the meta-graph: the weight of the meta edge (a, b) is the
+     * lightest edge between groups a and b, found when a joins the tree */
+    for (int g = 0; g < np; ++g) { bw[g] = INFINITY; blo[g] = -1; bhi[g] = -1; }
+    inT[0] = 1;
+    for (int added = 0, cur = 0; added < np - 1; ++added) {
+        for (int k = goff[cur]; k < goff[cur + 1]; ++k) {
+            const int u = mem[k];
+            for (int v = 0; v < n; ++v) {
+                const int g = part[v];
+                if (inT[g]) continue;
+                double w = edge_w(x + 3 * u, x + 3 * v);
+                int lo = u < v ? u : v, hi = u < v ? v : u;
+                if (blo[g] < 0 || key_less(w, lo, hi, bw[g], blo[g], bhi[g])) { bw[g] = w; blo[g] = lo; bhi[g] = hi; }
+            }
+        }
+        int pick = -1;
+        for (int g = 0; g < np; ++g) {
+            if (inT[g]) continue;
+            if (pick < 0 || key_less(bw[g], blo[g], bhi[g], bw[pick], blo[pick], bhi[pick])) pick = g;
+        }
+        inT[pick] = 1;
+        eu[ne] = blo[pick]; ev[ne] = bhi[pick]; ne++;
+        cur = pick;
+    }
+    /* 4. the union, oriented away from the root (breadth first) and walked */
+    for (int e = 0; e < ne; ++e) { aoff[eu[e] + 1]++; aoff[ev[e] + 1]++; }
+    for (int i = 0; i < n; ++i) aoff[i + 1] += aoff[i];
+    {
+        int *fill = (int *)malloc(sizeof(int) * (size_t)n);
+        if (!fill) { rc = ORC_E_NOMEM; goto out; }
+        for (int i = 0; i < n; ++i) fill[i] = aoff[i];
+        for (int e = 0; e < ne; ++e) { adj[fill[eu[e]]++] = ev[e]; adj[fill[ev[e]]++] = eu[e]; }
+        free(fill);
+    }
+    for (int i = 0; i < n; ++i) parent[i] = -2;
+    parent[root] = -1;
+    {
+        int head = 0, tail = 0;
+        queue[tail++] = root;
+        while (head < tail) {
+            const int u = queue[head++];
+            for (int k = aoff[u]; k < aoff[u + 1]; ++k) {
+                const int v = adj[k];
+                if (parent[v] != -2) continue;
+                parent[v] = u;
+                queue[tail++] = v;
+            }
+        }
+        if (tail != n) { rc = ORC_E_INVAL; goto out; }
+    }
+    if (orc_tree_levels(n, parent, level, order) != root) rc = ORC_E_INVAL;
+out:
+    free(cc); free(all); free(eu); free(ev); free(mem); free(goff); free(inT); free(bw); free(blo); free(bhi);
+    free(adj); free(aoff); free(queue);
+    return rc;
+}
+
+/* The tree builder of the driver: exact (Sec. 3.2) or divide-and-conquer (Sec. 3.3). */
+static int build_tree(int n, const double *x, int root, const orc_params *p, int *parent, int *level,
+                      int *order) {
+    if (p && p->mst_method == 1) {
+        int *part = (int *)malloc(sizeof(int) * (size_t)n), np = 0;
+        if (!part) return ORC_E_NOMEM;
+        int rc = orc_mst_dc(n, x, root, 0, parent, level, order, part, &np);
+        free(part);
+        return rc;
+    }
+    return orc_mst_prim(n, x, root, parent, level, order);
 }
 
 /* Deconstruction (Sec. 2.2 / 3.4): original-frame positions relative to the
@@ -874,12 +1081,21 @@ int orc_neville_export(int kf, int L, const double *tab, double *diag) {
 
 /* Build the MST state from Cartesian x, v (Sec. 3.2, 3.4): root nearest the
  * COM, Prim tree, edge vectors X_v = x_v - x_parent, V_v likewise. */
+static int build_state_p(int n, const double *m, const double *x, const double *v, const orc_params *p,
+                         int *parent, double *X, double *V, double *scal);
+
 int orc_build_state(int n, const double *m, const double *x, const double *v,
                     int *parent, double *X, double *V, double *scal) {
+    return build_state_p(n, m, x, v, NULL, parent, X, V, scal);
+}
+
+/* orc_build_state with the tree builder of params p (NULL: exact). */
+static int build_state_p(int n, const double *m, const double *x, const double *v, const orc_params *p,
+                         int *parent, double *X, double *V, double *scal) {
     int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
     if (!level || !order) { free(level); free(order); return ORC_E_NOMEM; }
     int root = orc_root_nearest_com(n, m, x);
-    int rc = orc_mst_prim(n, x, root, parent, level, order);
+    int rc = build_tree(n, x, root, p, parent, level, order);
     if (!rc) {
         for (int c = 0; c < 3; ++c) { X[3 * root + c] = 0.0; V[3 * root + c] = 0.0; }
         for (int u = 0; u < n; ++u) {
@@ -940,7 +1156,7 @@ static int rebuild(ostate *y, const orc_params *p, oscratch *s, int *topo_change
     orc_deconstruct(n, y->parent, y->order, y->X, s->rho);
     orc_deconstruct(n, y->parent, y->order, y->V, s->ups);
     int root = orc_root_nearest_com(n, y->m, s->rho);
-    int rc = orc_mst_prim(n, s->rho, root, np, nl, no);
+    int rc = build_tree(n, s->rho, root, p, np, nl, no);
     if (rc) goto out;
     int changed = 0;
     for (int u = 0; u < n; ++u) if (np[u] != y->parent[u]) { changed = 1; break; }
@@ -1030,7 +1246,7 @@ static int integrate_impl(int n, const double *m, double *x, double *v, double t
     int rc = scratch_alloc(&s, n);
     if (!rc && (!parent || !level || !order || !X || !V)) rc = ORC_E_NOMEM;
     if (rc) goto out;
-    rc = orc_build_state(n, m, x, v, parent, X, V, scal);
+    rc = build_state_p(n, m, x, v, p, parent, X, V, scal);
     if (rc) goto out;
     ostate y;
     make_state(&y, n, m, parent, level, order, X, V, scal);
@@ -1242,7 +1458,7 @@ int orc_replay(int n, const double *m, double *x, double *v, double t0, int64_t 
     if (!rc && (!parent || !level || !order || !X || !V)) rc = ORC_E_NOMEM;
     if (rc) goto out;
     if (parents) memcpy(parent, parents, sizeof(int) * (size_t)n);
-    else if ((rc = orc_mst_prim(n, x, orc_root_nearest_com(n, m, x), parent, level, order))) goto out;
+    else if ((rc = build_tree(n, x, orc_root_nearest_com(n, m, x), p, parent, level, order))) goto out;
     if (orc_tree_levels(n, parent, level, order) < 0) { rc = ORC_E_INVAL; goto out; }
     for (int u = 0; u < n; ++u) {
         int q = parent[u];
