@@ -320,6 +320,65 @@ def _energy(m, x, v, block=1024):
     return e
 
 
+def bench_mst(M, ctx, names=("plummer5000_binary", "plummer10000_binary"), steps=20, builds=10):
+    """Exact (Sec. 3.2) against divide-and-conquer (Sec. 3.3) spanning trees:
+    the tree builders alone on the warmed-up state (device arrays, `builds`
+    calls each), the tree length, and `steps` GBS step attempts from the same
+    warmed-up state with each builder (a rebuild before every attempt after
+    an accepted step, as in the headline measurement)."""
+    import numpy as np
+    import torch
+    import ics
+    out = {}
+    allow = (M.OK, M.W_TIME_TOL, M.E_MAXSTEPS)
+    for name in names:
+        m, x, v, wl = ics.workload(name)
+        base = dict(eta=wl["eta"], k_fix=8, n_d=2)
+        xw, vw, t1, h1, att = x, v, 0.0, 0.0, 0
+        for _ in range(100):   # steady state, as the headline measurement
+            xw, vw, rc, stw = ctx.integrate(m, xw, vw, t1, wl["t_end"], M.params(max_steps=10, h_init=h1, **base),
+                                            allow=allow)
+            att += stw["steps_accepted"] + stw["steps_rejected"]
+            t1, h1 = stw["t_reached"], stw["h_next"]
+            if att >= 25 and stw["steps_accepted"] >= 8:
+                break
+        mt, xt = torch.tensor(m, device="cuda"), torch.tensor(xw, device="cuda")
+        res = {"n_bodies": len(m)}
+        for kind, dc in (("exact", False), ("dc", True)):
+            parent, _, _ = ctx.mst_build(mt, xt, dc=dc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(builds):
+                parent, _, _ = ctx.mst_build(mt, xt, dc=dc)
+            torch.cuda.synchronize()
+            build_ms = (time.perf_counter() - t0) * 1e3 / builds
+            pa = parent.cpu().numpy()
+            d = xw - xw[np.where(pa >= 0, pa, np.arange(len(pa)))]
+            length = float(np.sqrt((d * d).sum(1)).sum())
+            p = M.params(max_steps=steps, h_init=h1, **base)
+            if dc:
+                p.flags |= M.MST_DC
+            vt = torch.tensor(vw, device="cuda")
+            ctx.integrate(mt, xt, vt, t1, wl["t_end"], p, allow=allow)   # graph capture, untimed
+            vt = torch.tensor(vw, device="cuda")
+            xs = torch.tensor(xw, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, rc, st = ctx.integrate(mt, xs, vt, t1, wl["t_end"], p, allow=allow)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            att = st["steps_accepted"] + st["steps_rejected"]
+            res[kind] = {"build_ms": build_ms, "tree_length": length, "ms_per_attempt": wall * 1e3 / att,
+                         "attempts": att, "accepted": st["steps_accepted"], "rebuilds": st["mst_rebuilds"]}
+        res["dc_tree_excess"] = res["dc"]["tree_length"] / res["exact"]["tree_length"] - 1.0
+        res["dc_step_saving"] = 1.0 - res["dc"]["ms_per_attempt"] / res["exact"]["ms_per_attempt"]
+        out[name] = res
+        print(f"[bench] mst {name}: build exact {res['exact']['build_ms']:.3f} ms dc {res['dc']['build_ms']:.3f} ms; "
+              f"ms/attempt exact {res['exact']['ms_per_attempt']:.3f} dc {res['dc']['ms_per_attempt']:.3f}; "
+              f"tree +{res['dc_tree_excess'] * 100:.1f} %", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_timing(M, ctx, sizes=None, seeds=3, eta=1e-6, sweep_n=1129, sweep_etas=None, do_cpu=True):
     """The N-body timing tests of Sec. 5.4 on one GPU: equal-mass Hernquist
     clusters without hard binaries (M = 1e7 Msun, r_half = 10 pc), integrated
@@ -392,6 +451,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-systems measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the batched small-systems measurement")
+    ap.add_argument("--mst-only", action="store_true",
+                    help="only exact vs divide-and-conquer spanning trees (Sec. 3.2 vs 3.3) at N = 5002 and 10002")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement")
     ap.add_argument("--rebuild-only", action="store_true",
@@ -433,6 +494,9 @@ def main():
     if args.timing_only:
         sizes = [k for k in ics.timing_sizes() if k <= args.timing_max_n]
         print(json.dumps({"timing": bench_timing(M, ctx, sizes, do_cpu=not args.no_cpu)}), flush=True)
+        return
+    if args.mst_only:
+        print(json.dumps({"mst": bench_mst(M, ctx)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)

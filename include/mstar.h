@@ -52,6 +52,11 @@ extern "C" {
 #define MSTAR_EAGER 2u         /* mstar_integrate*: launch each GBS step attempt's kernels from
                                   the host instead of replaying the attempt as a captured HIP
                                   graph (same kernels, same order, identical results) */
+#define MSTAR_MST_DC 4u        /* mstar_mst_build and the single-system integrators: build every
+                                  spanning tree by the divide-and-conquer method of Sec. 3.3
+                                  (octree groups of at most ceil(sqrt(N)) bodies, the minimum
+                                  spanning tree of each group and of the meta-graph of groups)
+                                  instead of the exact MST.  Ignored by the batched integrator. */
 
 /* Parameters of the method.  struct_size must be sizeof(mstar_params);
  * mstar_params_default fills every field. */
@@ -170,7 +175,14 @@ int mstar_integrate_ext(mstar_ctx *ctx, const mstar_params *params, int64_t n, c
  * index), rooted at the body nearest the centre of mass of masses m (ties to
  * the lowest index), or at `root_in` if 0 <= root_in < n.  Outputs parent[n]
  * (root -1), level[n] (root 0) and *root_out.  Host or device pointers per
- * `flags`. */
+ * `flags`.  With MSTAR_MST_DC in `flags` the tree is the divide-and-conquer
+ * spanning tree of Sec. 3.3 instead (same root rule): the bounding cube of x
+ * (lower corner the per-axis minimum, side the largest extent) is split as an
+ * octree, each cell holding more than ceil(sqrt(n)) bodies into its octants
+ * down to 10 levels, every non-empty unsplit cell is a group, and the tree is
+ * the union of each group's MST and of the MST of the meta-graph whose edge
+ * between two groups is their lightest connecting edge (all under the strict
+ * order above). */
 int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, const double *x,
                     int32_t root_in, int32_t *parent, int32_t *level, int32_t *root_out);
 

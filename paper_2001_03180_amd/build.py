@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmstar.so")
 SOURCES = ["api.hip", "kernels_force.hip", "kernels_step.hip", "kernels_tree.hip", "kernels_batch.hip",
-           "kernels_adjoint.hip", "kernels_probe.hip", "kernels_rebuild.hip", "noalloc.hip"]
+           "kernels_adjoint.hip", "kernels_probe.hip", "kernels_rebuild.hip", "kernels_dc.hip", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 

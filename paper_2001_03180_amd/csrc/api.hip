@@ -86,6 +86,8 @@ struct mstar_ctx {
     int mut_wps = 3;                   // waves per SIMD the mutual kernel's work is split for
     int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
     int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
+    DcBuf dc{};                        // divide-and-conquer tree builder buffers
+    int dc_cap_n = 0;                  // N they are sized for (0: none)
     bool ext_on = false;               // an external field applies to the running integration
     ExtField h_ext{};                  // host copy of that field
     // frozen-controller replay and adjoint (kernels_adjoint.hip)
@@ -167,6 +169,8 @@ void free_workspace(mstar_ctx *ctx) {
     ctx->d = Dev{};
     ctx->cap_n = 0;
     ctx->mut_cap_n = 0;
+    ctx->dc = DcBuf{};
+    ctx->dc_cap_n = 0;
 }
 
 int ensure(mstar_ctx *ctx, int n) {
@@ -602,11 +606,39 @@ int mst_max_rounds(const Dev &d) {
     return maxr;
 }
 
-int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in) {
+// Buffers of the divide-and-conquer builder, sized for the workspace's
+// capacity on first use (freed with the workspace).
+int ensure_dc(mstar_ctx *ctx) {
+    if (ctx->dc_cap_n >= ctx->cap_n && ctx->dc_cap_n > 0) return MSTAR_OK;
+    const size_t N = (size_t)ctx->cap_n;
+    DcBuf b{};
+    int rc = 0;
+    if ((rc = dalloc(ctx, &b.key, 2 * N)) || (rc = dalloc(ctx, &b.idx, 2 * N)) || (rc = dalloc(ctx, &b.flag, N + 1)) ||
+        (rc = dalloc(ctx, &b.cells, 2 * N)) || (rc = dalloc(ctx, &b.pstart, N + 1)) || (rc = dalloc(ctx, &b.part, N)) ||
+        (rc = dalloc(ctx, &b.spos, N)) || (rc = dalloc(ctx, &b.bw, N)) || (rc = dalloc(ctx, &b.bu, N)) ||
+        (rc = dalloc(ctx, &b.in, N)) || (rc = dalloc(ctx, &b.np, 1)))
+        return rc;
+    ctx->dc = b;
+    ctx->dc_cap_n = ctx->cap_n;
+    return MSTAR_OK;
+}
+
+// Groups of the divide-and-conquer builder hold at most ceil(sqrt(N)) bodies.
+int dc_mcap(int n) { return (int)std::ceil(std::sqrt((double)n)); }
+
+// The spanning tree on positions pos: the exact MST (Sec. 3.2) or, with dc,
+// the divide-and-conquer tree of Sec. 3.3 (its parts are the components the
+// Boruvka rounds start from).
+int build_mst(mstar_ctx *ctx, const d4 *pos, int root_in, bool dc = false) {
     const Dev &d = ctx->d;
     const int maxr = mst_max_rounds(d);
     const int ns = mst_splits(d);
+    if (dc) {
+        int rc = ensure_dc(ctx);
+        if (rc) return rc;
+    }
     launch_mst_init(d, ctx->stream, pos, root_in);
+    if (dc) launch_mst_dc(d, ctx->dc, ctx->stream, pos, dc_mcap(d.n));
     int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est, maxr) : maxr - 2;
     launch_mst_rounds(d, ctx->stream, pos, est, ns);
     for (int extra = 0;; ++extra) {
@@ -629,7 +661,7 @@ int rebuild(mstar_ctx *ctx, const mstar_params *p) {
     const Dev &d = ctx->d;
     const d4 *pos = d.P + (size_t)kBase * d.n;
     const d4 *vel = d.Vt + (size_t)kBase * d.n;
-    int rc = build_mst(ctx, pos, -1);
+    int rc = build_mst(ctx, pos, -1, (p->flags & MSTAR_MST_DC) != 0);
     if (rc) return rc;
     launch_rebuild_edges(d, ctx->stream, pos, vel, p->n_d);
     HIPCK(hipGetLastError());
@@ -648,6 +680,11 @@ int rebuild_queued(mstar_ctx *ctx, const mstar_params *p) {
     const int maxr = mst_max_rounds(d);
     const int est = ctx->mst_rounds_est > 0 ? std::min(ctx->mst_rounds_est + ctx->mst_spare, maxr) : maxr;
     launch_mst_init(d, ctx->stream, pos, -1);
+    if (p->flags & MSTAR_MST_DC) {
+        int rc = ensure_dc(ctx);
+        if (rc) return rc;
+        launch_mst_dc(d, ctx->dc, ctx->stream, pos, dc_mcap(d.n));
+    }
     launch_mst_rounds(d, ctx->stream, pos, est, mst_splits(d));
     launch_mst_root(d, ctx->stream);
     launch_rebuild_edges(d, ctx->stream, pos, vel, p->n_d);
@@ -909,7 +946,8 @@ int mstar_mst_build(mstar_ctx *ctx, uint32_t flags, int64_t n, const double *m, 
     if ((rc = in_dev(ctx, flags, x, ctx->xin, sizeof(double) * 3 * n, &xd))) return rc;
     const Dev &d = ctx->d;
     launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
-    if ((rc = build_mst(ctx, d.tsA, (root_in >= 0 && root_in < n) ? root_in : -1))) return rc;
+    if ((rc = build_mst(ctx, d.tsA, (root_in >= 0 && root_in < n) ? root_in : -1, (flags & MSTAR_MST_DC) != 0)))
+        return rc;
     launch_tree_finish(d, ctx->stream);
     HIPCK(hipGetLastError());
     if ((rc = out_copy(ctx, flags, parent, d.parent, sizeof(int32_t) * n))) return rc;
@@ -1094,10 +1132,15 @@ int prepare_step(mstar_ctx *ctx, const mstar_params *p, bool rebuild_due, bool r
         return prepare_start(ctx, p, resync, true, nforce);
     }
     const double kd[] = {p->G, p->alpha, p->beta, p->gamma};
-    const int ki[] = {p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, ctx->mst_rounds_est, ctx->mst_spare};
+    const int ki[] = {p->n_d, ctx->d.n, ctx->ws_gen, ctx->ext_on ? 1 : 0, ctx->mst_rounds_est, ctx->mst_spare,
+                      (p->flags & MSTAR_MST_DC) ? 1 : 0};
     std::string key((const char *)kd, sizeof kd);
     key.append((const char *)ki, sizeof ki);
     (void)force_cap(ctx, p->n_d);
+    if (p->flags & MSTAR_MST_DC) {   // allocate outside the capture
+        int rc = ensure_dc(ctx);
+        if (rc) return rc;
+    }
     int rc = replay_graph(ctx, ctx->r_exec, ctx->r_key, key, [&]() {
         int r = rebuild_queued(ctx, p);
         return r ? r : prepare_start(ctx, p, false, true, nullptr);
@@ -1155,7 +1198,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     if ((rc = in_dev(ctx, flags, v, ctx->vin, sizeof(double) * 3 * n, &vd))) return rc;
     // initial MST on the Cartesian positions, edge vectors, COM
     launch_pack3(ctx->stream, (const double *)xd, nullptr, d.tsA, (int)n);
-    if ((rc = build_mst(ctx, d.tsA, -1))) return rc;
+    if ((rc = build_mst(ctx, d.tsA, -1, (flags & MSTAR_MST_DC) != 0))) return rc;
     launch_tree_finish(d, ctx->stream);
     launch_set_sys(d, ctx->stream, t0, 0.0, 0.0, nullptr, nullptr, 0);
     launch_state_from_cartesian(d, ctx->stream, (const double *)xd, (const double *)vd);

@@ -191,6 +191,23 @@ struct Dev {
 //  steps, one per wave.  A wave leaves one i-side partial per row it touches
 //  and one j-side partial per j-block; a j-block cut between two waves leaves
 //  two (pieces 0 and 1).  Every partial is written exactly once per launch.
+// Buffers of the divide-and-conquer tree builder (Sec. 3.3); n = capacity.
+struct DcBuf {
+    uint32_t *key;              // [2n] Morton keys (two radix-sort buffers)
+    int32_t *idx;               // [2n] body of each key
+    int32_t *flag;              // [n + 1] part starts over sorted positions
+    int2 *cells;                // [2n] octree cell ranges of two levels
+    int32_t *pstart;            // [n + 1] first sorted position of each part
+    int32_t *part;              // [n] part of each body
+    d4 *spos;                   // [n] positions in sorted order
+    double *bw;                 // [n] Prim of a large part: lightest edge into the part tree
+    int32_t *bu;                // [n] its tree end
+    int32_t *in;                // [n] in the part tree
+    int32_t *np;                // number of parts
+};
+// Partition and part trees; the Boruvka rounds of the exact builder finish the tree.
+void launch_mst_dc(const Dev &d, const DcBuf &b, hipStream_t s, const d4 *pos, int mcap);
+
 struct FLay {
     int mut;
     int nparts;                 // mut = 0

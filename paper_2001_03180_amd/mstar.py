@@ -21,6 +21,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_COINCIDENT, E_NOCONV, E_MAXSTEPS,
 W_TIME_TOL = 1
 DEVICE_PTRS = 1
 EAGER = 2
+MST_DC = 4          # divide-and-conquer spanning trees (Sec. 3.3) instead of the exact MST
 
 
 class Params(C.Structure):
@@ -248,8 +249,9 @@ class Context:
         return rc
 
     # ---------------------------------------------------------------- calls
-    def mst_build(self, m, x, root_in=-1):
-        """MST of positions x rooted near the COM: (parent, level, root)."""
+    def mst_build(self, m, x, root_in=-1, dc=False):
+        """MST of positions x rooted near the COM (dc: the divide-and-conquer
+        tree of Sec. 3.3): (parent, level, root)."""
         n = len(m)
         M, X = _Arg(m, np.float64, (n,)), _Arg(x, np.float64, (n, 3))
         flags = _mode(M, X)
@@ -262,7 +264,8 @@ class Context:
             parent, level, root = (np.empty(n, np.int32), np.empty(n, np.int32), np.empty(1, np.int32))
         P, L, R = (_Arg(parent, np.int32, writable=True), _Arg(level, np.int32, writable=True),
                    _Arg(root, np.int32, writable=True))
-        self._check(lib().mstar_mst_build(self._h, flags, n, M.ptr, X.ptr, int(root_in), P.ptr, L.ptr, R.ptr))
+        self._check(lib().mstar_mst_build(self._h, flags | (MST_DC if dc else 0), n, M.ptr, X.ptr, int(root_in),
+                                          P.ptr, L.ptr, R.ptr))
         return parent, level, int(root[0])
 
     def force(self, m, rho, parent, X, p: Params | None = None, omega: bool = False):
