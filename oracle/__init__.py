@@ -95,6 +95,7 @@ def lib():
             "orc_integrate_rec": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_double, P, C.POINTER(Stats),
                                             C.c_int64, D, I, I64]),
             "orc_replay": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, I, P, D, D]),
+            "orc_rebuild_state": (C.c_int, [C.c_int, D, I, D, D, D, P, I]),
             "orc_force_tlm": (C.c_int, [C.c_int, D, D, C.c_double, C.c_int, D, D, D, D, D, C.c_int]),
             "orc_lagrange_weights": (None, [C.c_int, D]),
             "orc_replay_tlm": (C.c_int, [C.c_int, D, D, D, C.c_double, C.c_int64, D, P, C.c_int, D, D, D, D]),
@@ -390,6 +391,20 @@ def replay(m, x, v, t0, H, parents, p: Params | None = None, times=False):
     _check(lib().orc_replay(len(m), pm, _d(x)[1], _d(v)[1], float(t0), len(H), _d(H)[1], pp, C.byref(p),
                             C.byref(t), _d(ts)[1] if times else None), "replay")
     return (x, v, t.value, ts) if times else (x, v, t.value)
+
+
+def rebuild_state(m, parent, X, V, scal, p: Params | None = None):
+    """The driver's rebuild (Sec. 3.5) of the state (parent, X, V, scal):
+    (new parent, new X, new V, changed)."""
+    p = p or params()
+    m, pm = _d(m)
+    parent = np.array(parent, dtype=np.int32)
+    X = np.array(X, dtype=np.float64, order="C"); V = np.array(V, dtype=np.float64, order="C")
+    ch = np.zeros(1, dtype=np.int32)
+    _check(lib().orc_rebuild_state(len(m), pm, parent.ctypes.data_as(C.POINTER(C.c_int32)), _d(X)[1], _d(V)[1],
+                                   _d(scal)[1], C.byref(p), ch.ctypes.data_as(C.POINTER(C.c_int32))),
+           "rebuild_state")
+    return parent, X, V, bool(ch[0])
 
 
 def force_tlm(m, r, dr, G=1.0, nthreads=0):

@@ -1179,6 +1179,23 @@ out:
     return rc;
 }
 
+/* The driver's rebuild (Sec. 3.5) applied to a given state, exported for the
+ * tests of the new-edge rule: parent, X and V (edge rows) are replaced by the
+ * new tree's and *changed tells whether the tree changed. */
+int orc_rebuild_state(int n, const double *m, int *parent, double *X, double *V, const double *scal,
+                      const orc_params *p, int *changed) {
+    int *level = (int *)malloc(sizeof(int) * (size_t)n), *order = (int *)malloc(sizeof(int) * (size_t)n);
+    oscratch s;
+    int rc = scratch_alloc(&s, n);
+    if (!rc && (!level || !order)) rc = ORC_E_NOMEM;
+    ostate y;
+    if (!rc) rc = make_state(&y, n, m, parent, level, order, X, V, scal);
+    if (!rc) rc = rebuild(&y, p, &s, changed);
+    scratch_free(&s);
+    free(level); free(order);
+    return rc;
+}
+
 static int all_finite(int k, const double *a) {
     for (int i = 0; i < k; ++i) if (!isfinite(a[i])) return 0;
     return 1;
