@@ -253,17 +253,19 @@ def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
 def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
     """Coordinate round trips of Sec. 3.5: `seeds` equal-mass Hernquist clusters
     of N = 379, each with the MST and with the chain, n_cycles build /
-    deconstruct cycles in one call per stretch (all 2 * seeds systems side by
-    side); the energy error of every system after each stretch."""
+    deconstruct cycles in one call per stretch (all systems side by side),
+    once with compensated centre-of-mass sums and once with plain ones (the
+    paper's test; kinds 2 and 3); the energy error of every system after each
+    stretch."""
     import math
     import numpy as np
     import ics
     sys_ = [ics.hernquist(n, seed) for seed in range(1, seeds + 1)]
-    off = np.cumsum([0] + [n] * (2 * seeds))
-    m = np.concatenate([s[0] for s in sys_] * 2)
-    x = np.concatenate([s[1] for s in sys_] * 2)
-    v = np.concatenate([s[2] for s in sys_] * 2)
-    kinds = [0] * seeds + [1] * seeds
+    off = np.cumsum([0] + [n] * (4 * seeds))
+    m = np.concatenate([s[0] for s in sys_] * 4)
+    x = np.concatenate([s[1] for s in sys_] * 4)
+    v = np.concatenate([s[2] for s in sys_] * 4)
+    kinds = [0] * seeds + [1] * seeds + [2] * seeds + [3] * seeds
 
     def energy(s, xx, vv):
         """E = T - U with every term summed exactly rounded (math.fsum)."""
@@ -275,7 +277,7 @@ def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
             terms.extend(-(ms[i] * ms[i + 1:]) / np.sqrt((d * d).sum(1)))
         return math.fsum(terms)
 
-    E0 = [energy(s, x, v) for s in range(2 * seeds)]
+    E0 = [energy(s, x, v) for s in range(4 * seeds)]
     marks = [c for c in (300, 1000, 3000, 10000, 30000, 100000) if c < n_cycles] + [n_cycles]
     curve, done, gpu_s, levels = [], 0, 0.0, None
     xc, vc = x.copy(), v.copy()
@@ -285,11 +287,15 @@ def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
         gpu_s += time.perf_counter() - t0
         xc, vc, done = xs[0].copy(), vs[0].copy(), c
         levels = ml if levels is None else levels
-        err = [abs(energy(s, xc, vc) - E0[s]) / abs(E0[s]) for s in range(2 * seeds)]
-        curve.append({"cycles": c, "mst_mean": float(np.mean(err[:seeds])), "mst_sd": float(np.std(err[:seeds])),
-                      "chain_mean": float(np.mean(err[seeds:])), "chain_sd": float(np.std(err[seeds:]))})
-        print(f"[bench] rebuild {c} cycles: MST |dE/E| {curve[-1]['mst_mean']:.3e}, chain "
-              f"{curve[-1]['chain_mean']:.3e} ({gpu_s:.1f} s)", file=sys.stderr, flush=True)
+        err = [abs(energy(s, xc, vc) - E0[s]) / abs(E0[s]) for s in range(4 * seeds)]
+        q = lambda k: err[k * seeds:(k + 1) * seeds]
+        curve.append({"cycles": c, "mst_mean": float(np.mean(q(0))), "mst_sd": float(np.std(q(0))),
+                      "chain_mean": float(np.mean(q(1))), "chain_sd": float(np.std(q(1))),
+                      "plain_mst_mean": float(np.mean(q(2))), "plain_mst_sd": float(np.std(q(2))),
+                      "plain_chain_mean": float(np.mean(q(3))), "plain_chain_sd": float(np.std(q(3)))})
+        print(f"[bench] rebuild {c} cycles: compensated sums MST |dE/E| {curve[-1]['mst_mean']:.3e}, chain "
+              f"{curve[-1]['chain_mean']:.3e}; plain sums MST {curve[-1]['plain_mst_mean']:.3e}, chain "
+              f"{curve[-1]['plain_chain_mean']:.3e} ({gpu_s:.1f} s)", file=sys.stderr, flush=True)
     # CPU baseline: the oracle on a bounded sample, one system, both structures, 200 cycles
     import oracle as orc
     t0 = time.perf_counter()
@@ -298,11 +304,12 @@ def bench_rebuild(M, ctx, n_cycles=100000, seeds=10, n=379):
     cpu_s = time.perf_counter() - t0
     return {
         "workload": f"{seeds} equal-mass Hernquist clusters, N={n}, r_half=1 (seeds 1..{seeds}), each with the "
-                    f"MST and with the chain; {n_cycles} build/deconstruct cycles",
-        "mean_level_mst": float(np.mean(levels[:seeds])), "mean_level_chain": float(np.mean(levels[seeds:])),
+                    f"MST and with the chain, with compensated and with plain centre-of-mass sums; {n_cycles} "
+                    "build/deconstruct cycles",
+        "mean_level_mst": float(np.mean(levels[:seeds])), "mean_level_chain": float(np.mean(levels[seeds:2 * seeds])),
         "curve": curve,
         "gpu_s": gpu_s,
-        "round_trips_per_s": 2 * seeds * n_cycles / gpu_s,
+        "round_trips_per_s": 4 * seeds * n_cycles / gpu_s,
         "cpu_oracle": {"round_trips_per_s": 400 / cpu_s, "cores": 1, "kind": "oracle",
                        "sample": "one cluster, MST and chain, 200 cycles each"},
     }

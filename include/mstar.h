@@ -257,7 +257,10 @@ int mstar_profile_read_kernel(mstar_ctx *ctx, int32_t kind, int64_t *launches, d
  * end joins there; edges compared under the strict order of the MST, the
  * lower-indexed end of the first edge is the first tail) -- form the edge
  * vectors and the centre of mass, and rebuild x, v from them (x = r_cm +
- * (rho - rho_bar), rho the root-relative path sums).  The inputs x, v
+ * (rho - rho_bar), rho the root-relative path sums).  Centre-of-mass sums
+ * are compensated (Neumaier); kinds 2 and 3 are kinds 0 and 1 with plain
+ * sums in index order instead (the paper's test, Sec. 3.5, does not
+ * compensate).  The inputs x, v
  * ([n_tot][3]) are not modified; after cycle (k+1) n_cycles / n_out the state
  * is written to x_out[k], v_out[k] ([n_out][n_tot][3]).  mean_level (host,
  * nullable, [n_sys]) receives the structure's mean body level averaged over

@@ -169,7 +169,8 @@ def chain(x):
 
 def rebuild_cycles(m, x, v, kind, n_cycles, n_out):
     """Sec. 3.5 rebuild test: n_cycles build / deconstruct round trips (kind 0
-    MST, 1 chain).  Returns the states after cycles (k+1) n_cycles / n_out,
+    MST, 1 chain; + 2: plain centre-of-mass sums in index order instead of
+    compensated ones).  Returns the states after cycles (k+1) n_cycles / n_out,
     shape [n_out, n, 3] each, and the mean level of the structure averaged
     over the cycles."""
     m, pm = _d(m)

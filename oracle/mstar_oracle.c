@@ -93,6 +93,16 @@ static void com3(int n, const double *m, const double *x, double out[3]) {
     for (int k = 0; k < 3; ++k) out[k] = ns_get(&s[k]) / Mt;
 }
 
+/* The same with plain sums in index order (no compensation). */
+static void com3_plain(int n, const double *m, const double *x, double out[3]) {
+    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n; ++i) {
+        M = M + m[i];
+        for (int k = 0; k < 3; ++k) s[k] = s[k] + m[i] * x[3 * i + k];
+    }
+    for (int k = 0; k < 3; ++k) out[k] = s[k] / M;
+}
+
 /* Squared edge length used as the MST weight (Sec. 3.1 weights by Euclidean
  * length; READING: the square, which orders edges identically, evaluated as
  * (dx*dx + dy*dy) + dz*dz with d = x_j - x_i, so w_ij = w_ji bit for bit). */
@@ -1842,26 +1852,33 @@ int orc_chain_build(int n, const double *x, int *parent, int *level, int *order)
  * from the Cartesian state (kind 0: MST rooted at the body nearest the centre of
  * mass, Sec. 3.2; kind 1: the chain above), form the edge vectors
  * X_v = x_v - x_parent(v), V_v likewise and the centre of mass, and deconstruct
- * back to Cartesian coordinates (orc_state_to_cartesian).  The physical state
+ * back to Cartesian coordinates, x = r_cm + (rho - rho_bar).  Centre-of-mass
+ * sums are compensated (Neumaier) unless kind has bit 2 set (kinds 2, 3):
+ * then they are plain sums in index order, as the paper's test has them (Sec.
+ * 3.5 leaves compensated summation for future work).  The physical state
  * does not change; only rounding accumulates.  x, v are updated in place; after
  * cycle (k+1) n_cycles / n_out (k < n_out) the state is copied to
  * xs[k], vs[k] ([n_out][n][3]).  levels_sum (nullable) receives the sum over
  * cycles of the mean level of the structure. */
 int orc_rebuild_cycles(int n, const double *m, double *x, double *v, int kind, int64_t n_cycles, int n_out,
                        double *xs, double *vs, double *levels_sum) {
-    if (n < 2 || (kind != 0 && kind != 1) || n_cycles < 0 || n_out < 0 || (n_out > 0 && (!xs || !vs)))
+    if (n < 2 || kind < 0 || kind > 3 || n_cycles < 0 || n_out < 0 || (n_out > 0 && (!xs || !vs)))
         return ORC_E_INVAL;
+    const int chain = kind & 1, plain = (kind & 2) != 0;
+    void (*com)(int, const double *, const double *, double *) = plain ? com3_plain : com3;
+    double *rho = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!rho) return ORC_E_NOMEM;
     int *parent = (int *)malloc(sizeof(int) * (size_t)n), *level = (int *)malloc(sizeof(int) * (size_t)n);
     int *order = (int *)malloc(sizeof(int) * (size_t)n);
     double *X = (double *)malloc(sizeof(double) * 3 * (size_t)n), *V = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     if (!parent || !level || !order || !X || !V) {
-        free(parent); free(level); free(order); free(X); free(V);
+        free(parent); free(level); free(order); free(X); free(V); free(rho);
         return ORC_E_NOMEM;
     }
     int rc = ORC_OK, k = 0;
     double lsum = 0.0;
     for (int64_t cyc = 1; cyc <= n_cycles && !rc; ++cyc) {
-        if (kind == 0) rc = orc_mst_prim(n, x, orc_root_nearest_com(n, m, x), parent, level, order);
+        if (!chain) rc = orc_mst_prim(n, x, orc_root_nearest_com(n, m, x), parent, level, order);
         else rc = orc_chain_build(n, x, parent, level, order);
         if (rc) break;
         double ls = 0.0;
@@ -1875,10 +1892,17 @@ int orc_rebuild_cycles(int n, const double *m, double *x, double *v, int kind, i
                 V[3 * u + c] = q < 0 ? 0.0 : v[3 * u + c] - v[3 * q + c];
             }
         }
-        com3(n, m, x, scal + 3);
-        com3(n, m, v, scal + 6);
-        scal[0] = scal[1] = scal[2] = 0.0;
-        rc = orc_state_to_cartesian(n, m, parent, X, V, scal, x, v);
+        com(n, m, x, scal + 3);
+        com(n, m, v, scal + 6);
+        /* x = r_cm + (rho - rho_bar), v alike (rho: top-down path sums) */
+        for (int pass = 0; pass < 2; ++pass) {
+            double c[3];
+            orc_deconstruct(n, parent, order, pass ? V : X, rho);
+            com(n, m, rho, c);
+            double *out = pass ? v : x;
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < 3; ++k) out[3 * i + k] = scal[(pass ? 6 : 3) + k] + (rho[3 * i + k] - c[k]);
+        }
         while (!rc && k < n_out && cyc == ((int64_t)(k + 1) * n_cycles) / n_out) {
             memcpy(xs + (size_t)k * 3 * n, x, sizeof(double) * 3 * (size_t)n);
             memcpy(vs + (size_t)k * 3 * n, v, sizeof(double) * 3 * (size_t)n);
@@ -1886,6 +1910,6 @@ int orc_rebuild_cycles(int n, const double *m, double *x, double *v, int kind, i
         }
     }
     if (levels_sum) *levels_sum = lsum;
-    free(parent); free(level); free(order); free(X); free(V);
+    free(parent); free(level); free(order); free(X); free(V); free(rho);
     return rc;
 }

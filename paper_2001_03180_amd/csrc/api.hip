@@ -1937,7 +1937,7 @@ extern "C" int mstar_rebuild_cycles(mstar_ctx *ctx, uint32_t flags, int32_t n_sy
         if (n < 2 || n > kRebuildMaxN)
             return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: system %d has %lld bodies (need 2..%d)", s, (long long)n,
                         kRebuildMaxN);
-        if (kd[s] != 0 && kd[s] != 1) return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: kind must be 0 or 1");
+        if (kd[s] < 0 || kd[s] > 3) return fail(ctx, MSTAR_E_INVAL, "rebuild_cycles: kind must be 0..3");
     }
     const int64_t n_tot = off[n_sys];
     // device buffers for this call (freed before returning)

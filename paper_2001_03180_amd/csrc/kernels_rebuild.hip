@@ -18,7 +18,9 @@
 //    levels, parents first (rho_v = rho_parent + X_v, so each rho_v is the
 //    top-down sum along its path); x = r_cm + (rho - rho_bar), velocities alike.
 //  * centre-of-mass sums are compensated (Neumaier) per lane, the lanes'
-//    sums and corrections combined in a fixed order.
+//    sums and corrections combined in a fixed order; or (kind bit 2) plain
+//    sums in index order, as in the paper's test, which then repeats the
+//    oracle's round trips bit for bit.
 #include "common.h"
 #include "rebuild.h"
 
@@ -104,8 +106,25 @@ __device__ __forceinline__ uint32_t wave_key_min(double w, int a, int b, bool va
     return umin64(k);
 }
 
-__device__ __forceinline__ void com_of(const RebLDS &S, const double (&arr)[3][kRebuildMaxN], int n, double out[3]) {
+// Centre of mass: compensated lane sums combined in a fixed order, or (plain)
+// one lane's plain sums in index order, the order of the paper's test.
+__device__ __forceinline__ void com_of(const RebLDS &S, const double (&arr)[3][kRebuildMaxN], int n, double out[3],
+                                       bool plain) {
     const int lane = __lane_id();
+    if (plain) {
+        double M = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (lane == 0)
+            for (int i = 0; i < n; ++i) {
+                M = M + S.m[i];
+                s0 = s0 + S.m[i] * arr[0][i];
+                s1 = s1 + S.m[i] * arr[1][i];
+                s2 = s2 + S.m[i] * arr[2][i];
+            }
+        out[0] = __shfl(s0 / M, 0, 64);
+        out[1] = __shfl(s1 / M, 0, 64);
+        out[2] = __shfl(s2 / M, 0, 64);
+        return;
+    }
     Comp M{0.0, 0.0}, s[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     for (int k = 0; k < kPer; ++k) {
         const int i = lane + 64 * k;
@@ -256,7 +275,8 @@ __device__ void build(RebLDS &S, int n, int kind, const double rcm[3]) {
 }
 
 // rho_v = rho_parent + (a_v - a_parent) by levels; then out = base + (rho - rho_bar).
-__device__ void rebuild_one(RebLDS &S, int n, int maxl, double (&a)[3][kRebuildMaxN], const double base[3]) {
+__device__ void rebuild_one(RebLDS &S, int n, int maxl, double (&a)[3][kRebuildMaxN], const double base[3],
+                            bool plain) {
     const int lane = __lane_id();
     for (int k = 0; k < kPer; ++k) {
         const int i = lane + 64 * k;
@@ -274,7 +294,7 @@ __device__ void rebuild_one(RebLDS &S, int n, int maxl, double (&a)[3][kRebuildM
         lds_sync();
     }
     double cb[3];
-    com_of(S, S.rho, n, cb);
+    com_of(S, S.rho, n, cb, plain);
     lds_sync();
     for (int k = 0; k < kPer; ++k) {
         const int i = lane + 64 * k;
@@ -292,6 +312,7 @@ __global__ __launch_bounds__(64) void k_rebuild(const RebuildArgs *__restrict__ 
     const int64_t o = A.off[sys];
     const int n = (int)(A.off[sys + 1] - o);
     const int kind = A.kind[sys];
+    const bool plain = (kind & 2) != 0;
     for (int k = 0; k < kPer; ++k) {
         const int i = lane + 64 * k;
         if (i < n) {
@@ -307,9 +328,9 @@ __global__ __launch_bounds__(64) void k_rebuild(const RebuildArgs *__restrict__ 
     int kout = (int)A.next_out[sys];
     for (int64_t cyc = c0 + 1; cyc <= c1; ++cyc) {
         double rcm[3], vcm[3];
-        com_of(S, S.x, n, rcm);
-        com_of(S, S.v, n, vcm);
-        build(S, n, kind, rcm);
+        com_of(S, S.x, n, rcm, plain);
+        com_of(S, S.v, n, vcm, plain);
+        build(S, n, kind & 1, rcm);
         int ml = 0;
         long ls = 0;
         for (int k = 0; k < kPer; ++k) {
@@ -324,8 +345,8 @@ __global__ __launch_bounds__(64) void k_rebuild(const RebuildArgs *__restrict__ 
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) lsd = lsd + __shfl_xor(lsd, off, 64);
         lsum = lsum + lsd / n;
-        rebuild_one(S, n, maxl, S.x, rcm);
-        rebuild_one(S, n, maxl, S.v, vcm);
+        rebuild_one(S, n, maxl, S.x, rcm, plain);
+        rebuild_one(S, n, maxl, S.v, vcm, plain);
         while (kout < A.n_out && cyc == ((int64_t)(kout + 1) * A.n_cycles) / A.n_out) {
             double *xo = A.x_out + ((size_t)kout * A.n_tot + o) * 3, *vo = A.v_out + ((size_t)kout * A.n_tot + o) * 3;
             for (int k = 0; k < kPer; ++k) {

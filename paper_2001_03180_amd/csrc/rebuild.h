@@ -9,7 +9,7 @@ constexpr int kRebuildMaxN = 512;   // bodies per system (one wave, 8 bodies per
 
 struct RebuildArgs {
     const int64_t *off;        // [n_sys + 1] body offsets
-    const int32_t *kind;       // [n_sys] 0: MST, 1: chain
+    const int32_t *kind;       // [n_sys] 0: MST, 1: chain; + 2: plain centre-of-mass sums
     const double *m;           // [n_tot]
     double *x, *v;             // [n_tot][3] state, carried from launch to launch
     int64_t n_cycles, n_tot;

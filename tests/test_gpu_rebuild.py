@@ -7,7 +7,9 @@ the same positions, so the mean levels agree exactly; the states differ only
 by the summation order of the centre-of-mass sums (compensated on both
 sides), so after C cycles they agree to ~C * 1e-16 of the position scale
 (bound 1e-13 for 30 cycles).  On a dyadic lattice every operation is exact
-and the state must return bit for bit."""
+and the state must return bit for bit.  With plain centre-of-mass sums in
+index order (kinds 2, 3: the paper's test) every operation is the oracle's,
+and the GPU repeats its round trips bit for bit."""
 import sys
 
 import numpy as np
@@ -106,7 +108,50 @@ def test_rebuild_error_chain_exceeds_mst(ctx, orc):
 def test_rebuild_cycles_validation(ctx, M):
     m, x, v = ics.plummer(8, 1)
     with pytest.raises(M.MstarError):
-        ctx.rebuild_cycles([0, 8], [2], m, x, v, 1, 1)
+        ctx.rebuild_cycles([0, 8], [4], m, x, v, 1, 1)
     m, x, v = ics.plummer(513, 1)
     with pytest.raises(M.MstarError):
         ctx.rebuild_cycles([0, 513], [0], m, x, v, 1, 1)
+
+
+def test_plain_sum_round_trips_repeat_the_oracle_over_2000_cycles(ctx, orc):
+    """The Sec. 3.5 curve with plain sums: ten Hernquist clusters (N = 379),
+    MST and chain, 2000 round trips; the GPU states after 500, 1000, 1500 and
+    2000 cycles equal the oracle's bit for bit, so the energy-error curves
+    are the same curve.  Its values are printed."""
+    import concurrent.futures as cf
+    import math
+    sys_ = [ics.hernquist(379, seed) for seed in range(1, 11)]
+    off = np.cumsum([0] + [379] * 20)
+    m = np.concatenate([s[0] for s in sys_] * 2)
+    x = np.concatenate([s[1] for s in sys_] * 2)
+    v = np.concatenate([s[2] for s in sys_] * 2)
+    say("plain-sum round trips, 20 systems x 2000 cycles")
+    xs, vs, ml = ctx.rebuild_cycles(off, [2] * 10 + [3] * 10, m, x, v, 2000, 4)
+
+    def one(s):
+        ms, x0, v0 = sys_[s % 10]
+        return orc.rebuild_cycles(ms, x0, v0, 2 if s < 10 else 3, 2000, 4)
+
+    with cf.ThreadPoolExecutor(max_workers=16) as pool:
+        ref = list(pool.map(one, range(20)))
+
+    def energy(ms, xx, vv):
+        terms = list(0.5 * ms * (vv * vv).sum(1))
+        for i in range(len(ms) - 1):
+            d = xx[i + 1:] - xx[i]
+            terms.extend(-(ms[i] * ms[i + 1:]) / np.sqrt((d * d).sum(1)))
+        return math.fsum(terms)
+
+    curve = np.zeros((4, 2))
+    for s in range(20):
+        o, e = off[s], off[s + 1]
+        xo, vo, mlo = ref[s]
+        assert np.array_equal(xs[:, o:e], xo) and np.array_equal(vs[:, o:e], vo), s
+        assert abs(ml[s] - mlo) <= 1e-12 * mlo   # per-launch partial sums of the same levels
+        ms = sys_[s % 10][0]
+        E0 = energy(ms, sys_[s % 10][1], sys_[s % 10][2])
+        for k in range(4):
+            curve[k, s // 10] += abs(energy(ms, xs[k, o:e], vs[k, o:e]) / E0 - 1.0) / 10
+    for k in range(4):
+        say(f"{500 * (k + 1)} cycles: mean |dE/E| MST {curve[k, 0]:.2e}, chain {curve[k, 1]:.2e}")
