@@ -168,6 +168,27 @@ def test_adjoint_vs_finite_differences_of_replay(ctx, orc, M):
         assert abs(fd - ad) <= 1e-6 * (abs(ad) + np.linalg.norm(ax) + np.linalg.norm(av)), (q, fd, ad)
 
 
+def test_autograd_device_path_matches_host_path(ctx, M):
+    """CUDA tensors go through the library's device-pointer path in both the
+    forward and the backward pass; the results equal the host path's bit for
+    bit and stay on the device."""
+    import torch
+    from paper_2001_03180_amd import autograd as AG
+    m, x, v = ics.plummer_with_central_mass(31, 9)
+    n = len(m)
+    res = {}
+    for dev in ("cpu", "cuda"):
+        x0 = torch.tensor(x, device=dev, requires_grad=True)
+        v0 = torch.tensor(v, device=dev, requires_grad=True)
+        xs, vs, ts = AG.integrate(x0, v0, m, 0.0, 10.0, max_accepted=60, ctx=ctx, eta=1e-12, checkpoint_every=20)
+        J = xs[n - 1].sum() + 0.5 * vs[0].sum() + ts
+        gx, gv = torch.autograd.grad(J, (x0, v0))
+        assert xs.device.type == dev and gx.device.type == dev
+        res[dev] = [t.detach().cpu().numpy() for t in (xs, vs, ts, gx, gv)]
+    for a, b in zip(res["cpu"], res["cuda"]):
+        assert np.array_equal(a, b)
+
+
 def test_autograd_function(ctx, orc, M):
     import torch
     from paper_2001_03180_amd import autograd as AG
