@@ -236,8 +236,10 @@ def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
     t_rep = time.perf_counter() - t0
     kf = 8
     ops = 2 * kf * (kf + 1) + kf
+    step_bytes = (32 * n * ops + 64 * ops + 255) // 256 * 256   # kept substep states of one step
+    store = 2 * min(checkpoint_every, (4 << 30) // (2 * step_bytes)) * step_bytes   # two blocks of steps
     dev_bytes = 32 * n * (2 * ((steps + checkpoint_every - 1) // checkpoint_every) + 2 * checkpoint_every +
-                          ops + 4 * kf + 4) + 8 * ops * 8
+                          2 + 4 * kf + 4) + store
     return {
         "workload": "plummer256_bh: Plummer N=256 (seed 501) + central mass 0.01 (N_p=257); eta=1e-12, "
                     f"{steps} accepted GBS steps; gradient of the central mass's end x-position w.r.t. all 6N "

@@ -378,11 +378,25 @@ int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const do
  * the masses m, which enter the accelerations, the force function U of the
  * kicks' time transformation, the kinetic energy T of the drifts' and the
  * binding energy B = U(x0) - T(v0).  Checkpoints the state every
- * checkpoint_every steps and recomputes each segment (and each step's
- * substep states) during the reverse pass. */
+ * checkpoint_every steps; the reverse pass recomputes one segment at a time
+ * from its checkpoint, keeping the substep states of all its steps (blocks
+ * of fewer steps if two segments' states exceed the context's store limit,
+ * see mstar_adjoint_store_limit), on a second stream of the context's device
+ * while the previous block is reversed on ctx's stream.  The result is
+ * bitwise independent of checkpoint_every and of the store limit. */
 int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
                          const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
                          const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm);
+
+/* Upper bound, in bytes, of the device memory in which the reverse pass of
+ * mstar_replay_adjoint / mstar_integrate_adjoint keeps recomputed substep
+ * states (two blocks of steps; each step holds every kick's positions, every
+ * drift's velocities and the op scalars of its k_fix divisions, about
+ * 32 (2 k_fix^2 + 3 k_fix) N bytes).  0 restores the default of 4 GiB.  At
+ * least two steps' states are always kept, whatever the limit.  The memory is
+ * allocated on the next adjoint call that needs more than the context holds
+ * and kept until mstar_destroy.  MSTAR_E_INVAL for bytes < 0. */
+int mstar_adjoint_store_limit(mstar_ctx *ctx, int64_t bytes);
 
 /* Record and reverse in one call: integrate from (x0, v0) at t0 toward t_end
  * (mstar_integrate's driver, Sec. 2.4) until n_steps steps are accepted or

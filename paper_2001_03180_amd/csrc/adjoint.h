@@ -14,7 +14,8 @@ constexpr int kAdjOpScal = 8;    // scalars kept per leapfrog op: dt, g, T or U,
 // vst, and its op scalars at ops 2k(k+1)+k .. of sc.
 struct AdjDev {
     int n, kf;
-    int tpb;                // threads per body (1..4): the j-range of each body is split tpb ways
+    int tpb;                // threads per body (1..4): the j-range of each body is split tpb ways,
+    int ext;                // that of the first ext bodies tpb + 1 ways (tpb n + ext <= 1024 threads)
     double G, alpha, gamma;
     const double *m;        // [n]
     const double *c;        // [kf] extrapolation weights

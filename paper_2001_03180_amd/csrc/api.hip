@@ -101,6 +101,15 @@ struct mstar_ctx {
     double *cpt = nullptr;
     d4 *sgr = nullptr, *sgv = nullptr;    // states of one checkpoint segment
     double *sgt = nullptr;
+    d4 *brr = nullptr, *brv = nullptr;    // running state of the block recomputation
+    double *brt = nullptr;
+    // the reverse pass recomputes the next block of steps (keeping every
+    // substep state) on a second stream while the current block is reversed
+    hipStream_t a_s2 = nullptr;
+    hipEvent_t a_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // kept[2], reversed[2], checkpoints
+    void *a_store = nullptr;              // two slots of kept substep states
+    size_t a_store_cap = 0;               // bytes
+    size_t a_store_max = size_t(4) << 30; // limit of both slots together (bytes)
     double *a_m = nullptr, *a_c = nullptr, *a_io[4] = {nullptr, nullptr, nullptr, nullptr};
     double *a_gm = nullptr;               // mass gradient [n]
 };
@@ -852,7 +861,12 @@ void mstar_destroy(mstar_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_workspace(ctx);
+    if (ctx->a_s2) (void)hipStreamSynchronize(ctx->a_s2);
     for (void *p : ctx->a_allocs) (void)hipFree(p);
+    if (ctx->a_store) (void)hipFree(ctx->a_store);
+    for (hipEvent_t e : ctx->a_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->a_s2) (void)hipStreamDestroy(ctx->a_s2);
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
     if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
@@ -1660,14 +1674,22 @@ int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_s
 
 namespace {
 
+// Threads per body of the division kernels: up to 4, and one more for as many
+// bodies as fit in 1024 threads.
+void adj_threads(AdjDev &d, int n) {
+    d.tpb = std::max(1, std::min(4, kAdjMaxN / n));
+    d.ext = d.tpb < 4 ? std::min(n, kAdjMaxN - d.tpb * n) : 0;
+}
+
 int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     if (n <= ctx->a_n && kf <= ctx->a_kf && ncp <= ctx->a_ncp && seg <= ctx->a_seg) {
         ctx->ad.n = n;
         ctx->ad.kf = kf;
-        ctx->ad.tpb = std::max(1, std::min(4, kAdjMaxN / n));
+        adj_threads(ctx->ad, n);
         return MSTAR_OK;
     }
     HIPCK(hipStreamSynchronize(ctx->stream));
+    if (ctx->a_s2) HIPCK(hipStreamSynchronize(ctx->a_s2));
     const size_t N = (size_t)std::max(n, ctx->a_n), K = (size_t)std::max(std::max(kf, 2), ctx->a_kf);
     const size_t CP = (size_t)std::max<int64_t>(std::max<int64_t>(ncp, 1), ctx->a_ncp);
     const size_t SG = (size_t)std::max<int64_t>(std::max<int64_t>(seg, 1), ctx->a_seg);
@@ -1675,7 +1697,6 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     ctx->a_allocs.clear();
     ctx->a_n = ctx->a_kf = 0;
     ctx->a_ncp = ctx->a_seg = 0;
-    const size_t kicks = K * (K + 1), drifts = K * (K + 1) + K, ops = 2 * K * (K + 1) + K;
     AdjDev &d = ctx->ad;
     auto A = [&](auto **p, size_t count) -> int {
         void *q = nullptr;
@@ -1691,8 +1712,7 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
         (rc = A(&d.Et, K)) || (rc = A(&d.Lr, N)) || (rc = A(&d.Lv, N)) || (rc = A(&d.Lt, 1)) || (rc = A(&d.LB, 1)) ||
         (rc = A(&d.Sr, K * N)) || (rc = A(&d.Sv, K * N)) || (rc = A(&d.St, K)) || (rc = A(&d.SB, K)) ||
         (rc = A(&d.Sm, K * N)) || (rc = A(&d.Lm, N)) || (rc = A(&ctx->a_gm, N)) ||
-        (rc = A(&d.rst, kicks * N)) || (rc = A(&d.vst, drifts * N)) || (rc = A(&d.sc, ops * kAdjOpScal)) ||
-        (rc = A(&ctx->Yr, N)) || (rc = A(&ctx->Yv, N)) || (rc = A(&ctx->Yt, 1)) || (rc = A(&ctx->cpr, CP * N)) ||
+        (rc = A(&ctx->brr, N)) || (rc = A(&ctx->brv, N)) || (rc = A(&ctx->brt, 1)) || (rc = A(&ctx->Yr, N)) || (rc = A(&ctx->Yv, N)) || (rc = A(&ctx->Yt, 1)) || (rc = A(&ctx->cpr, CP * N)) ||
         (rc = A(&ctx->cpv, CP * N)) || (rc = A(&ctx->cpt, CP)) || (rc = A(&ctx->sgr, SG * N)) ||
         (rc = A(&ctx->sgv, SG * N)) || (rc = A(&ctx->sgt, SG)))
         return rc;
@@ -1708,7 +1728,7 @@ int ensure_adj(mstar_ctx *ctx, int n, int kf, int64_t ncp, int64_t seg) {
     ctx->a_seg = (int64_t)SG;
     d.n = n;
     d.kf = kf;
-    d.tpb = std::max(1, std::min(4, kAdjMaxN / n));
+    adj_threads(d, n);
     return MSTAR_OK;
 }
 
@@ -1765,9 +1785,44 @@ int adj_setup(mstar_ctx *ctx, const mstar_params *p, int64_t n, const double *m,
 }
 
 // One replayed GBS step from (r, v, t) into (or, ov, ot) (may alias).
-void adj_step(mstar_ctx *ctx, const d4 *r, const d4 *v, const double *t, double H, d4 *or_, d4 *ov, double *ot) {
-    launch_adj_fwd(ctx->ad, ctx->stream, r, v, t, H, false);
-    launch_adj_combine(ctx->ad, ctx->stream, r, v, t, or_, ov, ot);
+void adj_step(mstar_ctx *ctx, hipStream_t s, const d4 *r, const d4 *v, const double *t, double H, d4 *or_, d4 *ov,
+              double *ot) {
+    launch_adj_fwd(ctx->ad, s, r, v, t, H, false);
+    launch_adj_combine(ctx->ad, s, r, v, t, or_, ov, ot);
+}
+
+// Kept substep states of one GBS step: every kick's positions, every drift's
+// velocities and the op scalars of the k_fix divisions, 256-byte aligned.
+size_t adj_step_bytes(int n, int kf) {
+    const size_t kicks = (size_t)kf * (kf + 1), drifts = kicks + kf, ops = 2 * kicks + kf;
+    const size_t b = sizeof(d4) * (kicks + drifts) * (size_t)n + sizeof(double) * kAdjOpScal * ops;
+    return (b + 255) & ~size_t(255);
+}
+// AdjDev whose store pointers address step a of slot z (Q steps per slot).
+AdjDev adj_slot(const mstar_ctx *ctx, int z, int64_t Q, int64_t a) {
+    AdjDev d = ctx->ad;
+    const size_t kicks = (size_t)d.kf * (d.kf + 1), drifts = kicks + d.kf;
+    char *base = (char *)ctx->a_store + (size_t)(z * Q + a) * adj_step_bytes(d.n, d.kf);
+    d.rst = (d4 *)base;
+    d.vst = d.rst + kicks * (size_t)d.n;
+    d.sc = (double *)(d.vst + drifts * (size_t)d.n);
+    return d;
+}
+int ensure_adj_pipe(mstar_ctx *ctx, size_t bytes) {
+    if (!ctx->a_s2) HIPCK(hipStreamCreateWithFlags(&ctx->a_s2, hipStreamNonBlocking));
+    for (hipEvent_t &e : ctx->a_ev)
+        if (!e) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (bytes > ctx->a_store_cap) {
+        HIPCK(hipStreamSynchronize(ctx->stream));
+        HIPCK(hipStreamSynchronize(ctx->a_s2));
+        if (ctx->a_store) (void)hipFree(ctx->a_store);
+        ctx->a_store = nullptr;
+        ctx->a_store_cap = 0;
+        if (hipMalloc(&ctx->a_store, bytes) != hipSuccess)
+            return fail(ctx, MSTAR_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        ctx->a_store_cap = bytes;
+    }
+    return MSTAR_OK;
 }
 
 int adj_out(mstar_ctx *ctx, uint32_t flags, int64_t n, const d4 *a, double *dst, int io) {
@@ -1785,7 +1840,8 @@ int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const do
     ctx->err.clear();
     int rc = adj_setup(ctx, params, n, m, x, v, t0, n_steps, H, 1, 1);
     if (rc) return rc;
-    for (int64_t k = 0; k < n_steps; ++k) adj_step(ctx, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
+    for (int64_t k = 0; k < n_steps; ++k)
+        adj_step(ctx, ctx->stream, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
     HIPCK(hipGetLastError());
     const uint32_t flags = params->flags;
     if ((rc = adj_out(ctx, flags, n, ctx->Yr, x, 2))) return rc;
@@ -1816,7 +1872,7 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
         if (k % C == 0)
             launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr + (size_t)(k / C) * N,
                             ctx->cpv + (size_t)(k / C) * N, ctx->cpt + k / C);
-        adj_step(ctx, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
+        adj_step(ctx, s, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
     }
     if (n_steps == 0) launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr, ctx->cpv, ctx->cpt);
     // seeds: cotangent of the end state
@@ -1828,21 +1884,70 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     launch_adj_pack(s, (int)n, (const double *)gvd, d.Lv, 0.0, nullptr);
     launch_adj_zero(s, d.LB);
     launch_adj_zero_n(s, (int)n, d.Lm);
-    // reverse pass, one checkpoint segment at a time
-    for (int64_t seg = ncp - 1; seg >= 0 && n_steps > 0; --seg) {
-        const int64_t j0 = seg * C, j1 = std::min(n_steps, j0 + C);
-        launch_adj_copy(s, (int)n, ctx->cpr + (size_t)seg * N, ctx->cpv + (size_t)seg * N, ctx->cpt + seg, ctx->sgr,
-                        ctx->sgv, ctx->sgt);
-        for (int64_t j = j0; j + 1 < j1; ++j) {
-            const size_t a = (size_t)(j - j0), b = a + 1;
-            adj_step(ctx, ctx->sgr + a * N, ctx->sgv + a * N, ctx->sgt + a, H[j], ctx->sgr + b * N, ctx->sgv + b * N,
-                     ctx->sgt + b);
+    // Reverse pass in blocks of at most Q steps, the last block first.  A
+    // block is recomputed from its start state on the second stream, keeping
+    // the substep states of all its steps in one of two slots, and then
+    // reversed on the context's stream; the recomputation of the next block
+    // runs while the current one is reversed.  A block is a whole checkpoint
+    // segment when two segments' states fit the store (Q = C); otherwise the
+    // segment's step states are first recomputed into sgr and its blocks
+    // start there.  The kernels and their order per step are those of a
+    // serial pass, so the result does not depend on C or Q.
+    if (n_steps > 0) {
+        const size_t sb = adj_step_bytes((int)n, d.kf);
+        const int64_t Q = std::max<int64_t>(1, std::min<int64_t>(C, (int64_t)(ctx->a_store_max / (2 * sb))));
+        if ((rc = ensure_adj_pipe(ctx, 2 * (size_t)Q * sb))) return rc;
+        hipStream_t s2 = ctx->a_s2;
+        hipEvent_t *kept = ctx->a_ev, *done = ctx->a_ev + 2;
+        HIPCK(hipEventRecord(ctx->a_ev[4], s));   // checkpoints and seeds are in place
+        HIPCK(hipStreamWaitEvent(s2, ctx->a_ev[4], 0));
+        struct Blk { int64_t seg, b0, b1; };
+        std::vector<Blk> blocks;   // in the order they are reversed
+        for (int64_t seg = ncp - 1; seg >= 0; --seg) {
+            const int64_t j0 = seg * C, j1 = std::min(n_steps, j0 + C);
+            for (int64_t b1 = j1; b1 > j0; b1 -= Q) blocks.push_back(Blk{seg, std::max(j0, b1 - Q), b1});
         }
-        for (int64_t j = j1 - 1; j >= j0; --j) {
-            const size_t a = (size_t)(j - j0);
-            launch_adj_fwd(d, s, ctx->sgr + a * N, ctx->sgv + a * N, ctx->sgt + a, H[j], true);
-            launch_adj_rev(d, s);
-            launch_adj_combine_rev(d, s);
+        auto recompute = [&](size_t i) -> int {
+            const Blk &B = blocks[i];
+            const int z = (int)(i & 1);
+            const int64_t j0 = B.seg * C, j1 = std::min(n_steps, j0 + C);
+            const d4 *sr = ctx->cpr + (size_t)B.seg * N, *sv = ctx->cpv + (size_t)B.seg * N;
+            const double *st = ctx->cpt + B.seg;
+            if (j1 - j0 > Q) {
+                // the segment's step states, once per segment (its last block comes first)
+                if (B.b1 == j1) {
+                    launch_adj_copy(s2, (int)n, sr, sv, st, ctx->sgr, ctx->sgv, ctx->sgt);
+                    for (int64_t j = j0; j < B.b0; ++j) {   // states up to the latest block start
+                        const size_t a = (size_t)(j - j0), b = a + 1;
+                        adj_step(ctx, s2, ctx->sgr + a * N, ctx->sgv + a * N, ctx->sgt + a, H[j], ctx->sgr + b * N,
+                                 ctx->sgv + b * N, ctx->sgt + b);
+                    }
+                }
+                const size_t a = (size_t)(B.b0 - j0);
+                sr = ctx->sgr + a * N;
+                sv = ctx->sgv + a * N;
+                st = ctx->sgt + a;
+            }
+            if (i >= 2) HIPCK(hipStreamWaitEvent(s2, done[z], 0));   // the slot's previous block is reversed
+            launch_adj_copy(s2, (int)n, sr, sv, st, ctx->brr, ctx->brv, ctx->brt);
+            for (int64_t j = B.b0; j < B.b1; ++j) {
+                launch_adj_fwd(adj_slot(ctx, z, Q, j - B.b0), s2, ctx->brr, ctx->brv, ctx->brt, H[j], true);
+                if (j + 1 < B.b1) launch_adj_combine(d, s2, ctx->brr, ctx->brv, ctx->brt, ctx->brr, ctx->brv, ctx->brt);
+            }
+            HIPCK(hipEventRecord(kept[z], s2));
+            return MSTAR_OK;
+        };
+        if ((rc = recompute(0))) return rc;
+        for (size_t i = 0; i < blocks.size(); ++i) {
+            if (i + 1 < blocks.size() && (rc = recompute(i + 1))) return rc;
+            const Blk &B = blocks[i];
+            const int z = (int)(i & 1);
+            HIPCK(hipStreamWaitEvent(s, kept[z], 0));
+            for (int64_t j = B.b1 - 1; j >= B.b0; --j) {
+                launch_adj_rev(adj_slot(ctx, z, Q, j - B.b0), s);
+                launch_adj_combine_rev(d, s);
+            }
+            HIPCK(hipEventRecord(done[z], s));
         }
     }
     launch_adj_finish(d, s, ctx->cpr, ctx->cpv, ctx->a_io[2], ctx->a_io[3], gm ? ctx->a_gm : nullptr);
@@ -1851,6 +1956,14 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     if ((rc = out_copy(ctx, flags, gv0, ctx->a_io[3], sizeof(double) * 3 * n))) return rc;
     if (gm && (rc = out_copy(ctx, flags, gm, ctx->a_gm, sizeof(double) * n))) return rc;
     HIPCK(hipStreamSynchronize(s));
+    return MSTAR_OK;
+}
+
+int mstar_adjoint_store_limit(mstar_ctx *ctx, int64_t bytes) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    if (bytes < 0) return fail(ctx, MSTAR_E_INVAL, "adjoint_store_limit: bytes < 0");
+    ctx->a_store_max = bytes == 0 ? size_t(4) << 30 : (size_t)bytes;
     return MSTAR_OK;
 }
 

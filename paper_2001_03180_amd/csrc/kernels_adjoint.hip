@@ -18,8 +18,8 @@
 // Hessian-vector product).
 //
 // One workgroup integrates (or reverses) one substep division of one GBS
-// step with up to 1024 threads: min(4, 1024/N) threads per body, each summing
-// a contiguous chunk of the j-range, the chunks added in order through LDS.
+// step with up to 1024 threads: up to 4 threads per body, each summing a
+// contiguous chunk of the j-range, the chunks added in order through LDS.
 // Positions and the adjoint weights of the j-bodies are broadcast from LDS,
 // and U, T, the COM velocity and the d(dt) sums are workgroup sums in a
 // fixed order.
@@ -112,22 +112,32 @@ struct AdjShared {
     double red[2 * 4 * kMaxWaves];
 };
 
-// Thread layout: T = d.tpb threads per body; thread (b, q) owns body b and the
-// q-th of T contiguous chunks of the j-range.  Per-body state is replicated in
-// the T threads (they compute identical values); sums over bodies take the
-// q = 0 threads only.
+// Thread layout: the first d.ext bodies take d.tpb + 1 threads, the others
+// d.tpb (so that up to 1024 threads share the pair work evenly); thread
+// (b, q) of a body with T threads owns body b and the q-th of T contiguous
+// chunks of the j-range.  Per-body state is replicated in the T threads
+// (they compute identical values); sums over bodies take the q = 0 threads
+// only.  split (uniform) tells whether any body has more than one thread.
 struct Lay {
     int b, q, T;
-    bool live, lead;
+    bool live, lead, split;
     int jb, je;
 };
 __device__ __forceinline__ Lay layout(const AdjDev &d) {
     Lay L;
-    L.T = d.tpb;
-    L.b = (int)threadIdx.x / L.T;
-    L.q = (int)threadIdx.x - L.b * L.T;
+    const int t = (int)threadIdx.x, T1 = d.tpb + 1, wide = d.ext * T1;
+    if (t < wide) {
+        L.T = T1;
+        L.b = t / T1;
+        L.q = t - L.b * T1;
+    } else {
+        L.T = d.tpb;
+        L.b = d.ext + (t - wide) / d.tpb;
+        L.q = (t - wide) - (L.b - d.ext) * d.tpb;
+    }
     L.live = L.b < d.n;
     L.lead = L.live && L.q == 0;
+    L.split = d.tpb > 1 || d.ext > 0;
     const int c = (d.n + L.T - 1) / L.T;
     L.jb = min(d.n, L.q * c);
     L.je = min(d.n, L.jb + c);
@@ -194,7 +204,7 @@ __device__ __forceinline__ void accel_hvp_part(const AdjShared &S, int jb, int j
 // The barrier before the writes ends every thread's reads of pos / la.
 __device__ __forceinline__ void sum_parts(AdjShared &S, const Lay &L, int n, double &ax, double &ay, double &az,
                                           double &ph) {
-    if (L.T == 1) return;
+    if (!L.split) return;
     __syncthreads();
     if (L.live) S.pos[L.q * n + L.b] = d4{ax, ay, az, ph};
     __syncthreads();
@@ -392,7 +402,7 @@ __global__ __launch_bounds__(kAdjMaxN) void k_adj_rev(AdjDev d) {
             // lambda_dt = sum_i lambda_v,i . a_i, from the per-thread partials
             double s1[1] = {L.live ? (lv.x * (d.G * ax) + lv.y * (d.G * ay)) + lv.z * (d.G * az) : 0.0};
             wave_partials<1>(s1, S.red, rb);
-            if (L.T > 1) {
+            if (L.split) {
                 __syncthreads();   // every j-loop has finished reading pos / la
                 if (L.live) {
                     S.pos[L.q * n + L.b] = d4{ax, ay, az, ph};
@@ -558,7 +568,7 @@ __global__ void k_adj_copy(int n, const d4 *a, const d4 *b, const double *t, d4 
     if (i == 0) *ot = *t;
 }
 
-int threads_for(const AdjDev &d) { return ((d.n * d.tpb + 63) / 64) * 64; }
+int threads_for(const AdjDev &d) { return ((d.n * d.tpb + d.ext + 63) / 64) * 64; }
 
 }  // namespace
 

@@ -121,6 +121,7 @@ EXPORTS = {
                                           C.c_void_p, C.c_double, C.c_double, C.c_int64, C.c_int32, C.c_void_p,
                                           C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.POINTER(Stats)]),
+    "mstar_adjoint_store_limit": (C.c_int, [C.c_void_p, C.c_int64]),
     "mstar_force_hvp": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
     "mstar_force_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p,
@@ -498,6 +499,10 @@ class Context:
                                                a[3].ptr, a[4].ptr, float(gt), o[0].ptr, o[1].ptr,
                                                om.ptr if om else None))
         return (gx0, gv0, gm) if with_mass else (gx0, gv0)
+
+    def adjoint_store_limit(self, nbytes):
+        """Bound (bytes) of the recomputed substep states the reverse pass keeps; 0 = default."""
+        self._check(lib().mstar_adjoint_store_limit(self._h, int(nbytes)))
 
     def integrate_adjoint(self, m, x0, v0, t0, t_end, n_steps, gxT, gvT, gtT=0.0, checkpoint_every=50,
                           p: Params | None = None, with_mass=True):

@@ -8,7 +8,8 @@
 * adjoint: dot-product test against the oracle TLM on random directions,
   <lambda, J delta> = <J^T lambda, delta> (1e-9 relative), central
   differences of the GPU replay (1e-6), and bitwise independence of the
-  checkpoint interval (the recomputation is deterministic).  The GPU and the
+  checkpoint interval and of the store limit (the recomputation is
+  deterministic).  The GPU and the
   oracle linearise around their own trajectories, which differ by rounding
   that the dynamics stretches by the same factor G as the tangents; the
   mismatch of the dot products stays ~1e-12 while G <= 1e3 and grows to
@@ -139,6 +140,30 @@ def test_adjoint_checkpoint_interval_is_bitwise_irrelevant(ctx, orc, M):
         say(f"checkpoint every {ce}")
         out = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.3, ce)
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+
+
+def test_adjoint_store_limit_is_bitwise_irrelevant(ctx, orc, M):
+    """Store limits below two segments' substep states split each segment into
+    blocks recomputed from its step states (one step per block at the
+    smallest limit, ragged blocks of two or three steps in between); the
+    gradient stays the same to the bit, masses included."""
+    m, x, v = ics.plummer(40, 21)
+    H, par = record(orc, m, x, v, 10.0, 37)
+    rng = np.random.default_rng(3)
+    gx, gv = rng.standard_normal((2, 40, 3))
+    ref = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.3, 1, with_mass=True)
+    step_bytes = 32 * (2 * 8 * 8 + 3 * 8) * 40
+    try:
+        for limit, ce in ((1, 7), (6 * step_bytes, 7), (6 * step_bytes, 37), (1, 100)):
+            say(f"store limit {limit} B, checkpoint every {ce}")
+            ctx.adjoint_store_limit(limit)
+            out = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.3, ce, with_mass=True)
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b)
+    finally:
+        ctx.adjoint_store_limit(0)
+    with pytest.raises(M.MstarError):
+        ctx.adjoint_store_limit(-1)
 
 
 def test_adjoint_vs_finite_differences_of_replay(ctx, orc, M):
