@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = os.path.join(_HERE, "liborc.so")
+# MSTAR_ORACLE_LIB selects another build of the same source (the sanitizer test)
+_LIB = os.environ.get("MSTAR_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
 
 OK, E_INVAL, E_NOMEM, E_NONFINITE, E_COINCIDENT, E_NOCONV, E_MAXSTEPS = 0, -1, -2, -4, -5, -6, -7
 W_TIME_TOL = 1
