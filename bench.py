@@ -59,8 +59,8 @@ BATCH_ETA = 1e-12
 # valid only for the force-kernel sources with this hash.
 # (per force kernel kind; None where not measured for the current sources)
 FORCE_TRAFFIC = {
-    1: {"sha256": "9726d0be1a8c026c04f479a8562f469c2ce3b81336b4a5dfbfa835a688aeccee",
-        "fetch_bytes": 6283.17 * 1024 * 2.000, "write_bytes": 38820.8 * 1024 * 1.000,
+    1: {"sha256": "55f013ec72b50b9bc43aafa6617b0dc30f927edc65ec64beeb303c02843272fb",
+        "fetch_bytes": 6248.03 * 1024 * 2.000, "write_bytes": 29412.10 * 1024 * 1.000,
         # executed FP64 flops (ADD + MUL + 2 FMA + TRANS) per directed pair
         "exec_flops_per_pair": 35.0 / 2},
 }

@@ -15,6 +15,11 @@ namespace mstar {
 struct __attribute__((aligned(32))) d4 {
     double x, y, z, w;
 };
+// Packed xyz (24 bytes) for the mutual force kernel's partial sums: the kernel
+// writes them and the kick reads them back, so every byte is HBM traffic twice.
+struct d3 {
+    double x, y, z;
+};
 
 constexpr int kMaxDiv = 17;        // k_fix <= 16 divisions plus the start-state slot
 constexpr int kBaseSlot = kMaxDiv - 1;   // slot holding the start state of a GBS step
@@ -174,8 +179,8 @@ struct Dev {
     int32_t *cnt;
     double *scr;                // misc scalar scratch
     // mutual (i < j) force kernel output (allocated when N suits that kernel)
-    d4 *mip;                    // [slot][rows][maxw][64 kMutIPL] i-side partials, one per wave and row
-    d4 *mjp;                    // [slot][2][rows][n] j-side partials, one per row (two if a wave split the block)
+    d3 *mip;                    // [slot][rows][maxw][64 kMutIPL] i-side partials, one per wave and row
+    d3 *mjp;                    // [slot][2][rows][n] j-side partials, one per row (two if a wave split the block)
     d4 *mcp;                    // [slot][n] close-pair corrections
     double *mup;                // [slot][rows * maxw + nib] potential partials
     size_t mip_s, mjp_s, mup_s; // per-slot strides
@@ -244,19 +249,19 @@ __device__ inline void force_sum(const Dev &d, const d4 *part, const FLay &f, in
     const long long base = (long long)ea * f.Ec;
     const long long wf = (base + mut_rs(f, P)) / f.L, wl = (base + mut_rs(f, P + 1) - 1) / f.L;
     const int nw = (int)(wl - wf + 1);
-    const d4 *ip = d.mip + (size_t)slot * d.mip_s + ((size_t)P * f.maxw) * rowb + (v - rowb * P);
+    const d3 *ip = d.mip + (size_t)slot * d.mip_s + ((size_t)P * f.maxw) * rowb + (v - rowb * P);
     for (int k = t; k < nw; k += nt) {
-        const d4 e = ip[(size_t)k * rowb];
+        const d3 e = ip[(size_t)k * rowb];
         x = x + e.x; y = y + e.y; z = z + e.z;
     }
     const int J = v / 64;
-    const d4 *jp = d.mjp + (size_t)slot * d.mjp_s + v;
+    const d3 *jp = d.mjp + (size_t)slot * d.mjp_s + v;
     for (int Q = t; Q <= P; Q += nt) {
-        const d4 e = jp[(size_t)Q * n];
+        const d3 e = jp[(size_t)Q * n];
         x = x + e.x; y = y + e.y; z = z + e.z;
         const long long st = base + mut_rs(f, Q) + mut_js(f, Q, J);
         if (st / f.L != (st + mut_cost(f, Q, J) - 1) / f.L) {
-            const d4 e2 = jp[((size_t)f.npr + Q) * n];
+            const d3 e2 = jp[((size_t)f.npr + Q) * n];
             x = x + e2.x; y = y + e2.y; z = z + e2.z;
         }
     }

@@ -377,7 +377,8 @@ int force_blocks_per_cu(int nd) {
 // path-sum terms minus the Cartesian terms, as in the pairwise kernel.
 struct MutArgs {
     const d4 *P;                  // [slot][n]
-    d4 *ip, *jp, *cp;             // FLay outputs (Dev::mip, mjp, mcp)
+    d3 *ip, *jp;                  // FLay outputs (Dev::mip, mjp)
+    d4 *cp;                       // Dev::mcp
     double *up;                   // Dev::mup
     size_t ip_s, jp_s, up_s;
     const d4 *X0, *dX;
@@ -398,12 +399,12 @@ __device__ __forceinline__ void mut_flush(const MutArgs &a, int slot, int ea, in
     const long long base = (long long)ea * f.Ec;
     const long long wf = (base + mut_rs(f, P)) / f.L, wl = (base + mut_rs(f, P + 1) - 1) / f.L;
     const int widx = (int)(w - wf), last = (int)(wl - wf);
-    d4 *ip = a.ip + (size_t)slot * a.ip_s + ((size_t)P * f.maxw + widx) * (64 * IPL);
+    d3 *ip = a.ip + (size_t)slot * a.ip_s + ((size_t)P * f.maxw + widx) * (64 * IPL);
     double u = 0.0;
 #pragma unroll
     for (int q = 0; q < IPL; ++q) {
         const int i = 64 * IPL * P + 64 * q + lane;
-        if (i < a.n) ip[64 * q + lane] = d4{ax[q], ay[q], az[q], 0.0};
+        if (i < a.n) ip[64 * q + lane] = d3{ax[q], ay[q], az[q]};
         u = u + mi[q] * ph[q];
     }
     u = wave_sum(u);
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(64) void k_force_mut(MutArgs a) {
             const int b = 64 * u.J + ((lane + onext) & 63);
             if (b < a.n) {
                 const int piece = u.s > 0 ? 1 : 0;
-                a.jp[(size_t)slot * a.jp_s + ((size_t)piece * f.npr + u.P) * a.n + b] = d4{jx, jy, jz, 0.0};
+                a.jp[(size_t)slot * a.jp_s + ((size_t)piece * f.npr + u.P) * a.n + b] = d3{jx, jy, jz};
             }
             __syncthreads();
             if (!more) break;
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(64) void k_force_mut(MutArgs a) {
             if (b < a.n) {
                 const int piece = u.s > 0 ? 1 : 0;
                 a.jp[(size_t)slot * a.jp_s + ((size_t)piece * f.npr + u.P) * a.n + b] =
-                    d4{AX[lane] + AX[lane + 64], AY[lane] + AY[lane + 64], AZ[lane] + AZ[lane + 64], 0.0};
+                    d3{AX[lane] + AX[lane + 64], AY[lane] + AY[lane + 64], AZ[lane] + AZ[lane + 64]};
             }
         }
         __syncthreads();
