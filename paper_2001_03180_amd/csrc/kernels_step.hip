@@ -213,17 +213,21 @@ __global__ __launch_bounds__(kWG) void k_kick(Dev d, SlotList sl, FLay fl, doubl
     const size_t prow = (size_t)slot * d.nsplit_max * n;
     const size_t o = (size_t)slot * n + v;
     const d4 *pp = d.part + prow;
-    d4 sa{0.0, 0.0, 0.0, 0.0}, so = sa;
+    // the sums are plain scalars and the other locals start from literal
+    // zeros: copies of one zero struct let the compiler merge the lead
+    // lanes' loads with reads of that struct, which then lives in scratch
+    double sx = 0.0, sy = 0.0, sz = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
     if (live) {
-        force_sum(d, pp, fl, slot, ai, v, part, 4, sa.x, sa.y, sa.z);
+        force_sum(d, pp, fl, slot, ai, v, part, 4, sx, sy, sz);
         if constexpr (OM) {   // the TTL kernel is always the pairwise one
             for (int sp = part; sp < fl.nparts; sp += 4) {
                 const d4 t3 = d.opart[prow + (size_t)sp * n + v];
-                so.x = so.x + t3.x; so.y = so.y + t3.y; so.z = so.z + t3.z;
+                ox = ox + t3.x; oy = oy + t3.y; oz = oz + t3.z;
             }
         }
     }
-    d4 dvt = sa, v0 = sa, vo = sa, fe = sa;
+    d4 sa{sx, sy, sz, 0.0}, so{ox, oy, oz, 0.0};
+    d4 dvt{0.0, 0.0, 0.0, 0.0}, v0{0.0, 0.0, 0.0, 0.0}, vo{0.0, 0.0, 0.0, 0.0}, fe{0.0, 0.0, 0.0, 0.0};
     double mv = 0.0, mo = 0.0;
     if (lead) {
         dvt = d.dVt[o];
