@@ -234,6 +234,13 @@ def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
     t0 = time.perf_counter()
     ctx.replay(m, x, v, 0.0, H)
     t_rep = time.perf_counter() - t0
+    # one call that records and reverses: the integrator feeds each accepted
+    # step to the adjoint's forward pass, which runs alongside it
+    t0 = time.perf_counter()
+    cx, cv, _, _ = ctx.integrate_adjoint(m, x, v, 0.0, 1e9, steps, seed, np.zeros((n, 3)), 0.0, checkpoint_every,
+                                         p=p, with_mass=False)
+    t_one = time.perf_counter() - t0
+    same = bool(np.array_equal(cx, gx) and np.array_equal(cv, gv))
     kf = 8
     ops = 2 * kf * (kf + 1) + kf
     step_bytes = (32 * n * ops + 64 * ops + 255) // 256 * 256   # kept substep states of one step
@@ -247,6 +254,8 @@ def bench_adjoint(M, ctx, steps=1000, checkpoint_every=50):
         "steps": steps, "rejected_steps": st["steps_rejected"], "t_reached": st["t_reached"],
         "forward_s": t_fwd, "adjoint_s": t_adj, "replay_s": t_rep,
         "fwd_plus_bwd_over_fwd": (t_fwd + t_adj) / t_fwd,
+        "integrate_adjoint_s": t_one, "integrate_adjoint_over_fwd": t_one / t_fwd,
+        "integrate_adjoint_equals_record_then_adjoint": same,
         "checkpoint_every": checkpoint_every, "adjoint_device_bytes": dev_bytes,
         "grad_norm": float(np.sqrt(np.sum(gx * gx) + np.sum(gv * gv))),
     }

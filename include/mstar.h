@@ -403,7 +403,11 @@ int mstar_adjoint_store_limit(mstar_ctx *ctx, int64_t bytes);
  * t_end is reached, then return the gradient of <gxT, x> + <gvT, v> + gtT t
  * at the end state with respect to x0, v0 (gx0, gv0 [n][3]) and the masses
  * (gm [n], nullable), with the step sizes and MST topologies of the recorded
- * run frozen (as mstar_replay_adjoint).  x0, v0 are not modified; stats
+ * run frozen (as mstar_replay_adjoint).  The adjoint's checkpoint pass
+ * replays each step on a second stream of the device as soon as the driver
+ * has accepted it, alongside the integration; the result equals
+ * mstar_integrate_record followed by mstar_replay_adjoint bit for bit.
+ * x0, v0 are not modified; stats
  * (nullable) receives the forward run's statistics (its steps_accepted is
  * the number of steps differentiated).  Pointers per params->flags.
  * Errors: MSTAR_E_INVAL, MSTAR_E_UNSUPPORTED (n > 1024, beta != 0), the

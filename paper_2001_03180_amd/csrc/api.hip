@@ -1164,25 +1164,33 @@ int prepare_step(mstar_ctx *ctx, const mstar_params *p, bool rebuild_due, bool r
     return MSTAR_OK;
 }
 
+// Receiver of the accepted steps while the driver runs (the host side of an
+// adjoint that replays the record as it grows); called outside any graph
+// capture, after the step's control block has been read back.
+struct StepFeed {
+    virtual int accepted(double H) = 0;
+    virtual ~StepFeed() = default;
+};
+
 // The driver (Sec. 2.4); with rec_H, the fictitious step of every accepted
 // step is recorded and the run stops after max_acc accepted steps.
 static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
                          double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
-                         int64_t *n_rec, const mstar_external *ext);
+                         int64_t *n_rec, const mstar_external *ext, StepFeed *feed);
 
 // The external field applies for the duration of one integration only.
 static int integrate_impl(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
                           double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
-                          int64_t *n_rec, const mstar_external *ext = nullptr) {
+                          int64_t *n_rec, const mstar_external *ext = nullptr, StepFeed *feed = nullptr) {
     if (!ctx) return MSTAR_E_INVAL;
-    const int rc = integrate_run(ctx, params, n, m, x, v, t0, t_end, stats, max_acc, rec_H, n_rec, ext);
+    const int rc = integrate_run(ctx, params, n, m, x, v, t0, t_end, stats, max_acc, rec_H, n_rec, ext, feed);
     ctx->ext_on = false;
     return rc;
 }
 
 static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x,
                          double *v, double t0, double t_end, mstar_stats *stats, int64_t max_acc, double *rec_H,
-                         int64_t *n_rec, const mstar_external *ext) {
+                         int64_t *n_rec, const mstar_external *ext, StepFeed *feed) {
     ctx->ext_on = false;
     if (n_rec) *n_rec = 0;
     int rc = check_params(ctx, params);
@@ -1275,6 +1283,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
             continue;
         }
         if (rec_H && *n_rec < max_acc) rec_H[(*n_rec)++] = H;
+        if (feed && (rc = feed->accepted(H))) break;
         st.steps_accepted++;
         st.h_last = H;
         halvings = 0;
@@ -1745,6 +1754,8 @@ int adj_setup(mstar_ctx *ctx, const mstar_params *p, int64_t n, const double *m,
     for (int64_t k = 0; k < nsteps; ++k)
         if (!std::isfinite(H[k]) || H[k] == 0.0) return fail(ctx, MSTAR_E_INVAL, "replay: H[%lld] invalid", (long long)k);
     (void)hipSetDevice(ctx->device);
+    // work a failed adjoint call left on the second stream shares the division buffers
+    if (ctx->a_s2) HIPCK(hipStreamSynchronize(ctx->a_s2));
     const uint32_t flags = p->flags;
     std::vector<double> hm((size_t)n), hx(3 * (size_t)n), hv(3 * (size_t)n);
     const hipMemcpyKind k = is_dev(flags) ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
@@ -1830,53 +1841,44 @@ int adj_out(mstar_ctx *ctx, uint32_t flags, int64_t n, const d4 *a, double *dst,
     return out_copy(ctx, flags, dst, ctx->a_io[io], sizeof(double) * 3 * n);
 }
 
-}  // namespace
-
-extern "C" {
-
-int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
-                 double t0, int64_t n_steps, const double *H, double *t_out) {
-    if (!ctx) return MSTAR_E_INVAL;
-    ctx->err.clear();
-    int rc = adj_setup(ctx, params, n, m, x, v, t0, n_steps, H, 1, 1);
-    if (rc) return rc;
-    for (int64_t k = 0; k < n_steps; ++k)
-        adj_step(ctx, ctx->stream, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
-    HIPCK(hipGetLastError());
-    const uint32_t flags = params->flags;
-    if ((rc = adj_out(ctx, flags, n, ctx->Yr, x, 2))) return rc;
-    if ((rc = adj_out(ctx, flags, n, ctx->Yv, v, 3))) return rc;
-    double t = 0.0;
-    HIPCK(hipMemcpyAsync(&t, ctx->Yt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCK(hipStreamSynchronize(ctx->stream));
-    if (t_out) *t_out = t;
-    return MSTAR_OK;
+// Step k of the forward pass of the adjoint on stream st: the state goes to
+// checkpoint k / C first when k is a multiple of C; H = 0 only stores the
+// checkpoint (a record without steps).
+void adj_forward_step(mstar_ctx *ctx, hipStream_t st, int64_t k, int64_t C, double H) {
+    const size_t N = (size_t)ctx->ad.n;
+    if (k % C == 0)
+        launch_adj_copy(st, (int)N, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr + (size_t)(k / C) * N,
+                        ctx->cpv + (size_t)(k / C) * N, ctx->cpt + k / C);
+    if (H != 0.0) adj_step(ctx, st, ctx->Yr, ctx->Yv, ctx->Yt, H, ctx->Yr, ctx->Yv, ctx->Yt);
 }
 
-int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
-                         const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
-                         const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm) {
-    if (!ctx) return MSTAR_E_INVAL;
-    ctx->err.clear();
-    if (checkpoint_every < 1 || !gx || !gv || !gx0 || !gv0 || !std::isfinite(gt))
-        return fail(ctx, MSTAR_E_INVAL, "replay_adjoint: bad arguments");
-    const int64_t C = checkpoint_every;
-    const int64_t ncp = n_steps > 0 ? (n_steps + C - 1) / C : 1;
-    int rc = adj_setup(ctx, params, n, m, x0, v0, t0, n_steps, H, ncp, C);
-    if (rc) return rc;
+// Forward pass of an adjoint fed by the driver: each accepted step is
+// replayed on the second stream as soon as the driver has accepted it, so the
+// pass runs alongside the integration instead of after it.
+struct AdjFeed final : StepFeed {
+    mstar_ctx *ctx;
+    int64_t C, k = 0;
+    AdjFeed(mstar_ctx *c, int64_t every) : ctx(c), C(every) {}
+    int accepted(double H) override {
+        adj_forward_step(ctx, ctx->a_s2, k++, C, H);
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? MSTAR_OK : fail(ctx, MSTAR_E_DEVICE, "adjoint replay launch: %s", hipGetErrorString(e));
+    }
+};
+
+// Reverse pass of the adjoint over the n_steps recorded steps H, once the
+// checkpoints are in place (the second stream must already be ordered after
+// the forward pass): seeds, the pipelined reverse, the chain through B and
+// the outputs.
+int adj_reverse(mstar_ctx *ctx, const mstar_params *params, int64_t n, int64_t n_steps, const double *H, int64_t C,
+                const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm) {
+    // seeds: cotangent of the end state
+    const uint32_t flags = params->flags;
     const AdjDev &d = ctx->ad;
     const size_t N = (size_t)n;
     hipStream_t s = ctx->stream;
-    // forward pass, keeping the state at every C-th step
-    for (int64_t k = 0; k < n_steps; ++k) {
-        if (k % C == 0)
-            launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr + (size_t)(k / C) * N,
-                            ctx->cpv + (size_t)(k / C) * N, ctx->cpt + k / C);
-        adj_step(ctx, s, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
-    }
-    if (n_steps == 0) launch_adj_copy(s, (int)n, ctx->Yr, ctx->Yv, ctx->Yt, ctx->cpr, ctx->cpv, ctx->cpt);
-    // seeds: cotangent of the end state
-    const uint32_t flags = params->flags;
+    const int64_t ncp = n_steps > 0 ? (n_steps + C - 1) / C : 1;
+    int rc = 0;
     const void *gxd, *gvd;
     if ((rc = in_dev(ctx, flags, gx, ctx->a_io[0], sizeof(double) * 3 * n, &gxd))) return rc;
     if ((rc = in_dev(ctx, flags, gv, ctx->a_io[1], sizeof(double) * 3 * n, &gvd))) return rc;
@@ -1899,8 +1901,6 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
         if ((rc = ensure_adj_pipe(ctx, 2 * (size_t)Q * sb))) return rc;
         hipStream_t s2 = ctx->a_s2;
         hipEvent_t *kept = ctx->a_ev, *done = ctx->a_ev + 2;
-        HIPCK(hipEventRecord(ctx->a_ev[4], s));   // checkpoints and seeds are in place
-        HIPCK(hipStreamWaitEvent(s2, ctx->a_ev[4], 0));
         struct Blk { int64_t seg, b0, b1; };
         std::vector<Blk> blocks;   // in the order they are reversed
         for (int64_t seg = ncp - 1; seg >= 0; --seg) {
@@ -1959,6 +1959,51 @@ int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
     return MSTAR_OK;
 }
 
+
+}  // namespace
+
+extern "C" {
+
+int mstar_replay(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, double *x, double *v,
+                 double t0, int64_t n_steps, const double *H, double *t_out) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    int rc = adj_setup(ctx, params, n, m, x, v, t0, n_steps, H, 1, 1);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n_steps; ++k)
+        adj_step(ctx, ctx->stream, ctx->Yr, ctx->Yv, ctx->Yt, H[k], ctx->Yr, ctx->Yv, ctx->Yt);
+    HIPCK(hipGetLastError());
+    const uint32_t flags = params->flags;
+    if ((rc = adj_out(ctx, flags, n, ctx->Yr, x, 2))) return rc;
+    if ((rc = adj_out(ctx, flags, n, ctx->Yv, v, 3))) return rc;
+    double t = 0.0;
+    HIPCK(hipMemcpyAsync(&t, ctx->Yt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (t_out) *t_out = t;
+    return MSTAR_OK;
+}
+
+int mstar_replay_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t n, const double *m, const double *x0,
+                         const double *v0, double t0, int64_t n_steps, const double *H, int32_t checkpoint_every,
+                         const double *gx, const double *gv, double gt, double *gx0, double *gv0, double *gm) {
+    if (!ctx) return MSTAR_E_INVAL;
+    ctx->err.clear();
+    if (checkpoint_every < 1 || !gx || !gv || !gx0 || !gv0 || !std::isfinite(gt))
+        return fail(ctx, MSTAR_E_INVAL, "replay_adjoint: bad arguments");
+    const int64_t C = checkpoint_every;
+    const int64_t ncp = n_steps > 0 ? (n_steps + C - 1) / C : 1;
+    int rc = adj_setup(ctx, params, n, m, x0, v0, t0, n_steps, H, ncp, C);
+    if (rc) return rc;
+    hipStream_t s = ctx->stream;
+    // forward pass, keeping the state at every C-th step
+    for (int64_t k = 0; k < n_steps; ++k) adj_forward_step(ctx, s, k, C, H[k]);
+    if (n_steps == 0) adj_forward_step(ctx, s, 0, C, 0.0);
+    if ((rc = ensure_adj_pipe(ctx, 0))) return rc;
+    HIPCK(hipEventRecord(ctx->a_ev[4], s));   // checkpoints in place: the recomputation may start
+    HIPCK(hipStreamWaitEvent(ctx->a_s2, ctx->a_ev[4], 0));
+    return adj_reverse(ctx, params, n, n_steps, H, C, gx, gv, gt, gx0, gv0, gm);
+}
+
 int mstar_adjoint_store_limit(mstar_ctx *ctx, int64_t bytes) {
     if (!ctx) return MSTAR_E_INVAL;
     ctx->err.clear();
@@ -1978,6 +2023,12 @@ int mstar_integrate_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t 
         return fail(ctx, n > kAdjMaxN ? MSTAR_E_UNSUPPORTED : MSTAR_E_INVAL, "integrate_adjoint: bad arguments");
     if (ttl_on(params)) return fail(ctx, MSTAR_E_UNSUPPORTED, "integrate_adjoint: beta != 0 (TTL) is not implemented");
     (void)hipSetDevice(ctx->device);
+    // the adjoint's start state and B from the caller's x0, v0; the driver
+    // then feeds every accepted step to its forward pass on the second stream
+    const int64_t C = checkpoint_every;
+    int rc = adj_setup(ctx, params, n, m, x0, v0, t0, 0, nullptr, (n_steps + C - 1) / C, C);
+    if (rc) return rc;
+    if ((rc = ensure_adj_pipe(ctx, 0))) return rc;   // adj_setup has synchronised ctx->stream
     // forward: the integrator, recording the accepted steps, on copies of x0, v0
     const size_t b3 = sizeof(double) * 3 * (size_t)n;
     std::vector<double> hx(3 * (size_t)n), hv(3 * (size_t)n), hm((size_t)n);
@@ -1991,12 +2042,16 @@ int mstar_integrate_adjoint(mstar_ctx *ctx, const mstar_params *params, int64_t 
     int64_t nrec = 0;
     mstar_stats st{};
     st.struct_size = sizeof(mstar_stats);
-    int rc = integrate_impl(ctx, &ph, n, hm.data(), hx.data(), hv.data(), t0, t_end, &st, n_steps, H.data(), &nrec);
+    AdjFeed feed(ctx, C);
+    rc = integrate_impl(ctx, &ph, n, hm.data(), hx.data(), hv.data(), t0, t_end, &st, n_steps, H.data(), &nrec,
+                        nullptr, &feed);
     if (stats) *stats = st;
     if (rc < 0) return rc;
-    // reverse: the adjoint of the recorded steps from the caller's x0, v0
-    const int rc2 = mstar_replay_adjoint(ctx, params, n, m, x0, v0, t0, nrec, H.data(), checkpoint_every, gxT, gvT,
-                                         gtT, gx0, gv0, gm);
+    if (nrec == 0) adj_forward_step(ctx, ctx->a_s2, 0, C, 0.0);   // the checkpoint of the start state only
+    HIPCK(hipEventRecord(ctx->a_ev[4], ctx->a_s2));   // the forward pass is complete: reverse on ctx->stream
+    HIPCK(hipStreamWaitEvent(ctx->stream, ctx->a_ev[4], 0));
+    // reverse: the adjoint of the recorded steps
+    const int rc2 = adj_reverse(ctx, params, n, nrec, H.data(), C, gxT, gvT, gtT, gx0, gv0, gm);
     return rc2 ? rc2 : rc;
 }
 

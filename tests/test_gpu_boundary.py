@@ -160,6 +160,32 @@ def test_integrate_adjoint_records_and_reverses(ctx, orc, M):
         assert abs(lhs - rhs) <= 1e-9 * scale
 
 
+def test_integrate_adjoint_short_record_and_store_limit(ctx, M):
+    """The driver feeds each accepted step to the adjoint's forward pass as it
+    goes: a run that reaches t_end before n_steps, and one whose substep
+    states are kept in blocks of two steps, still equal integrate_record
+    followed by replay_adjoint bit for bit."""
+    m, x, v = ics.plummer_with_central_mass(40, 12)
+    n = len(m)
+    rng = np.random.default_rng(9)
+    gx, gv = rng.standard_normal((2, n, 3))
+    p = M.params(eta=1e-12)
+    xr, vr, rc, st2, H = ctx.integrate_record(m, x, v, 0.0, 0.05, 1000, M.params(eta=1e-12))
+    assert 0 < len(H) < 1000
+    bx, bv, bm = ctx.replay_adjoint(m, x, v, 0.0, H, gx, gv, 0.1, 5, with_mass=True)
+    say(f"integrate_adjoint to t=0.05: {len(H)} steps of at most 1000")
+    ax, av, gm, st = ctx.integrate_adjoint(m, x, v, 0.0, 0.05, 1000, gx, gv, 0.1, checkpoint_every=5, p=p)
+    assert st["steps_accepted"] == len(H)
+    assert np.array_equal(ax, bx) and np.array_equal(av, bv) and np.array_equal(gm, bm)
+    step_bytes = 32 * (2 * 8 * 8 + 3 * 8) * n
+    try:
+        ctx.adjoint_store_limit(4 * step_bytes)
+        cx, cv, cm, _ = ctx.integrate_adjoint(m, x, v, 0.0, 0.05, 1000, gx, gv, 0.1, checkpoint_every=5, p=p)
+    finally:
+        ctx.adjoint_store_limit(0)
+    assert np.array_equal(cx, bx) and np.array_equal(cv, bv) and np.array_equal(cm, bm)
+
+
 def test_integrate_adjoint_errors(ctx, M):
     m, x, v = ics.plummer(8, 1)
     g = np.zeros((8, 3))
