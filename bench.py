@@ -338,6 +338,54 @@ def _energy(m, x, v, block=1024):
     return e
 
 
+def steady_attempts(M, ctx, name, steps, warmup):
+    """Pair interactions/s of whole GBS step attempts on a named workload, timed
+    like the headline: warm up into the step controller's steady state (the
+    first-step halvings over), then `steps` attempts with inputs in HBM."""
+    import torch
+    import ics
+    m, x, v, wl = ics.workload(name)
+    n = len(m)
+    base = dict(eta=wl["eta"], k_fix=8, n_d=2)
+    allow = (M.OK, M.W_TIME_TOL, M.E_MAXSTEPS)
+    xw, vw, t1, h1 = x, v, 0.0, 0.0
+    att_w = acc_w = 0
+    chunk = max(warmup, 1)
+    for _ in range(100):
+        xw, vw, rc, stw = ctx.integrate(m, xw, vw, t1, wl["t_end"], M.params(max_steps=chunk, h_init=h1, **base),
+                                        allow=allow)
+        att = stw["steps_accepted"] + stw["steps_rejected"]
+        att_w += att
+        acc_w += stw["steps_accepted"]
+        t1, h1 = stw["t_reached"], stw["h_next"]
+        if att_w >= warmup and stw["steps_accepted"] >= 0.8 * att and acc_w >= 10:
+            break
+        chunk = 10
+    mt, xt, vt = (torch.tensor(a, device="cuda") for a in (m, xw, vw))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rc, st = ctx.integrate(mt, xt, vt, t1, wl["t_end"], M.params(max_steps=steps, h_init=h1, **base),
+                                 allow=allow)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    done = st["steps_accepted"] + st["steps_rejected"]
+    return {"n_bodies": n, "eta": wl["eta"], "pair_interactions_per_s": st["force_evals"] * n * (n - 1) / wall,
+            "ms_per_attempt": wall * 1e3 / max(done, 1), "steps_accepted": st["steps_accepted"],
+            "steps_rejected": st["steps_rejected"], "t_start": t1, "warmup_attempts": att_w}
+
+
+def bench_configs(M, ctx, steps=30, warmup=20):
+    """The other single-system configurations: 32-body Plummer (eta 1e-12),
+    1000-body Plummer with a central mass (eta 1e-13), 10000-body Plummer with
+    a hard binary (eta 1e-13)."""
+    out = {}
+    for name in ("plummer32", "plummer1000_bh", "plummer10000_binary"):
+        out[name] = steady_attempts(M, ctx, name, steps, warmup)
+        print(f"[bench] {name}: {out[name]['pair_interactions_per_s']:.3e} pairs/s, "
+              f"{out[name]['ms_per_attempt']:.3f} ms per attempt", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_mst(M, ctx, names=("plummer5000_binary", "plummer10000_binary"), steps=20, builds=10):
     """Exact (Sec. 3.2) against divide-and-conquer (Sec. 3.3) spanning trees:
     the tree builders alone on the warmed-up state (device arrays, `builds`
@@ -472,6 +520,9 @@ def main():
     ap.add_argument("--mst-only", action="store_true",
                     help="only exact vs divide-and-conquer spanning trees (Sec. 3.2 vs 3.3) at N = 5002 and 10002")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other single-system configurations")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="only the other single-system configurations (N_p = 32, 1001, 10002)")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint measurement")
     ap.add_argument("--rebuild-only", action="store_true",
                     help="only the coordinate round-trip experiment (Sec. 3.5; a few minutes)")
@@ -518,6 +569,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)
+        return
+    if args.configs_only:
+        print(json.dumps({"configs_other": bench_configs(M, ctx)}), flush=True)
         return
     m, x, v, wl = ics.workload("plummer5000_binary")
     n = len(m)
@@ -642,6 +696,8 @@ def main():
         out["batch"] = bench_batch(M, ctx, threads, not args.no_cpu)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(M, ctx)
+    if not args.no_configs:
+        out["configs_other"] = bench_configs(M, ctx)
     ctx.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x, v, eta, threads)
