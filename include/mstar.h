@@ -327,7 +327,7 @@ int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_
 /* mstar_integrate_batch that also records the fictitious step H of every
  * accepted step of every system: H [n_sys][rec_cap] (host memory; row s
  * holds system s's first min(stats[s].steps_accepted, rec_cap) steps, the
- * rest of the row is unspecified).  The record lets a system be replayed step for step (as
+ * rest of the row is NaN).  The record lets a system be replayed step for step (as
  * mstar_integrate_record does for one system).  Errors as
  * mstar_integrate_batch, and MSTAR_E_INVAL for a NULL H or rec_cap < 1. */
 int mstar_integrate_batch_record(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,

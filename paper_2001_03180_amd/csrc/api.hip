@@ -21,6 +21,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <limits>
 #include <vector>
 
 #include "../../include/mstar.h"
@@ -1583,6 +1584,11 @@ static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int3
         HIPCK(hipStreamSynchronize(ctx->stream));
     }
     memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
+    if (H) {   // the slots past a system's recorded steps were never written: NaN, not stale memory
+        for (int32_t s = 0; s < n_sys; ++s)
+            for (int64_t k = std::max<int64_t>(0, std::min<int64_t>(stats[s].steps_accepted, rec_cap)); k < rec_cap; ++k)
+                H[(size_t)s * (size_t)rec_cap + (size_t)k] = std::numeric_limits<double>::quiet_NaN();
+    }
     if (ctx->prof) {
         double pairs = 0.0;
         for (int32_t s = 0; s < n_sys; ++s) {

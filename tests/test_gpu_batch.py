@@ -258,8 +258,12 @@ def test_record_buffer_survives_growth(ctx, M, small):
         o2, m2, x2, v2 = sub_batch(*full, list(range(k)))
         ctx.integrate_batch(o2, m2, x2, v2, 2e-4, p=p)
     again = ctx.integrate_batch_record(o8, m8, x8, v8, T_SHORT, 512, p=p)
-    for a, b in zip(first, again):
+    for a, b in zip(first[:3], again[:3]):
         assert np.array_equal(a, b)
+    H1, H2, acc = first[3], again[3], first[2]["steps_accepted"]
+    assert np.array_equal(H1, H2, equal_nan=True)
+    for s in range(len(acc)):   # recorded steps finite, the rest of each row NaN
+        assert np.all(np.isfinite(H1[s, :acc[s]])) and np.all(np.isnan(H1[s, acc[s]:]))
 
 
 def test_batch_matches_single_system_path(ctx, M, small):

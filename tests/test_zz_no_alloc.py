@@ -1,5 +1,6 @@
 """mstar_force_noalloc (the allocation-free force evaluation) against the
-existing entry point mstar_force, through the C ABI.
+existing entry point mstar_force, through the C ABI, from the largest size
+the scratch array takes down to 65 bodies.
 
 Same bar as the force parity tests: max_i |a_i - a_i'| / (G sum_j m_j/r_ij^2)
 <= 1e-13 and |U - U'| <= 1e-13 U, here also against the oracle.  Two calls in
@@ -67,7 +68,8 @@ def _noalloc(M, m, rho, parent, X, nd):
 @pytest.mark.parametrize("nd", [2, 0])
 def test_noalloc_matches_force_twice_shrinking(ctx, orc, nd):
     import paper_2001_03180_amd as M
-    for n, seed in ((5002, 301), (1001, 201), (65, 3)):
+    # the largest size the scratch array takes first, then smaller ones
+    for n, seed in ((M.NOALLOC_MAX_N, 17), (5002, 301), (1001, 201), (65, 3)):
         m, rho, parent, X = _case(orc, n, seed)
         say(f"force_noalloc n={n} nd={nd}")
         rc, acc, U = _noalloc(M, m, rho, parent, X, nd)
