@@ -316,10 +316,13 @@ typedef struct {
  * overwritten with each system's end state (where its status is OK,
  * W_TIME_TOL, NOCONV or MAXSTEPS).  offsets [n_sys+1] (int64, offsets[0] = 0),
  * t0, t_end [n_sys] and stats [n_sys] are host memory.  Every system has
- * 2 <= N_s <= 64 bodies; k_fix <= 8.
+ * N_s >= 2 bodies; k_fix <= 8.  Systems with N_s <= 64 run in the persistent
+ * launch; larger ones are integrated after it, one after the other, by
+ * mstar_integrate's driver (the same results as a mstar_integrate call, their
+ * own status in stats).
  * Returns MSTAR_OK when the launch completed (per-system results in stats),
  * MSTAR_E_INVAL (bad offsets, times or parameters), MSTAR_E_UNSUPPORTED
- * (N_s > 64, k_fix > 8, beta != 0, n_d > 2) or a device error. */
+ * (k_fix > 8, beta != 0, n_d > 2, accept_rule 1) or a device error. */
 int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
                           const double *m, double *x, double *v, const double *t0, const double *t_end,
                           mstar_batch_stats *stats);

@@ -1400,8 +1400,7 @@ int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const i
     for (int32_t s = 0; s < n_sys; ++s) {
         const int64_t n = off[s + 1] - off[s];
         if (n < 2) return fail(ctx, MSTAR_E_INVAL, "batch: system %d has %lld < 2 bodies", s, (long long)n);
-        if (n > kBatchMaxN)
-            return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: system %d has %lld > %d bodies", s, (long long)n, kBatchMaxN);
+        if (n > (1 << 24)) return fail(ctx, MSTAR_E_INVAL, "batch: system %d has %lld bodies", s, (long long)n);
         const double a = t0 ? t0[s] : 0.0;
         if (!std::isfinite(a) || !std::isfinite(t_end[s]) || a == t_end[s])
             return fail(ctx, MSTAR_E_INVAL, "batch: system %d needs finite t0 != t_end", s);
@@ -1431,7 +1430,11 @@ int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &c
     // two queues (whole-workgroup systems, single-wave systems), each by
     // decreasing cost estimate N^2 (ties by index)
     std::vector<int32_t> coop, wave;
-    for (int32_t s = 0; s < n_sys; ++s) ((off[s + 1] - off[s] > wmax) ? coop : wave).push_back(s);
+    for (int32_t s = 0; s < n_sys; ++s) {
+        const int64_t n = off[s + 1] - off[s];
+        if (n > kBatchMaxN) continue;   // integrated by the single-system driver after the launch
+        ((n > wmax) ? coop : wave).push_back(s);
+    }
     auto by_cost = [&](int32_t a, int32_t b) {
         const int64_t na = off[a + 1] - off[a], nb = off[b + 1] - off[b];
         return na != nb ? na > nb : a < b;
@@ -1584,16 +1587,53 @@ static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int3
         HIPCK(hipStreamSynchronize(ctx->stream));
     }
     memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
+    // systems beyond the kernel's kBatchMaxN bodies: mstar_integrate's driver,
+    // one after the other, in place, each with its own status
+    struct RowFeed final : StepFeed {
+        double *row = nullptr;
+        int64_t cap = 0, k = 0;
+        int accepted(double h) override {
+            if (row && k < cap) row[k] = h;
+            ++k;
+            return MSTAR_OK;
+        }
+    };
+    for (int32_t s = 0; s < n_sys; ++s) {
+        const int64_t o = offsets[s], n = offsets[s + 1] - o;
+        if (n <= kBatchMaxN) continue;
+        mstar_stats st{};
+        st.struct_size = sizeof(mstar_stats);
+        RowFeed feed;
+        if (H) {
+            feed.row = H + (size_t)s * (size_t)rec_cap;
+            feed.cap = rec_cap;
+        }
+        const int r = integrate_impl(ctx, params, n, m + o, x + 3 * o, v + 3 * o, t0 ? t0[s] : 0.0, t_end[s], &st, -1,
+                                     nullptr, nullptr, nullptr, H ? &feed : nullptr);
+        mstar_batch_stats &b = stats[s];
+        b.status = r;
+        b.reserved = 0;
+        b.steps_accepted = st.steps_accepted;
+        b.steps_rejected = st.steps_rejected;
+        b.force_evals = st.force_evals;
+        b.mst_rebuilds = st.mst_rebuilds;
+        b.topo_changes = st.topo_changes;
+        b.time_iters = st.time_iters;
+        b.t_reached = st.t_reached;
+        b.eps_last = st.eps_last;
+        b.h_next = st.h_next;
+        b.h_last = st.h_last;
+    }
     if (H) {   // the slots past a system's recorded steps were never written: NaN, not stale memory
         for (int32_t s = 0; s < n_sys; ++s)
             for (int64_t k = std::max<int64_t>(0, std::min<int64_t>(stats[s].steps_accepted, rec_cap)); k < rec_cap; ++k)
                 H[(size_t)s * (size_t)rec_cap + (size_t)k] = std::numeric_limits<double>::quiet_NaN();
     }
-    if (ctx->prof) {
+    if (ctx->prof) {   // the batched launch only
         double pairs = 0.0;
         for (int32_t s = 0; s < n_sys; ++s) {
             const double n = (double)(offsets[s + 1] - offsets[s]);
-            pairs += (double)stats[s].force_evals * n * (n - 1.0);
+            if (n <= kBatchMaxN) pairs += (double)stats[s].force_evals * n * (n - 1.0);
         }
         ctx->prof_launches += 1;
         ctx->prof_pairs += pairs;

@@ -394,9 +394,8 @@ def test_call_validation(ctx, M, small):
         with pytest.raises(M.MstarError) as e:
             ctx.integrate_batch(off, m, x, v, args["t_end"], p=args["p"])
         assert e.value.code == code, kw
-    big_m, big_x, big_v = ics.plummer(65, 5)
     with pytest.raises(M.MstarError) as e:
-        ctx.integrate_batch(np.array([0, 65]), big_m, big_x, big_v, T_SHORT)
+        ctx.integrate_batch(off, m, x, v, T_SHORT, p=M.params(accept_rule=1))
     assert e.value.code == M.E_UNSUPPORTED
     with pytest.raises(M.MstarError) as e:
         ctx.integrate_batch(np.array([0, 1, 3]), m[:3], x[:3], v[:3], T_SHORT)
@@ -404,6 +403,49 @@ def test_call_validation(ctx, M, small):
     with pytest.raises(M.MstarError) as e:
         ctx.set_batch_config(8, wave_lanes=24)
     assert e.value.code == M.E_INVAL
+
+
+def test_systems_beyond_the_kernel_use_the_single_system_driver(ctx, M):
+    """Systems of more than 64 bodies in a batch are integrated by
+    mstar_integrate's driver after the persistent launch: the same end state,
+    statistics and recorded steps as separate mstar_integrate_record calls,
+    bit for bit, next to the small systems of the same call (unchanged by the
+    larger ones' presence), on host and device arrays; a bad large system gets
+    its own status."""
+    import torch
+    sizes = [(5, 1), (100, 2), (12, 3), (257, 4)]
+    parts = [ics.plummer_with_central_mass(n - 1, seed) for n, seed in sizes]
+    off = np.concatenate([[0], np.cumsum([n for n, _ in sizes])]).astype(np.int64)
+    m = np.concatenate([q[0] for q in parts])
+    x = np.concatenate([q[1] for q in parts])
+    v = np.concatenate([q[2] for q in parts])
+    p = M.params(eta=1e-12)
+    t_end = 0.01
+    say("mixed batch: N = 5, 100, 12, 257")
+    xb, vb, st, H = ctx.integrate_batch_record(off, m, x, v, t_end, 64, p=p)
+    small_only = ctx.integrate_batch(np.array([0, 5]), m[:5], x[:5], v[:5], t_end, p=p)
+    assert np.array_equal(xb[:5], small_only[0]) and np.array_equal(vb[:5], small_only[1])
+    for s, (n, _) in enumerate(sizes):
+        o, e = int(off[s]), int(off[s + 1])
+        assert st["status"][s] == M.OK
+        if n <= 64:
+            continue
+        xs, vs, rc, ss, Hs = ctx.integrate_record(m[o:e], x[o:e], v[o:e], 0.0, t_end, 10 ** 6, p)
+        assert np.array_equal(xb[o:e], xs) and np.array_equal(vb[o:e], vs)
+        assert st["steps_accepted"][s] == ss["steps_accepted"] and st["force_evals"][s] == ss["force_evals"]
+        assert st["t_reached"][s] == ss["t_reached"]
+        k = min(len(Hs), 64)
+        assert np.array_equal(H[s, :k], Hs[:k]) and np.all(np.isnan(H[s, k:]))
+    # device arrays
+    T = lambda a: torch.tensor(a, device="cuda")
+    xd, vd, std = ctx.integrate_batch(off, T(m), T(x), T(v), t_end, p=p)
+    assert np.array_equal(xd.cpu().numpy(), xb) and np.array_equal(vd.cpu().numpy(), vb)
+    # a large system with a zero mass: its own error, the others unaffected
+    m2 = m.copy()
+    m2[int(off[3]) + 7] = 0.0
+    x2, v2, st2 = ctx.integrate_batch(off, m2, x, v, t_end, p=p)
+    assert st2["status"][3] == M.E_INVAL and all(st2["status"][s] == M.OK for s in range(3))
+    assert np.array_equal(x2[:int(off[3])], xb[:int(off[3])])
 
 
 def test_autotune(ctx, M):
