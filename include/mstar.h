@@ -74,7 +74,7 @@ typedef struct {
     double h_init;          /* > 0: first fictitious step; 0: automatic */
     int64_t max_steps;      /* GBS step attempts (accepted + rejected) */
     int32_t k_fix;          /* substep divisions n_k = 2k, k = 1..k_fix (Sec. 4.2); 2..16, default 8 */
-    int32_t n_d;            /* MST closeness N_d of eq. LCA; 0..4 here (0..2 in the batch call), default 2 */
+    int32_t n_d;            /* MST closeness N_d of eq. LCA; 0..4 here (0..2 in the batch kernel), default 2 */
     int32_t max_halvings;   /* consecutive rejections before MSTAR_E_NOCONV; default 60 */
     int32_t max_time_iter;  /* clipped end-time steps before MSTAR_W_TIME_TOL; default 8 */
     int32_t rebuild_every;  /* accepted steps between MST rebuilds (Sec. 3.5); default 1 */
@@ -82,7 +82,7 @@ typedef struct {
                                division count of Sec. 4.2, returning T_{k_fix,k_fix}; 1 at the first
                                k = 2..k_fix whose error measure eps_k <= eta (the serial rule of
                                Sec. 2.3), returning T_{k,k} and taking eq. hnext with that k.  All
-                               k_fix divisions are computed either way.  Not in the batched call. */
+                               k_fix divisions are computed either way.  Not in the batch kernel. */
 } mstar_params;
 
 /* Per-call statistics. */
@@ -316,13 +316,15 @@ typedef struct {
  * overwritten with each system's end state (where its status is OK,
  * W_TIME_TOL, NOCONV or MAXSTEPS).  offsets [n_sys+1] (int64, offsets[0] = 0),
  * t0, t_end [n_sys] and stats [n_sys] are host memory.  Every system has
- * N_s >= 2 bodies; k_fix <= 8.  Systems with N_s <= 64 run in the persistent
- * launch; larger ones are integrated after it, one after the other, by
+ * N_s >= 2 bodies.  Systems with N_s <= 64 run in the persistent launch;
+ * larger ones are integrated after it, one after the other, by
  * mstar_integrate's driver (the same results as a mstar_integrate call, their
- * own status in stats).
- * Returns MSTAR_OK when the launch completed (per-system results in stats),
+ * own status in stats).  Parameters the persistent kernel does not implement
+ * (k_fix > 8, beta != 0, n_d > 2, accept_rule 1) send every system through
+ * that driver, so the call takes the parameter sets mstar_integrate takes.
+ * Returns MSTAR_OK when the call completed (per-system results in stats),
  * MSTAR_E_INVAL (bad offsets, times or parameters), MSTAR_E_UNSUPPORTED
- * (k_fix > 8, beta != 0, n_d > 2, accept_rule 1) or a device error. */
+ * (as mstar_integrate: n_d > 4) or a device error. */
 int mstar_integrate_batch(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
                           const double *m, double *x, double *v, const double *t0, const double *t_end,
                           mstar_batch_stats *stats);
@@ -344,7 +346,9 @@ int mstar_batch_set_config(mstar_ctx *ctx, int32_t k_fix, const mstar_batch_conf
 /* Autotuner: time every launch shape (wave_lanes, wave_max_n, wgs_per_cu)
  * on this batch (same arguments as mstar_integrate_batch; x and v are not
  * modified; pass a shortened t_end to bound the cost), keep the fastest for
- * params->k_fix in the context and return it in *best. */
+ * params->k_fix in the context and return it in *best.  MSTAR_E_UNSUPPORTED
+ * for parameters the persistent kernel does not implement (k_fix > 8,
+ * beta != 0, n_d > 2, accept_rule 1). */
 int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,
                          const double *m, const double *x, const double *v, const double *t0,
                          const double *t_end, mstar_batch_config *best);

@@ -1386,15 +1386,23 @@ int ensure_batch(mstar_ctx *ctx, int64_t n_sys, int64_t n_tot) {
 }
 
 // Parameters, offsets and times of a batched call; *n_tot = offsets[n_sys].
+// The parameter sets the batched kernel implements; others go through the
+// single-system driver (mstar_integrate_batch) or are refused (autotune).
+const char *batch_kernel_gap(const mstar_params *p) {
+    if (ttl_on(p)) return "beta != 0 (TTL)";
+    if (p->n_d > 2) return "n_d > 2";
+    if (p->accept_rule != 0) return "accept_rule 1";
+    if (p->k_fix > kBatchMaxKF) return "k_fix > 8";
+    return nullptr;
+}
+
 int batch_validate(mstar_ctx *ctx, const mstar_params *p, int32_t n_sys, const int64_t *off, const double *t0,
-                   const double *t_end, int64_t *n_tot) {
+                   const double *t_end, int64_t *n_tot, bool kernel_only) {
     int rc = check_params(ctx, p);
     if (rc) return rc;
-    if (ttl_on(p)) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: beta != 0 (TTL) is not implemented");
-    if (p->n_d > 2) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: n_d > 2 is not implemented");
-    if (p->accept_rule != 0) return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: accept_rule 1 is not implemented");
-    if (p->k_fix > kBatchMaxKF)
-        return fail(ctx, MSTAR_E_UNSUPPORTED, "batch: k_fix > %d is not implemented", kBatchMaxKF);
+    if (kernel_only)
+        if (const char *g = batch_kernel_gap(p))
+            return fail(ctx, MSTAR_E_UNSUPPORTED, "batch kernel: %s is not implemented", g);
     if (n_sys < 1 || !off || !t_end) return fail(ctx, MSTAR_E_INVAL, "batch: need n_sys >= 1, offsets and t_end");
     if (off[0] != 0) return fail(ctx, MSTAR_E_INVAL, "batch: offsets[0] must be 0");
     for (int32_t s = 0; s < n_sys; ++s) {
@@ -1539,56 +1547,62 @@ static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int3
     if (!ctx) return MSTAR_E_INVAL;
     ctx->err.clear();
     int64_t n_tot = 0;
-    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot);
+    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot, false);
     if (rc) return rc;
     if (!m || !x || !v || !stats) return fail(ctx, MSTAR_E_INVAL, "batch: null array");
     if (H && (rec_cap < 1 || rec_cap > ((int64_t)1 << 40) / n_sys))
         return fail(ctx, MSTAR_E_INVAL, "batch_record: bad record capacity");
     (void)hipSetDevice(ctx->device);
-    if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
-    double *hrec = nullptr;
-    if (H) {   // device record of the accepted steps, kept in the context
-        const size_t need = (size_t)n_sys * (size_t)rec_cap;
-        if (need > ctx->b_hrec_cap) {
-            if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
-            ctx->b_hrec = nullptr;
-            ctx->b_hrec_cap = 0;
-            if (hipMalloc((void **)&ctx->b_hrec, sizeof(double) * need) != hipSuccess) {
-                ctx->b_hrec = nullptr;
-                return fail(ctx, MSTAR_E_NOMEM, "batch_record: device allocation failed");
-            }
-            ctx->b_hrec_cap = need;
-        }
-        hrec = ctx->b_hrec;
-    }
-    const uint32_t flags = params->flags;
-    const double *md = m;
-    double *xd = x, *vd = v;
-    if (!is_dev(flags)) {
-        HIPCK(hipMemcpyAsync(ctx->b_m, m, sizeof(double) * n_tot, hipMemcpyHostToDevice, ctx->stream));
-        HIPCK(hipMemcpyAsync(ctx->b_x, x, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
-        HIPCK(hipMemcpyAsync(ctx->b_v, v, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
-        md = ctx->b_m;
-        xd = ctx->b_x;
-        vd = ctx->b_v;
-    }
+    // parameters the batched kernel does not implement: every system takes
+    // the single-system driver below
+    const bool in_kernel = batch_kernel_gap(params) == nullptr;
     double ms = 0.0;
-    if ((rc = batch_run(ctx, params, ctx->bcfg[params->k_fix], n_sys, offsets, md, xd, vd, t0, t_end, &ms, hrec,
-                        rec_cap)))
-        return rc;
-    if (!is_dev(flags)) {
-        HIPCK(hipMemcpyAsync(x, ctx->b_x, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
-        HIPCK(hipMemcpyAsync(v, ctx->b_v, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
-        HIPCK(hipStreamSynchronize(ctx->stream));
+    if (in_kernel) {
+        if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
+        double *hrec = nullptr;
+        if (H) {   // device record of the accepted steps, kept in the context
+            const size_t need = (size_t)n_sys * (size_t)rec_cap;
+            if (need > ctx->b_hrec_cap) {
+                if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);
+                ctx->b_hrec = nullptr;
+                ctx->b_hrec_cap = 0;
+                if (hipMalloc((void **)&ctx->b_hrec, sizeof(double) * need) != hipSuccess) {
+                    ctx->b_hrec = nullptr;
+                    return fail(ctx, MSTAR_E_NOMEM, "batch_record: device allocation failed");
+                }
+                ctx->b_hrec_cap = need;
+            }
+            hrec = ctx->b_hrec;
+        }
+        const uint32_t flags = params->flags;
+        const double *md = m;
+        double *xd = x, *vd = v;
+        if (!is_dev(flags)) {
+            HIPCK(hipMemcpyAsync(ctx->b_m, m, sizeof(double) * n_tot, hipMemcpyHostToDevice, ctx->stream));
+            HIPCK(hipMemcpyAsync(ctx->b_x, x, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
+            HIPCK(hipMemcpyAsync(ctx->b_v, v, sizeof(double) * 3 * n_tot, hipMemcpyHostToDevice, ctx->stream));
+            md = ctx->b_m;
+            xd = ctx->b_x;
+            vd = ctx->b_v;
+        }
+        if ((rc = batch_run(ctx, params, ctx->bcfg[params->k_fix], n_sys, offsets, md, xd, vd, t0, t_end, &ms, hrec,
+                            rec_cap)))
+            return rc;
+        if (!is_dev(flags)) {
+            HIPCK(hipMemcpyAsync(x, ctx->b_x, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCK(hipMemcpyAsync(v, ctx->b_v, sizeof(double) * 3 * n_tot, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCK(hipStreamSynchronize(ctx->stream));
+        }
+        if (H) {
+            HIPCK(hipMemcpyAsync(H, hrec, sizeof(double) * (size_t)n_sys * (size_t)rec_cap, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+            HIPCK(hipStreamSynchronize(ctx->stream));
+        }
+        memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
     }
-    if (H) {
-        HIPCK(hipMemcpyAsync(H, hrec, sizeof(double) * (size_t)n_sys * (size_t)rec_cap, hipMemcpyDeviceToHost,
-                             ctx->stream));
-        HIPCK(hipStreamSynchronize(ctx->stream));
-    }
-    memcpy(stats, ctx->h_bstat, sizeof(BatchStat) * n_sys);
-    // systems beyond the kernel's kBatchMaxN bodies: mstar_integrate's driver,
-    // one after the other, in place, each with its own status
+    // systems beyond the kernel's kBatchMaxN bodies, or all of them when the
+    // kernel does not implement the parameters: mstar_integrate's driver, one
+    // after the other, in place, each with its own status
     struct RowFeed final : StepFeed {
         double *row = nullptr;
         int64_t cap = 0, k = 0;
@@ -1600,7 +1614,7 @@ static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int3
     };
     for (int32_t s = 0; s < n_sys; ++s) {
         const int64_t o = offsets[s], n = offsets[s + 1] - o;
-        if (n <= kBatchMaxN) continue;
+        if (in_kernel && n <= kBatchMaxN) continue;
         mstar_stats st{};
         st.struct_size = sizeof(mstar_stats);
         RowFeed feed;
@@ -1629,7 +1643,7 @@ static int integrate_batch_impl(mstar_ctx *ctx, const mstar_params *params, int3
             for (int64_t k = std::max<int64_t>(0, std::min<int64_t>(stats[s].steps_accepted, rec_cap)); k < rec_cap; ++k)
                 H[(size_t)s * (size_t)rec_cap + (size_t)k] = std::numeric_limits<double>::quiet_NaN();
     }
-    if (ctx->prof) {   // the batched launch only
+    if (ctx->prof && in_kernel) {   // the batched launch only
         double pairs = 0.0;
         for (int32_t s = 0; s < n_sys; ++s) {
             const double n = (double)(offsets[s + 1] - offsets[s]);
@@ -1677,7 +1691,7 @@ int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_s
     if (!ctx) return MSTAR_E_INVAL;
     ctx->err.clear();
     int64_t n_tot = 0;
-    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot);
+    int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot, true);
     if (rc) return rc;
     if (!m || !x || !v || !best) return fail(ctx, MSTAR_E_INVAL, "autotune: null argument");
     (void)hipSetDevice(ctx->device);

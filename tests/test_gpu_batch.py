@@ -383,9 +383,8 @@ def test_call_validation(ctx, M, small):
     off, m, x, v = small
     say("validation")
     cases = [
-        (dict(p=M.params(k_fix=9)), M.E_UNSUPPORTED),
-        (dict(p=M.params(beta=1.0)), M.E_UNSUPPORTED),
-        (dict(p=M.params(n_d=3)), M.E_UNSUPPORTED),
+        (dict(p=M.params(n_d=5)), M.E_UNSUPPORTED),
+        (dict(p=M.params(k_fix=17)), M.E_INVAL),
         (dict(t_end=0.0), M.E_INVAL),
     ]
     for kw, code in cases:
@@ -394,9 +393,6 @@ def test_call_validation(ctx, M, small):
         with pytest.raises(M.MstarError) as e:
             ctx.integrate_batch(off, m, x, v, args["t_end"], p=args["p"])
         assert e.value.code == code, kw
-    with pytest.raises(M.MstarError) as e:
-        ctx.integrate_batch(off, m, x, v, T_SHORT, p=M.params(accept_rule=1))
-    assert e.value.code == M.E_UNSUPPORTED
     with pytest.raises(M.MstarError) as e:
         ctx.integrate_batch(np.array([0, 1, 3]), m[:3], x[:3], v[:3], T_SHORT)
     assert e.value.code == M.E_INVAL
@@ -446,6 +442,37 @@ def test_systems_beyond_the_kernel_use_the_single_system_driver(ctx, M):
     x2, v2, st2 = ctx.integrate_batch(off, m2, x, v, t_end, p=p)
     assert st2["status"][3] == M.E_INVAL and all(st2["status"][s] == M.OK for s in range(3))
     assert np.array_equal(x2[:int(off[3])], xb[:int(off[3])])
+
+
+@pytest.mark.parametrize("kw", [dict(k_fix=9), dict(beta=1.0), dict(n_d=3), dict(accept_rule=1)],
+                         ids=["k_fix9", "ttl", "n_d3", "accept_rule1"])
+def test_parameters_beyond_the_kernel_use_the_single_system_driver(ctx, M, small, kw):
+    """Parameter sets the persistent kernel does not implement send every
+    system of the call through mstar_integrate's driver: end states,
+    statistics and recorded steps equal separate mstar_integrate_record calls
+    bit for bit, on host and device arrays.  The autotuner, which times the
+    kernel, refuses them."""
+    import torch
+    off, m, x, v = small
+    o2, m2, x2, v2 = sub_batch(off, m, x, v, list(range(6)))
+    p = M.params(eta=1e-12, **kw)
+    say(f"batch with {kw}: {len(o2) - 1} systems")
+    xb, vb, st, H = ctx.integrate_batch_record(o2, m2, x2, v2, T_SHORT, 32, p=p)
+    for s in range(len(o2) - 1):
+        o, e = int(o2[s]), int(o2[s + 1])
+        xs, vs, rc, ss, Hs = ctx.integrate_record(m2[o:e], x2[o:e], v2[o:e], 0.0, T_SHORT, 10 ** 6, p)
+        assert st["status"][s] == M.OK and rc == M.OK
+        assert np.array_equal(xb[o:e], xs) and np.array_equal(vb[o:e], vs)
+        for f in ("steps_accepted", "steps_rejected", "force_evals", "t_reached", "h_next"):
+            assert st[f][s] == ss[f], f
+        k = min(len(Hs), 32)
+        assert np.array_equal(H[s, :k], Hs[:k]) and np.all(np.isnan(H[s, k:]))
+    T = lambda a: torch.tensor(a, device="cuda")
+    xd, vd, _ = ctx.integrate_batch(o2, T(m2), T(x2), T(v2), T_SHORT, p=p)
+    assert np.array_equal(xd.cpu().numpy(), xb) and np.array_equal(vd.cpu().numpy(), vb)
+    with pytest.raises(M.MstarError) as e:
+        ctx.batch_autotune(o2, m2, x2, v2, T_SHORT, p=p)
+    assert e.value.code == M.E_UNSUPPORTED
 
 
 def test_autotune(ctx, M):
