@@ -509,6 +509,48 @@ def bench_timing(M, ctx, sizes=None, seeds=3, eta=1e-6, sweep_n=1129, sweep_etas
     return out
 
 
+def bench_step_control(M, ctx, safety=(0.6, 0.85, 0.9, 0.95, 1.0), etas=(1e-6, 1e-10, 1e-13)):
+    """Work of the step-size controller (eq. hnext) against its safety factor
+    a_GBS, at three tolerances: force evaluations, wall time, rejections and
+    |dE/E| of whole integrations (three N = 1129 and three N = 4833 timing
+    clusters over 0.1 Myr; plummer5000_binary to t = 0.02; plummer1000_bh to
+    t = 0.2).  Below eta = 1e-11 a_GBS < 0.8 is skipped: the controller then
+    aims at eps = eta a_GBS^(2 k_fix - 1), below the rounding floor of the
+    error measure, and the steps shrink without end."""
+    import ics
+    allow = (M.OK, M.W_TIME_TOL)
+    cases = []
+    for n in (1129, 4833):
+        cases.append((f"timing{n}", [ics.timing_cluster(n, s)[:3] for s in (1, 2, 3)], ics.TIMING_T_END))
+    for name, te in (("plummer5000_binary", 0.02), ("plummer1000_bh", 0.2)):
+        cases.append((name, [ics.workload(name)[:3]], te))
+    rows = []
+    for name, systems, te in cases:
+        e0 = [_energy(m, x, v) for m, x, v in systems]
+        for eta in etas:
+            for a in safety:
+                if eta < 1e-11 and a < 0.8:
+                    continue
+                wall = 0.0
+                acc = rej = fe = 0
+                de = 0.0
+                for (m, x, v), e in zip(systems, e0):
+                    ctx.integrate(m, x, v, 0.0, te, M.params(eta=eta, a_gbs=a, max_steps=1),
+                                  allow=allow + (M.E_MAXSTEPS,))      # sizes the context's buffers
+                    t0 = time.perf_counter()
+                    x1, v1, rc, st = ctx.integrate(m, x, v, 0.0, te, M.params(eta=eta, a_gbs=a), allow=allow)
+                    wall += time.perf_counter() - t0
+                    acc += st["steps_accepted"]
+                    rej += st["steps_rejected"]
+                    fe += st["force_evals"]
+                    de = max(de, abs(_energy(m, x1, v1) / e - 1.0))
+                rows.append({"workload": name, "eta": eta, "a_gbs": a, "wall_s": wall, "steps_accepted": acc,
+                             "steps_rejected": rej, "force_evals": fe, "max_abs_dE_over_E": de})
+                print(f"[bench] step control {name} eta={eta:.0e} a_gbs={a}: {fe} force evals, "
+                      f"{rej}/{acc + rej} rejected, {wall:.3f} s", file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,6 +572,8 @@ def main():
     ap.add_argument("--timing-only", action="store_true",
                     help="only the cluster timing tests (Sec. 5.4: 20 sizes x 3 seeds, 0.1 Myr, and the eta sweep)")
     ap.add_argument("--timing-max-n", type=int, default=10000)
+    ap.add_argument("--step-control-only", action="store_true",
+                    help="only the controller's safety-factor study (eq. hnext; about two minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -566,6 +610,9 @@ def main():
         return
     if args.mst_only:
         print(json.dumps({"mst": bench_mst(M, ctx)}), flush=True)
+        return
+    if args.step_control_only:
+        print(json.dumps({"step_control": bench_step_control(M, ctx)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(M, ctx, threads, not args.no_cpu)}), flush=True)
