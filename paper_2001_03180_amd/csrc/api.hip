@@ -87,6 +87,9 @@ struct mstar_ctx {
     int mut_wps = 3;                   // waves per SIMD the mutual kernel's work is split for
     int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
     int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
+    int div_chains = 1;                // independent chains of division lanes (1 or 2)
+    hipStream_t div_s2 = nullptr;      // stream of the second chain
+    hipEvent_t div_ev[2] = {nullptr, nullptr};   // fork, join
     DcBuf dc{};                        // divide-and-conquer tree builder buffers
     int dc_cap_n = 0;                  // N they are sized for (0: none)
     bool ext_on = false;               // an external field applies to the running integration
@@ -476,7 +479,8 @@ int load_tree(mstar_ctx *ctx, uint32_t flags, int64_t n, const int32_t *parent) 
     return MSTAR_OK;
 }
 
-int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, const FLay &f, bool om) {
+int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, const FLay &f, bool om, hipStream_t st = nullptr) {
+    if (!st) st = ctx->stream;
     if (ctx->prof) {
         if (ctx->ev_used == ctx->ev.size()) {
             hipEvent_t a, b;
@@ -486,9 +490,9 @@ int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, const FLay &f, bool o
         }
         const size_t k = ctx->ev_used++;
         auto &e = ctx->ev[k];
-        HIPCK(hipEventRecord(e.first, ctx->stream));
-        launch_force(ctx->d, ctx->stream, sl, nd, f, om);
-        HIPCK(hipEventRecord(e.second, ctx->stream));
+        HIPCK(hipEventRecord(e.first, st));
+        launch_force(ctx->d, st, sl, nd, f, om);
+        HIPCK(hipEventRecord(e.second, st));
         const double pairs = (double)sl.nact * (double)ctx->d.n * (double)(ctx->d.n - 1);
         if (ctx->ev_kind.size() < ctx->ev.size()) {
             ctx->ev_kind.resize(ctx->ev.size());
@@ -499,7 +503,7 @@ int prof_force(mstar_ctx *ctx, const SlotList &sl, int nd, const FLay &f, bool o
         ctx->prof_launches++;
         ctx->prof_pairs += pairs;
     } else {
-        launch_force(ctx->d, ctx->stream, sl, nd, f, om);
+        launch_force(ctx->d, st, sl, nd, f, om);
     }
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -561,18 +565,38 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
     const int cap = ndiv > 0 ? nlist[order[0]] : 0;
     int lane_len[kMaxDiv], nlanes = 0;
     int start[kMaxDiv];   // stage at which each division's first drift runs
+    int lane_of[kMaxDiv];
     for (int q = 0; q < ndiv; ++q) {
         const int k = order[q];
         int l = 0;
         while (l < nlanes && lane_len[l] + nlist[k] > cap) ++l;
         if (l == nlanes) lane_len[nlanes++] = 0;
         start[k] = 1 + lane_len[l];
+        lane_of[k] = l;
         lane_len[l] += nlist[k];
     }
+    // with two chains, lanes go (longest first) to the chain with fewer force
+    // evaluations; the chains share no slot, so their launches run on two
+    // streams, each one's kicks and drifts beside the other's force launches
+    const int nch = (ctx->div_chains > 1 && nlanes > 1) ? 2 : 1;
+    int chain_of_lane[kMaxDiv];
+    long load[2] = {0, 0};
+    for (int l = 0; l < nlanes; ++l) {
+        const int c = (nch == 2 && load[1] < load[0]) ? 1 : 0;
+        chain_of_lane[l] = c;
+        load[c] += lane_len[l];
+    }
+    if (nch == 2) {
+        HIPCK(hipEventRecord(ctx->div_ev[0], ctx->stream));
+        HIPCK(hipStreamWaitEvent(ctx->div_s2, ctx->div_ev[0], 0));
+    }
     const int last = cap;
+    for (int c = 0; c < nch; ++c)
     for (int t = 1; t <= last + 1; ++t) {
+        hipStream_t st = c ? ctx->div_s2 : ctx->stream;
         SlotList dr{}, fk{};
         for (int k = 0; k < ndiv; ++k) {
+            if (chain_of_lane[lane_of[k]] != c) continue;
             const int s = t - start[k] + 1;   // local stage of division k
             const int nk = nlist[k];
             if (s < 1 || s > nk + 1) continue;
@@ -582,14 +606,18 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
             dr.nact++;
             if (s <= nk) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nk; fk.nact++; }
         }
-        if (dr.nact) launch_drift(d, ctx->stream, dr, ttl_of(p), ctx->ext_on);
+        if (dr.nact) launch_drift(d, st, dr, ttl_of(p), ctx->ext_on);
         if (!fk.nact) continue;
         const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p));
-        int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p));
+        int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p), st);
         if (rc) return rc;
-        if (ctx->ext_on) launch_ext(d, ctx->stream, fk, 0);
-        launch_kick(d, ctx->stream, fk, f, p->G, ttl_of(p), ctx->ext_on);
+        if (ctx->ext_on) launch_ext(d, st, fk, 0);
+        launch_kick(d, st, fk, f, p->G, ttl_of(p), ctx->ext_on);
         if (nforce) *nforce += fk.nact;
+    }
+    if (nch == 2) {
+        HIPCK(hipEventRecord(ctx->div_ev[1], ctx->div_s2));
+        HIPCK(hipStreamWaitEvent(ctx->stream, ctx->div_ev[1], 0));
     }
     HIPCK(hipGetLastError());
     return MSTAR_OK;
@@ -829,6 +857,18 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 8) ctx->mut_wps = v;
     }
+    // division lanes in one chain of launches or two concurrent ones
+    // (MSTAR_DIV_CHAINS = 1 | 2)
+    if (const char *e = std::getenv("MSTAR_DIV_CHAINS")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2) ctx->div_chains = v;
+    }
+    if (hipStreamCreateWithFlags(&ctx->div_s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->div_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->div_ev[1], hipEventDisableTiming) != hipSuccess) {
+        mstar_destroy(ctx);
+        return MSTAR_E_DEVICE;
+    }
     if (hipHostMalloc((void **)&ctx->h_blk, sizeof(CtlBlock), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         mstar_destroy(ctx);
@@ -868,6 +908,12 @@ void mstar_destroy(mstar_ctx *ctx) {
     for (hipEvent_t e : ctx->a_ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->a_s2) (void)hipStreamDestroy(ctx->a_s2);
+    if (ctx->div_s2) {
+        (void)hipStreamSynchronize(ctx->div_s2);
+        (void)hipStreamDestroy(ctx->div_s2);
+    }
+    for (hipEvent_t e : ctx->div_ev)
+        if (e) (void)hipEventDestroy(e);
     for (void *p : ctx->b_allocs) (void)hipFree(p);
     if (ctx->h_bstat) (void)hipHostFree(ctx->h_bstat);
     if (ctx->b_hrec) (void)hipFree(ctx->b_hrec);

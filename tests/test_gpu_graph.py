@@ -114,3 +114,46 @@ def test_unfinished_rebuild_repeats_the_step_exactly(M):
         assert np.array_equal(a[0], r[0]) and np.array_equal(a[1], r[1])
         for k in ("steps_accepted", "steps_rejected", "mst_rebuilds", "t_reached"):
             assert a[3][k] == r[3][k], k
+
+
+def test_two_division_chains(M):
+    """MSTAR_DIV_CHAINS=2 (here with MSTAR_MUT_WPS=1) runs the division lanes
+    as two chains of launches on two streams.  Graph replay, which captures
+    the fork and the join, equals eager launch bit for bit.  Against the
+    one-chain schedule the force partials are grouped differently, so the
+    agreement is to rounding: the same step counts, end states within 1e-10
+    of the system's extent, the same energy error to 1e-13."""
+    import os
+    from bench import _energy
+    m, x, v, _ = ics.workload("plummer5000_binary")
+    te = 2e-3
+    p = dict(eta=1e-13)
+    one = M.Context(0)
+    keys = ("MSTAR_DIV_CHAINS", "MSTAR_MUT_WPS")
+    old = {k: os.environ.get(k) for k in keys}
+    os.environ.update(MSTAR_DIV_CHAINS="2", MSTAR_MUT_WPS="1")
+    try:
+        two = M.Context(0)
+    finally:
+        for k in keys:
+            if old[k] is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = old[k]
+    try:
+        say("plummer5000_binary to t=2e-3: one chain, two chains (graph), two chains (eager)")
+        a = one.integrate(m, x, v, 0.0, te, M.params(**p))
+        g = two.integrate(m, x, v, 0.0, te, M.params(**p))
+        e = two.integrate(m, x, v, 0.0, te, M.params(flags=M.EAGER, **p))
+        assert g[3]["steps_accepted"] + g[3]["steps_rejected"] > 10
+        _same(g, e)
+        for f in ("steps_accepted", "steps_rejected", "force_evals"):
+            assert g[3][f] == a[3][f], f
+        ext = np.ptp(a[0], axis=0).max()
+        assert np.abs(g[0] - a[0]).max() <= 1e-10 * ext
+        assert np.abs(g[1] - a[1]).max() <= 1e-10 * np.ptp(a[1], axis=0).max()
+        e0 = _energy(m, x, v)
+        assert abs(_energy(m, g[0], g[1]) / e0 - _energy(m, a[0], a[1]) / e0) <= 1e-13
+    finally:
+        one.close()
+        two.close()
