@@ -88,10 +88,19 @@ def test_integrate_accept_rule_one(ctx, orc, M, n, eta, t_end):
     assert np.abs(xg - xo).max() <= 1e-10 * R and np.abs(vg - vo).max() <= 1e-10 * Vs
 
 
-def test_batch_rejects_accept_rule_one(ctx, M):
+def test_batch_accept_rule_one_takes_the_single_system_driver(ctx, M):
+    """The batch kernel implements accept_rule 0 only: a batch call with rule 1
+    integrates each system with the single-system driver (the same result as a
+    separate call), and the autotuner, which times the kernel, refuses it."""
     off, mb, xb, vb = ics.batch_subsystems(n_sys=2, seed=401, n_max=8)
+    p = M.params(accept_rule=1)
+    xg, vg, st = ctx.integrate_batch(off, mb, xb, vb, 1e-4, p=p)
+    for s in range(2):
+        o, e = int(off[s]), int(off[s + 1])
+        xs, vs, rc, ss = ctx.integrate(mb[o:e], xb[o:e], vb[o:e], 0.0, 1e-4, M.params(accept_rule=1))
+        assert st["status"][s] == rc and np.array_equal(xg[o:e], xs) and np.array_equal(vg[o:e], vs)
     with pytest.raises(M.MstarError) as e:
-        ctx.integrate_batch(off, mb, xb, vb, 1e-4, p=M.params(accept_rule=1))
+        ctx.batch_autotune(off, mb, xb, vb, 1e-4, p=p)
     assert e.value.code == M.E_UNSUPPORTED
 
 

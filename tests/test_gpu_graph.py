@@ -121,9 +121,14 @@ def test_two_division_chains(M):
     as two chains of launches on two streams.  Graph replay, which captures
     the fork and the join, equals eager launch bit for bit.  Against the
     one-chain schedule the force partials are grouped differently, so the
-    agreement is to rounding: the same step counts, end states within 1e-10
-    of the system's extent, the same energy error to 1e-13."""
+    agreement is to rounding: the step lengths differ in their last bits, and
+    the end-time iteration may take a step more or less; both reach t_end,
+    with end states within 1e-10 of the system's extent and the same energy
+    error to 1e-13."""
     import os
+    import torch
+    if not torch.cuda.is_available():   # torch first: it brings up the device runtime
+        pytest.skip("no GPU")
     from bench import _energy
     m, x, v, _ = ics.workload("plummer5000_binary")
     te = 2e-3
@@ -147,13 +152,18 @@ def test_two_division_chains(M):
         e = two.integrate(m, x, v, 0.0, te, M.params(flags=M.EAGER, **p))
         assert g[3]["steps_accepted"] + g[3]["steps_rejected"] > 10
         _same(g, e)
-        for f in ("steps_accepted", "steps_rejected", "force_evals"):
-            assert g[3][f] == a[3][f], f
+        say(f"steps (accepted + rejected): one chain {a[3]['steps_accepted']} + {a[3]['steps_rejected']}, "
+            f"two chains {g[3]['steps_accepted']} + {g[3]['steps_rejected']}")
+        assert abs(g[3]["steps_accepted"] - a[3]["steps_accepted"]) <= 2
+        for r in (a, g):
+            assert abs(r[3]["t_reached"] - te) <= 1e-12 * te
         ext = np.ptp(a[0], axis=0).max()
-        assert np.abs(g[0] - a[0]).max() <= 1e-10 * ext
-        assert np.abs(g[1] - a[1]).max() <= 1e-10 * np.ptp(a[1], axis=0).max()
+        dx = np.abs(g[0] - a[0]).max() / ext
+        dv = np.abs(g[1] - a[1]).max() / np.ptp(a[1], axis=0).max()
         e0 = _energy(m, x, v)
-        assert abs(_energy(m, g[0], g[1]) / e0 - _energy(m, a[0], a[1]) / e0) <= 1e-13
+        de = abs(_energy(m, g[0], g[1]) / e0 - _energy(m, a[0], a[1]) / e0)
+        say(f"state difference {dx:.2e} (x), {dv:.2e} (v) of the extents; dE/E difference {de:.1e}")
+        assert dx <= 1e-10 and dv <= 1e-10 and de <= 1e-13
     finally:
         one.close()
         two.close()
