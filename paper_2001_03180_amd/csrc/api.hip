@@ -591,34 +591,40 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
         HIPCK(hipStreamWaitEvent(ctx->div_s2, ctx->div_ev[0], 0));
     }
     const int last = cap;
-    for (int c = 0; c < nch; ++c)
-    for (int t = 1; t <= last + 1; ++t) {
+    // the stages of chain c, launched on its stream
+    auto run_chain = [&](int c) -> int {
         hipStream_t st = c ? ctx->div_s2 : ctx->stream;
-        SlotList dr{}, fk{};
-        for (int k = 0; k < ndiv; ++k) {
-            if (chain_of_lane[lane_of[k]] != c) continue;
-            const int s = t - start[k] + 1;   // local stage of division k
-            const int nk = nlist[k];
-            if (s < 1 || s > nk + 1) continue;
-            dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk;
-            dr.half[dr.nact] = (s == 1 || s == nk + 1) ? 1 : 0;
-            dr.first[dr.nact] = (s == 1) ? 1 : 0;
-            dr.nact++;
-            if (s <= nk) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nk; fk.nact++; }
+        for (int t = 1; t <= last + 1; ++t) {
+            SlotList dr{}, fk{};
+            for (int k = 0; k < ndiv; ++k) {
+                if (chain_of_lane[lane_of[k]] != c) continue;
+                const int s = t - start[k] + 1;   // local stage of division k
+                const int nk = nlist[k];
+                if (s < 1 || s > nk + 1) continue;
+                dr.slot[dr.nact] = k; dr.nsub[dr.nact] = nk;
+                dr.half[dr.nact] = (s == 1 || s == nk + 1) ? 1 : 0;
+                dr.first[dr.nact] = (s == 1) ? 1 : 0;
+                dr.nact++;
+                if (s <= nk) { fk.slot[fk.nact] = k; fk.nsub[fk.nact] = nk; fk.nact++; }
+            }
+            if (dr.nact) launch_drift(d, st, dr, ttl_of(p), ctx->ext_on);
+            if (!fk.nact) continue;
+            const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p));
+            int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p), st);
+            if (rc) return rc;
+            if (ctx->ext_on) launch_ext(d, st, fk, 0);
+            launch_kick(d, st, fk, f, p->G, ttl_of(p), ctx->ext_on);
+            if (nforce) *nforce += fk.nact;
         }
-        if (dr.nact) launch_drift(d, st, dr, ttl_of(p), ctx->ext_on);
-        if (!fk.nact) continue;
-        const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p));
-        int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p), st);
-        if (rc) return rc;
-        if (ctx->ext_on) launch_ext(d, st, fk, 0);
-        launch_kick(d, st, fk, f, p->G, ttl_of(p), ctx->ext_on);
-        if (nforce) *nforce += fk.nact;
-    }
-    if (nch == 2) {
+        return MSTAR_OK;
+    };
+    int rc = MSTAR_OK;
+    for (int c = 0; c < nch && !rc; ++c) rc = run_chain(c);
+    if (nch == 2) {   // join even after an error: a capture must not end with the fork open
         HIPCK(hipEventRecord(ctx->div_ev[1], ctx->div_s2));
         HIPCK(hipStreamWaitEvent(ctx->stream, ctx->div_ev[1], 0));
     }
+    if (rc) return rc;
     HIPCK(hipGetLastError());
     return MSTAR_OK;
 }
