@@ -19,8 +19,9 @@
  * where the paper is silent are marked READING.  Parity unpinned against the
  * paper (no printed value or closed form fixes them; they are checked
  * oracle-vs-GPU only): the step-controller constants a_GBS, f_min, f_max and
- * the first-step factor q, the TTL weights omega_ij, and the rule that gives a
- * new MST edge its vector at a rebuild.
+ * the first-step factor q, and the TTL weights omega_ij.  The error measure
+ * and the rule that gives a new MST edge its vector at a rebuild are pinned by
+ * the CPU tests (closed-form Kepler errors; persisting edges keep their bits).
  */
 #include <math.h>
 #include <stdint.h>
