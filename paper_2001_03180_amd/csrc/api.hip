@@ -1503,10 +1503,15 @@ int batch_run(mstar_ctx *ctx, const mstar_params *p, const mstar_batch_config &c
     std::sort(wave.begin(), wave.end(), by_cost);
     std::vector<int32_t> order(coop);
     order.insert(order.end(), wave.begin(), wave.end());
+    if (order.empty()) {   // every system is left to the single-system driver
+        if (kernel_ms) *kernel_ms = 0.0;
+        return MSTAR_OK;
+    }
     std::vector<double> h0;
     if (t0) h0.assign(t0, t0 + n_sys);
     HIPCK(hipMemcpyAsync(ctx->b_off, off, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice, ctx->stream));
-    HIPCK(hipMemcpyAsync(ctx->b_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->b_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
     HIPCK(hipMemcpyAsync(ctx->b_te, t_end, sizeof(double) * n_sys, hipMemcpyHostToDevice, ctx->stream));
     if (t0) HIPCK(hipMemcpyAsync(ctx->b_t0, h0.data(), sizeof(double) * n_sys, hipMemcpyHostToDevice, ctx->stream));
 

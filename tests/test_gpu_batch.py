@@ -442,6 +442,15 @@ def test_systems_beyond_the_kernel_use_the_single_system_driver(ctx, M):
     x2, v2, st2 = ctx.integrate_batch(off, m2, x, v, t_end, p=p)
     assert st2["status"][3] == M.E_INVAL and all(st2["status"][s] == M.OK for s in range(3))
     assert np.array_equal(x2[:int(off[3])], xb[:int(off[3])])
+    # only large systems: nothing for the persistent kernel
+    say("batch of large systems only: N = 100, 257")
+    o3 = np.array([0, 100, 357], dtype=np.int64)
+    sl = np.r_[int(off[1]):int(off[2]), int(off[3]):int(off[4])]
+    x3, v3, st3, H3 = ctx.integrate_batch_record(o3, m[sl], x[sl], v[sl], t_end, 64, p=p)
+    assert np.array_equal(x3[:100], xb[int(off[1]):int(off[2])]) and np.array_equal(x3[100:], xb[int(off[3]):])
+    assert np.array_equal(v3[:100], vb[int(off[1]):int(off[2])]) and np.array_equal(v3[100:], vb[int(off[3]):])
+    assert np.array_equal(st3, st[[1, 3]])
+    assert np.array_equal(H3, H[[1, 3]], equal_nan=True)
 
 
 @pytest.mark.parametrize("kw", [dict(k_fix=9), dict(beta=1.0), dict(n_d=3), dict(accept_rule=1)],
