@@ -56,7 +56,7 @@ BATCH_T_END = 1e-2
 BATCH_ETA = 1e-12
 # HBM bytes per k_force launch on this workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a plain 256 MiB copy;
-# valid only for the force-kernel sources with this hash.
+# valid only for the force-kernel and launch-planning sources with this hash.
 # (per force kernel kind; None where not measured for the current sources)
 FORCE_TRAFFIC = {
     1: {"sha256": "55f013ec72b50b9bc43aafa6617b0dc30f927edc65ec64beeb303c02843272fb",
@@ -69,7 +69,7 @@ FORCE_TRAFFIC = {
 def _force_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels_force.hip", "pair.h", "common.h"):
+    for f in ("kernels_force.hip", "pair.h", "common.h", "api.hip"):   # api.hip: the launch shapes
         with open(os.path.join(ROOT, "paper_2001_03180_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -551,6 +551,33 @@ def bench_step_control(M, ctx, safety=(0.6, 0.85, 0.9, 0.95, 1.0), etas=(1e-6, 1
     return rows
 
 
+def trace_union(csv_path, pattern):
+    """Busy time of the kernels whose name contains `pattern` in a rocprofv3
+    kernel trace (the union of their [start, end] intervals), with their
+    launch count and mean duration: the same measure as the benchmark's
+    kernel time, from the profiler's own timestamps."""
+    import csv
+    iv = []
+    with open(csv_path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if pattern in row["Kernel_Name"]:
+                iv.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    iv.sort()
+    busy, lo, hi = 0, None, None
+    for a, b in iv:
+        if hi is None or a > hi:
+            if hi is not None:
+                busy += hi - lo
+            lo, hi = a, b
+        else:
+            hi = max(hi, b)
+    if hi is not None:
+        busy += hi - lo
+    n = len(iv)
+    return {"kernel": pattern, "launches": n, "busy_us_per_launch": busy / 1e3 / max(n, 1),
+            "mean_duration_us": sum(b - a for a, b in iv) / 1e3 / max(n, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -572,6 +599,8 @@ def main():
     ap.add_argument("--timing-only", action="store_true",
                     help="only the cluster timing tests (Sec. 5.4: 20 sizes x 3 seeds, 0.1 Myr, and the eta sweep)")
     ap.add_argument("--timing-max-n", type=int, default=10000)
+    ap.add_argument("--trace-union", nargs=2, metavar=("KERNEL_TRACE_CSV", "NAME"),
+                    help="busy time per launch of kernels named NAME in a rocprofv3 kernel trace (no GPU)")
     ap.add_argument("--step-control-only", action="store_true",
                     help="only the controller's safety-factor study (eq. hnext; about two minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -581,6 +610,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
               "drives one GPU per process and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.trace_union:
+        print(json.dumps(trace_union(*args.trace_union)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -655,8 +687,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # force-kernel timing: HIP events around every force launch (on the
-    # library's stream) over a second pass of the same steps; kept out of the
-    # timed pass because each event pair adds launch gaps.  The roofline is
+    # stream it runs on) over a second pass of the same steps; kept out of the
+    # timed pass because each event pair adds launch gaps.  The kernel time is
+    # the union of the launches' intervals: at this size the divisions run as
+    # two concurrent chains whose force launches overlap.  The roofline is
     # that of the dominant kernel (the one with the most launch time).
     ctx.profile_enable(True)
     ctx.integrate(mt, xt, vt, t1, wl["t_end"], p, allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
@@ -715,6 +749,8 @@ def main():
             "kernel": KERNEL_NAME[kind],
             "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
+            "time_base": "busy time of the kernel (union of its launch intervals, HIP events) per launch; "
+                         "the two division chains' launches overlap",
             "all_force_launches": {"launches": all_launches, "avg_launch_us": all_ms * 1e3 / max(all_launches, 1),
                                    "tflops_algorithmic": FLOPS_PER_PAIR * all_pairs / (all_ms * 1e-3) / 1e12,
                                    "by_kernel": {KERNEL_NAME[k]: {"launches": v[0], "ms": v[1]}

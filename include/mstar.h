@@ -241,10 +241,14 @@ int mstar_force_noalloc(void *hip_stream, const mstar_params *params, int64_t n,
                         const int32_t *parent, const double *X, double *acc, double *U);
 
 /* Force-kernel timing for measurement: when enabled, every force-kernel
- * launch is bracketed by HIP events on the context stream; the totals cover
- * all launches since the last reset.  A batched call counts as one launch
- * (the persistent batch kernel) with the pair interactions of all its force
- * evaluations. */
+ * launch is bracketed by HIP events on the stream it runs on; the totals cover
+ * all launches since the last reset.  kernel_ms is the time during which any
+ * of them ran: the union of their intervals (the launches of two concurrent
+ * division chains overlap; for launches on one stream it is the sum of their
+ * durations), placed by float-millisecond offsets from the enable call
+ * (resolution about 1e-7 of the profiling window).  A batched call counts as
+ * one launch (the persistent batch kernel) with the pair interactions of all
+ * its force evaluations. */
 int mstar_profile_enable(mstar_ctx *ctx, int enable);
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs);
 /* The same totals for one force kernel: kind 0 the pairwise kernel (each

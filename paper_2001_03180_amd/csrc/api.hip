@@ -52,6 +52,7 @@ struct mstar_ctx {
     std::vector<int> ev_kind;          // force kernel of each event pair: 0 pairwise, 1 mutual
     std::vector<double> ev_pairs;      // directed pairs of each launch
     size_t ev_used = 0;
+    hipEvent_t prof_ref = nullptr;     // recorded when profiling is enabled: the time origin
     int64_t prof_launches = 0;
     double prof_pairs = 0.0;
     double prof_batch_ms = 0.0;        // batched launches (timed with b_ev)
@@ -87,7 +88,7 @@ struct mstar_ctx {
     int mut_wps = 3;                   // waves per SIMD the mutual kernel's work is split for
     int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
     int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
-    int div_chains = 1;                // independent chains of division lanes (1 or 2)
+    int div_chains = 0;                // chains of division lanes: 0 automatic, 1 or 2
     hipStream_t div_s2 = nullptr;      // stream of the second chain
     hipEvent_t div_ev[2] = {nullptr, nullptr};   // fork, join
     DcBuf dc{};                        // divide-and-conquer tree builder buffers
@@ -328,7 +329,10 @@ int force_cap(mstar_ctx *ctx, int nd) {
 // Layout of one force launch over nact evaluations: the mutual kernel where
 // it applies (no TTL function, N_d <= 2, buffers sized for this N), else the
 // pairwise kernel with j-splits sized to fill the chip.
-FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om);
+FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om, bool chain = false);
+
+// Bodies from which the divisions run as two chains of launches by default.
+constexpr int kChainMinN = 4096;
 
 // Number of j-splits of one force launch over `nact` divisions.  The
 // workgroups of a launch all take about the same time, so they run in rounds
@@ -351,7 +355,7 @@ int nsplit_for(const Dev &d, int nact, int cap) {
     return hi;
 }
 
-FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om) {
+FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om, bool chain) {
     const Dev &d = ctx->d;
     // the mutual kernel's waves split the launch's pairs evenly, one range per
     // wave; a single evaluation below kMutSoloN has too few steps to give every
@@ -360,7 +364,9 @@ FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om) {
         (ctx->force_mode == 2 || (d.n >= kMutMinN && (nact > 1 || d.n >= kMutSoloN)))) {
         FLay f = mut_geometry(d.n, 1, kMutLmin);   // L = the shortest allowed
         const long long total = (long long)nact * f.Ec;
-        const long long waves = std::max(1, ctx->mut_waves);
+        // one of two concurrent chains: one wave per SIMD, so that the two
+        // chains' launches leave a slot for the other chain's kicks and drifts
+        const long long waves = std::max(1, chain ? 4 * ctx->num_cu : ctx->mut_waves);
         f.L = std::max(f.L, (total + waves - 1) / waves);
         f.maxw = (int)((mut_rs(f, 1) + f.L - 1) / f.L) + 1;
         f.ncorr = nd > 0 ? 1 : 0;
@@ -578,7 +584,11 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
     // with two chains, lanes go (longest first) to the chain with fewer force
     // evaluations; the chains share no slot, so their launches run on two
     // streams, each one's kicks and drifts beside the other's force launches
-    const int nch = (ctx->div_chains > 1 && nlanes > 1) ? 2 : 1;
+    // (measured faster where the mutual kernel runs at N >= kChainMinN, slower
+    // below, where an attempt is bound by its launches)
+    const bool two = ctx->div_chains == 2 ||
+                     (ctx->div_chains == 0 && d.n >= kChainMinN && plan_force(ctx, 2, p->n_d, ttl_on(p), true).mut);
+    const int nch = (two && nlanes > 1) ? 2 : 1;
     int chain_of_lane[kMaxDiv];
     long load[2] = {0, 0};
     for (int l = 0; l < nlanes; ++l) {
@@ -609,7 +619,7 @@ int run_divisions(mstar_ctx *ctx, const mstar_params *p, const int *nlist, int n
             }
             if (dr.nact) launch_drift(d, st, dr, ttl_of(p), ctx->ext_on);
             if (!fk.nact) continue;
-            const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p));
+            const FLay f = plan_force(ctx, fk.nact, p->n_d, ttl_on(p), nch == 2);
             int rc = prof_force(ctx, fk, p->n_d, f, ttl_on(p), st);
             if (rc) return rc;
             if (ctx->ext_on) launch_ext(d, st, fk, 0);
@@ -864,7 +874,8 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         if (v >= 1 && v <= 8) ctx->mut_wps = v;
     }
     // division lanes in one chain of launches or two concurrent ones
-    // (MSTAR_DIV_CHAINS = 1 | 2)
+    // (MSTAR_DIV_CHAINS = 1 | 2; default: two where the mutual kernel runs
+    // at N >= kChainMinN)
     if (const char *e = std::getenv("MSTAR_DIV_CHAINS")) {
         const int v = std::atoi(e);
         if (v == 1 || v == 2) ctx->div_chains = v;
@@ -930,6 +941,7 @@ void mstar_destroy(mstar_ctx *ctx) {
     for (hipEvent_t e : ctx->b_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->ev) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    if (ctx->prof_ref) (void)hipEventDestroy(ctx->prof_ref);
     if (ctx->h_blk) (void)hipHostFree(ctx->h_blk);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -942,26 +954,64 @@ int mstar_profile_enable(mstar_ctx *ctx, int enable) {
     if (!ctx) return MSTAR_E_INVAL;
     (void)hipSetDevice(ctx->device);
     HIPCK(hipStreamSynchronize(ctx->stream));
+    if (ctx->div_s2) HIPCK(hipStreamSynchronize(ctx->div_s2));
     ctx->prof = enable != 0;
     ctx->ev_used = 0;
     ctx->prof_launches = 0;
     ctx->prof_pairs = 0.0;
     ctx->prof_batch_ms = 0.0;
+    if (ctx->prof) {
+        if (!ctx->prof_ref) HIPCK(hipEventCreate(&ctx->prof_ref));
+        HIPCK(hipEventRecord(ctx->prof_ref, ctx->stream));
+    }
+    return MSTAR_OK;
+}
+
+// Time during which force launches of `kind` (-1: any) ran: the union of
+// their intervals, placed on one time line by their offsets from the event
+// recorded when profiling was enabled (the two division chains' launches
+// overlap; launches on one stream do not, and then this is the sum of their
+// durations).  Offsets are float milliseconds: about 1e-7 of the profiling
+// window.
+static int prof_busy(mstar_ctx *ctx, int kind, int64_t *nl, double *ms, double *pairs) {
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (ctx->div_s2) HIPCK(hipStreamSynchronize(ctx->div_s2));
+    std::vector<std::pair<double, double>> iv;
+    double pr = 0.0;
+    for (size_t k = 0; k < ctx->ev_used; ++k) {
+        if (kind >= 0 && ctx->ev_kind[k] != kind) continue;
+        float a = 0.f, dur = 0.f;
+        HIPCK(hipEventElapsedTime(&a, ctx->prof_ref, ctx->ev[k].first));
+        HIPCK(hipEventElapsedTime(&dur, ctx->ev[k].first, ctx->ev[k].second));
+        iv.emplace_back((double)a, (double)a + (double)dur);
+        pr += ctx->ev_pairs[k];
+    }
+    std::sort(iv.begin(), iv.end());
+    double tot = 0.0, lo = 0.0, hi = -1.0;
+    for (const auto &q : iv) {
+        if (q.first > hi) {
+            if (hi > lo) tot += hi - lo;
+            lo = q.first;
+            hi = q.second;
+        } else {
+            hi = std::max(hi, q.second);
+        }
+    }
+    if (hi > lo) tot += hi - lo;
+    if (nl) *nl = (int64_t)iv.size();
+    if (ms) *ms = tot;
+    if (pairs) *pairs = pr;
     return MSTAR_OK;
 }
 
 int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, double *pairs) {
     if (!ctx) return MSTAR_E_INVAL;
     (void)hipSetDevice(ctx->device);
-    HIPCK(hipStreamSynchronize(ctx->stream));
-    double tot = ctx->prof_batch_ms;
-    for (size_t k = 0; k < ctx->ev_used; ++k) {
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
-        tot += ms;
-    }
+    double ms = 0.0;
+    int rc = prof_busy(ctx, -1, nullptr, &ms, nullptr);
+    if (rc) return rc;
     if (launches) *launches = ctx->prof_launches;
-    if (kernel_ms) *kernel_ms = tot;
+    if (kernel_ms) *kernel_ms = ms + ctx->prof_batch_ms;
     if (pairs) *pairs = ctx->prof_pairs;
     return MSTAR_OK;
 }
@@ -969,21 +1019,7 @@ int mstar_profile_read(mstar_ctx *ctx, int64_t *launches, double *kernel_ms, dou
 int mstar_profile_read_kernel(mstar_ctx *ctx, int32_t kind, int64_t *launches, double *kernel_ms, double *pairs) {
     if (!ctx || kind < 0 || kind > 1) return MSTAR_E_INVAL;
     (void)hipSetDevice(ctx->device);
-    HIPCK(hipStreamSynchronize(ctx->stream));
-    int64_t nl = 0;
-    double tot = 0.0, pr = 0.0;
-    for (size_t k = 0; k < ctx->ev_used; ++k) {
-        if (ctx->ev_kind[k] != kind) continue;
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, ctx->ev[k].first, ctx->ev[k].second));
-        tot += ms;
-        pr += ctx->ev_pairs[k];
-        ++nl;
-    }
-    if (launches) *launches = nl;
-    if (kernel_ms) *kernel_ms = tot;
-    if (pairs) *pairs = pr;
-    return MSTAR_OK;
+    return prof_busy(ctx, kind, launches, kernel_ms, pairs);
 }
 
 int mstar_issue_rates(mstar_ctx *ctx, double *fma_cycles, double *rsq_cycles) {

@@ -88,6 +88,9 @@ def test_unfinished_rebuild_repeats_the_step_exactly(M):
     step repeated.  The integration must equal the default one bit for bit
     (only the count of force evaluations grows)."""
     import os
+    import torch
+    if not torch.cuda.is_available():   # torch first: it brings up the device runtime
+        pytest.skip("no GPU")
     m, x, v = ics.plummer_with_central_mass(256, 501)
     p = dict(eta=1e-12)
     ref = M.Context(0)
@@ -117,14 +120,14 @@ def test_unfinished_rebuild_repeats_the_step_exactly(M):
 
 
 def test_two_division_chains(M):
-    """MSTAR_DIV_CHAINS=2 (here with MSTAR_MUT_WPS=1) runs the division lanes
-    as two chains of launches on two streams.  Graph replay, which captures
-    the fork and the join, equals eager launch bit for bit.  Against the
-    one-chain schedule the force partials are grouped differently, so the
-    agreement is to rounding: the step lengths differ in their last bits, and
-    the end-time iteration may take a step more or less; both reach t_end,
-    with end states within 1e-10 of the system's extent and the same energy
-    error to 1e-13."""
+    """At N_p = 5002 the divisions run as two chains of launches on two
+    streams (the default where the mutual kernel runs at N >= 4096).  Graph
+    replay, which captures the fork and the join, equals eager launch bit for
+    bit.  Against one chain (MSTAR_DIV_CHAINS=1) the force launches group the
+    evaluations and their partials differently, so the agreement is to
+    rounding: the step lengths differ in their last bits, and the end-time
+    iteration may take a step more or less; both reach t_end, with end states
+    within 1e-10 of the system's extent and the same energy error to 1e-13."""
     import os
     import torch
     if not torch.cuda.is_available():   # torch first: it brings up the device runtime
@@ -133,18 +136,16 @@ def test_two_division_chains(M):
     m, x, v, _ = ics.workload("plummer5000_binary")
     te = 2e-3
     p = dict(eta=1e-13)
-    one = M.Context(0)
-    keys = ("MSTAR_DIV_CHAINS", "MSTAR_MUT_WPS")
-    old = {k: os.environ.get(k) for k in keys}
-    os.environ.update(MSTAR_DIV_CHAINS="2", MSTAR_MUT_WPS="1")
+    two = M.Context(0)
+    old = os.environ.get("MSTAR_DIV_CHAINS")
+    os.environ["MSTAR_DIV_CHAINS"] = "1"
     try:
-        two = M.Context(0)
+        one = M.Context(0)
     finally:
-        for k in keys:
-            if old[k] is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = old[k]
+        if old is None:
+            os.environ.pop("MSTAR_DIV_CHAINS", None)
+        else:
+            os.environ["MSTAR_DIV_CHAINS"] = old
     try:
         say("plummer5000_binary to t=2e-3: one chain, two chains (graph), two chains (eager)")
         a = one.integrate(m, x, v, 0.0, te, M.params(**p))
