@@ -59,7 +59,7 @@ BATCH_ETA = 1e-12
 # valid only for the force-kernel and launch-planning sources with this hash.
 # (per force kernel kind; None where not measured for the current sources)
 FORCE_TRAFFIC = {
-    1: {"sha256": "55f013ec72b50b9bc43aafa6617b0dc30f927edc65ec64beeb303c02843272fb",
+    1: {"sha256": "92c8e0311e22e7d7c5ecc705c7f4ef158c6bcf70820d1c8b8771338f092ac1ed",
         "fetch_bytes": 6248.03 * 1024 * 2.000, "write_bytes": 29412.10 * 1024 * 1.000,
         # executed FP64 flops (ADD + MUL + 2 FMA + TRANS) per directed pair
         "exec_flops_per_pair": 35.0 / 2},
@@ -689,9 +689,10 @@ def main():
     # force-kernel timing: HIP events around every force launch (on the
     # stream it runs on) over a second pass of the same steps; kept out of the
     # timed pass because each event pair adds launch gaps.  The kernel time is
-    # the union of the launches' intervals: at this size the divisions run as
-    # two concurrent chains whose force launches overlap.  The roofline is
-    # that of the dominant kernel (the one with the most launch time).
+    # the union of the launches' intervals (the sum of their durations for
+    # launches on one stream; MSTAR_DIV_CHAINS lets two chains overlap).  The
+    # roofline is that of the dominant kernel (the one with the most launch
+    # time).
     ctx.profile_enable(True)
     ctx.integrate(mt, xt, vt, t1, wl["t_end"], p, allow=(M.OK, M.W_TIME_TOL, M.E_MAXSTEPS))
     all_launches, all_ms, all_pairs = ctx.profile_read()
@@ -749,8 +750,7 @@ def main():
             "kernel": KERNEL_NAME[kind],
             "launches": launches,
             "avg_launch_us": avg_launch_s * 1e6,
-            "time_base": "busy time of the kernel (union of its launch intervals, HIP events) per launch; "
-                         "the two division chains' launches overlap",
+            "time_base": "busy time of the kernel (union of its launch intervals, HIP events) per launch",
             "all_force_launches": {"launches": all_launches, "avg_launch_us": all_ms * 1e3 / max(all_launches, 1),
                                    "tflops_algorithmic": FLOPS_PER_PAIR * all_pairs / (all_ms * 1e-3) / 1e12,
                                    "by_kernel": {KERNEL_NAME[k]: {"launches": v[0], "ms": v[1]}

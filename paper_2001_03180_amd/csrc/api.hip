@@ -88,7 +88,7 @@ struct mstar_ctx {
     int mut_wps = 3;                   // waves per SIMD the mutual kernel's work is split for
     int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
     int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
-    int div_chains = 0;                // chains of division lanes: 0 automatic, 1 or 2
+    int div_chains = 1;                // chains of division lanes: 1, 2, or 0 (two at large N)
     hipStream_t div_s2 = nullptr;      // stream of the second chain
     hipEvent_t div_ev[2] = {nullptr, nullptr};   // fork, join
     DcBuf dc{};                        // divide-and-conquer tree builder buffers
@@ -331,7 +331,7 @@ int force_cap(mstar_ctx *ctx, int nd) {
 // pairwise kernel with j-splits sized to fill the chip.
 FLay plan_force(mstar_ctx *ctx, int nact, int nd, bool om, bool chain = false);
 
-// Bodies from which the divisions run as two chains of launches by default.
+// Bodies from which MSTAR_DIV_CHAINS=0 runs the divisions as two chains.
 constexpr int kChainMinN = 4096;
 
 // Number of j-splits of one force launch over `nact` divisions.  The
@@ -874,11 +874,11 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         if (v >= 1 && v <= 8) ctx->mut_wps = v;
     }
     // division lanes in one chain of launches or two concurrent ones
-    // (MSTAR_DIV_CHAINS = 1 | 2; default: two where the mutual kernel runs
-    // at N >= kChainMinN)
+    // (MSTAR_DIV_CHAINS = 1, the default; 2; or 0: two where the mutual
+    // kernel runs at N >= kChainMinN)
     if (const char *e = std::getenv("MSTAR_DIV_CHAINS")) {
         const int v = std::atoi(e);
-        if (v == 1 || v == 2) ctx->div_chains = v;
+        if (v == 0 || v == 1 || v == 2) ctx->div_chains = v;
     }
     if (hipStreamCreateWithFlags(&ctx->div_s2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->div_ev[0], hipEventDisableTiming) != hipSuccess ||

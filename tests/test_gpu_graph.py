@@ -120,10 +120,11 @@ def test_unfinished_rebuild_repeats_the_step_exactly(M):
 
 
 def test_two_division_chains(M):
-    """At N_p = 5002 the divisions run as two chains of launches on two
-    streams (the default where the mutual kernel runs at N >= 4096).  Graph
-    replay, which captures the fork and the join, equals eager launch bit for
-    bit.  Against one chain (MSTAR_DIV_CHAINS=1) the force launches group the
+    """With MSTAR_DIV_CHAINS=0 the divisions at N_p = 5002 run as two chains
+    of launches on two streams (automatic where the mutual kernel runs at
+    N >= 4096).  Graph replay, which captures the fork and the join, equals
+    eager launch bit for bit.  Against one chain (the default) the force
+    launches group the
     evaluations and their partials differently, so the agreement is to
     rounding: the step lengths differ in their last bits, and the end-time
     iteration may take a step more or less; both reach t_end, with end states
@@ -136,11 +137,11 @@ def test_two_division_chains(M):
     m, x, v, _ = ics.workload("plummer5000_binary")
     te = 2e-3
     p = dict(eta=1e-13)
-    two = M.Context(0)
+    one = M.Context(0)
     old = os.environ.get("MSTAR_DIV_CHAINS")
-    os.environ["MSTAR_DIV_CHAINS"] = "1"
+    os.environ["MSTAR_DIV_CHAINS"] = "0"
     try:
-        one = M.Context(0)
+        two = M.Context(0)
     finally:
         if old is None:
             os.environ.pop("MSTAR_DIV_CHAINS", None)
