@@ -354,7 +354,8 @@ int mstar_batch_set_config(mstar_ctx *ctx, int32_t k_fix, const mstar_batch_conf
 /* Autotuner: time every launch shape (wave_lanes, wave_max_n, wgs_per_cu)
  * on this batch (same arguments as mstar_integrate_batch; x and v are not
  * modified; pass a shortened t_end to bound the cost), keep the fastest for
- * params->k_fix in the context and return it in *best.  MSTAR_E_UNSUPPORTED
+ * params->k_fix in the context and return it in *best.  MSTAR_E_INVAL when
+ * no system has at most 64 bodies (nothing runs in the kernel); MSTAR_E_UNSUPPORTED
  * for parameters the persistent kernel does not implement (k_fix > 8,
  * beta != 0, n_d > 2, accept_rule 1). */
 int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_sys, const int64_t *offsets,

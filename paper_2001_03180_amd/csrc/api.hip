@@ -1787,6 +1787,9 @@ int mstar_batch_autotune(mstar_ctx *ctx, const mstar_params *params, int32_t n_s
     int rc = batch_validate(ctx, params, n_sys, offsets, t0, t_end, &n_tot, true);
     if (rc) return rc;
     if (!m || !x || !v || !best) return fail(ctx, MSTAR_E_INVAL, "autotune: null argument");
+    bool any = false;
+    for (int32_t s = 0; s < n_sys && !any; ++s) any = offsets[s + 1] - offsets[s] <= kBatchMaxN;
+    if (!any) return fail(ctx, MSTAR_E_INVAL, "autotune: no system of at most %d bodies to time", kBatchMaxN);
     (void)hipSetDevice(ctx->device);
     if ((rc = ensure_batch(ctx, n_sys, n_tot))) return rc;
     const hipMemcpyKind k = is_dev(params->flags) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;

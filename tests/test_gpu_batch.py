@@ -451,6 +451,10 @@ def test_systems_beyond_the_kernel_use_the_single_system_driver(ctx, M):
     assert np.array_equal(v3[:100], vb[int(off[1]):int(off[2])]) and np.array_equal(v3[100:], vb[int(off[3]):])
     assert np.array_equal(st3, st[[1, 3]])
     assert np.array_equal(H3, H[[1, 3]], equal_nan=True)
+    before = ctx.batch_config(8)
+    with pytest.raises(M.MstarError) as e:   # nothing for the autotuner to time
+        ctx.batch_autotune(o3, m[sl], x[sl], v[sl], t_end, p=p)
+    assert e.value.code == M.E_INVAL and ctx.batch_config(8) == before
 
 
 @pytest.mark.parametrize("kw", [dict(k_fix=9), dict(beta=1.0), dict(n_d=3), dict(accept_rule=1)],
