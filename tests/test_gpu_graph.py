@@ -169,3 +169,52 @@ def test_two_division_chains(M):
     finally:
         one.close()
         two.close()
+
+
+@pytest.mark.parametrize("case", ["ttl", "field"])
+def test_two_chains_with_ttl_and_external_field(M, case):
+    """MSTAR_DIV_CHAINS=2 with the pairwise kernel: the TTL run (Omega partials
+    per slot) and a run under an external field (per-slot field kicks).  Graph
+    replay equals eager launch bit for bit; against one chain the agreement is
+    to rounding (end states within 1e-10 of the extents)."""
+    import os
+    import torch
+    if not torch.cuda.is_available():   # torch first: it brings up the device runtime
+        pytest.skip("no GPU")
+    m, x, v = ics.plummer(48, 9)
+    one = M.Context(0)
+    old = os.environ.get("MSTAR_DIV_CHAINS")
+    os.environ["MSTAR_DIV_CHAINS"] = "2"
+    try:
+        two = M.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("MSTAR_DIV_CHAINS", None)
+        else:
+            os.environ["MSTAR_DIV_CHAINS"] = old
+    if case == "ttl":
+        kw = dict(eta=1e-12, alpha=1.0, beta=1.0, gamma=0.0, omega_mass_max=1.0)
+
+        def run(c, **f):
+            return c.integrate(m, x, v, 0.0, 0.05, M.params(**kw, **f))
+    else:
+        kw = dict(eta=1e-12)
+
+        def run(c, **f):
+            return c.integrate_ext(m, x, v, 0.0, 0.05, g=(0.3, 0.0, 0.1), points=[[5.0, 4.0, 0.0, 0.0, 0.5]],
+                                   p=M.params(**kw, **f))
+    try:
+        say(f"two chains, {case}: one chain, two chains (graph), two chains (eager)")
+        a = run(one)
+        b = run(two)
+        e = run(two, flags=M.EAGER)
+        assert b[3]["steps_accepted"] + b[3]["steps_rejected"] > 5
+        _same(b, e)
+        assert abs(b[3]["steps_accepted"] - a[3]["steps_accepted"]) <= 2
+        dx = np.abs(b[0] - a[0]).max() / np.ptp(a[0], axis=0).max()
+        dv = np.abs(b[1] - a[1]).max() / np.ptp(a[1], axis=0).max()
+        say(f"state difference {dx:.2e} (x), {dv:.2e} (v) of the extents")
+        assert dx <= 1e-10 and dv <= 1e-10
+    finally:
+        one.close()
+        two.close()
