@@ -59,7 +59,7 @@ BATCH_ETA = 1e-12
 # valid only for the force-kernel and launch-planning sources with this hash.
 # (per force kernel kind; None where not measured for the current sources)
 FORCE_TRAFFIC = {
-    1: {"sha256": "44c2ee68a22d5c7807f4b9b40905e9c1ccdb7fdddd3466126b893cf9aa91a4d3",
+    1: {"sha256": "30b68adc528fefe9ff9616e572258658a064733c094713bbb2d76051faa74e56",
         "fetch_bytes": 6248.03 * 1024 * 2.000, "write_bytes": 29412.10 * 1024 * 1.000,
         # executed FP64 flops (ADD + MUL + 2 FMA + TRANS) per directed pair
         "exec_flops_per_pair": 35.0 / 2},

@@ -32,6 +32,10 @@
 
 using namespace mstar;
 
+// Default accepted steps between re-deriving the carried positions and
+// velocities from the MST edges.
+constexpr int kResyncEvery = 32;
+
 struct mstar_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -89,6 +93,7 @@ struct mstar_ctx {
     int mut_waves = 0;                 // resident mutual-kernel waves on the chip (occupancy x CUs)
     int mut_cap_n = 0;                 // N the mutual-kernel buffers are sized for (0: none)
     int div_chains = 1;                // chains of division lanes: 1, 2, or 0 (two at large N)
+    int resync_every = kResyncEvery;   // accepted steps between re-deriving the Cartesian caches
     hipStream_t div_s2 = nullptr;      // stream of the second chain
     hipEvent_t div_ev[2] = {nullptr, nullptr};   // fork, join
     DcBuf dc{};                        // divide-and-conquer tree builder buffers
@@ -317,7 +322,6 @@ Ttl ttl_of(const mstar_params *p) { return Ttl{p->alpha, p->beta, p->gamma}; }
 bool ttl_on(const mstar_params *p) { return p->beta != 0.0; }
 
 constexpr int kBase = kBaseSlot;     // slot of the start state
-constexpr int kResyncEvery = 32;     // accepted steps between re-deriving positions from the MST edges
 
 // Resident force workgroups on the whole chip (queried once per N_d kind).
 int force_cap(mstar_ctx *ctx, int nd) {
@@ -873,6 +877,12 @@ int mstar_create(mstar_ctx **out, int hip_device, void *hip_stream) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 8) ctx->mut_wps = v;
     }
+    // accepted steps between re-deriving the carried Cartesian caches from
+    // the MST edges (MSTAR_RESYNC_EVERY, 1..1000)
+    if (const char *e = std::getenv("MSTAR_RESYNC_EVERY")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 1000) ctx->resync_every = v;
+    }
     // division lanes in one chain of launches or two concurrent ones
     // (MSTAR_DIV_CHAINS = 1, the default; 2; or 0: two where the mutual
     // kernel runs at N >= kChainMinN)
@@ -1338,7 +1348,7 @@ static int integrate_run(mstar_ctx *ctx, const mstar_params *params, int64_t n, 
                 since_rebuild = 0;
                 just_rebuilt = true;
             }
-            const bool resync = since_resync >= kResyncEvery;
+            const bool resync = since_resync >= ctx->resync_every;
             if (resync) since_resync = 0;
             last_resync = resync;
             if ((rc = prepare_step(ctx, &p, due, resync, &st.force_evals))) break;

@@ -94,3 +94,55 @@ def test_free_integration_parity_with_energy(ctx, orc, M, name, t_end):
     say(line)
     assert ex <= 1e-10 and ev <= 1e-10, line
     assert abs(dEg) <= 1e-13 and abs(dEg - dEo) <= 1e-13, line
+
+
+RESYNC_CASES = [("plummer5000_binary", 5000, 301, 0.006), ("plummer500_binary", 500, 17, 0.02)]
+
+
+@pytest.mark.parametrize("name,n,seed,t_end", RESYNC_CASES, ids=[c[0] for c in RESYNC_CASES])
+def test_carried_caches_against_resync_every_step(M, name, n, seed, t_end):
+    """The driver carries COM-frame positions and velocities through the
+    divisions and the extrapolation, and re-derives them from the MST edges
+    (the deconstruction of Sec. 2.2) every 32 accepted steps.  Re-deriving
+    them at every step (MSTAR_RESYNC_EVERY=1) bounds what the carried copies
+    drift in between: on hard-binary systems over at least two periods the
+    two runs agree to the oracle-parity bars (end state 1e-10 of the extents,
+    the binary's internal state 1e-8 of its size, |dE/E| within 1e-13)."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from bench import _energy as energy
+    m, x, v = ics.plummer_with_binary(n, seed)
+    eta = 1e-13
+    dflt = M.Context(0)
+    old = os.environ.get("MSTAR_RESYNC_EVERY")
+    os.environ["MSTAR_RESYNC_EVERY"] = "1"
+    try:
+        every = M.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("MSTAR_RESYNC_EVERY", None)
+        else:
+            os.environ["MSTAR_RESYNC_EVERY"] = old
+    try:
+        say(f"{name}: resync every 32 steps (default) and every step, t_end={t_end}")
+        xa, va, rca, sa = dflt.integrate(m, x, v, 0.0, t_end, M.params(eta=eta))
+        xb, vb, rcb, sb = every.integrate(m, x, v, 0.0, t_end, M.params(eta=eta))
+    finally:
+        dflt.close()
+        every.close()
+    assert sa["steps_accepted"] >= 64, sa["steps_accepted"]
+    ex = np.abs(xa - xb).max() / np.ptp(xb, axis=0).max()
+    ev = np.abs(va - vb).max() / np.ptp(vb, axis=0).max()
+    rb, ub = xb[-1] - xb[-2], vb[-1] - vb[-2]
+    br = np.linalg.norm((xa[-1] - xa[-2]) - rb) / np.linalg.norm(rb)
+    bv = np.linalg.norm((va[-1] - va[-2]) - ub) / np.linalg.norm(ub)
+    E0 = energy(m, x, v)
+    de = abs(energy(m, xa, va) / E0 - energy(m, xb, vb) / E0)
+    line = (f"{name}: {sa['steps_accepted']} / {sb['steps_accepted']} accepted steps; state |dx|/R={ex:.2e} "
+            f"|dv|/V={ev:.2e}; binary |dr|/r={br:.2e} |du|/u={bv:.2e}; dE/E difference {de:.1e}")
+    say(line)
+    assert ex <= 1e-10 and ev <= 1e-10, line
+    assert br <= 1e-8 and bv <= 1e-8, line
+    assert de <= 1e-13, line
