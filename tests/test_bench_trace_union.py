@@ -37,3 +37,32 @@ def test_no_matching_kernel(tmp_path):
     _trace(p, [("k_kick", 0, 10)])
     r = bench.trace_union(str(p), "k_force_mut")
     assert r["launches"] == 0 and r["busy_us_per_launch"] == 0.0
+
+
+def test_step_control_study_wiring():
+    """bench_step_control against a stand-in context: every workload, tolerance
+    and safety factor is run (a_GBS < 0.8 skipped below eta = 1e-11) and the
+    counts of each workload's systems are summed."""
+    import paper_2001_03180_amd.mstar as M
+
+    class Ctx:
+        def __init__(self):
+            self.calls = []
+
+        def integrate(self, m, x, v, t0, te, p, allow=()):
+            self.calls.append((len(m), p.eta, p.a_gbs, p.max_steps))
+            return x, v, 0, {"steps_accepted": 3, "steps_rejected": 1, "force_evals": 72}
+
+    ctx = Ctx()
+    rows = bench.bench_step_control(M, ctx, safety=(0.6, 0.9), etas=(1e-6, 1e-13))
+    # 4 workloads x (2 safety factors at 1e-6 + 1 at 1e-13)
+    assert len(rows) == 12
+    by = {(r["workload"], r["eta"], r["a_gbs"]): r for r in rows}
+    assert ("timing1129", 1e-13, 0.6) not in by
+    r = by[("timing4833", 1e-6, 0.6)]
+    assert r["force_evals"] == 3 * 72 and r["steps_accepted"] == 9 and r["steps_rejected"] == 3
+    assert by[("plummer5000_binary", 1e-13, 0.9)]["force_evals"] == 72
+    assert r["max_abs_dE_over_E"] == 0.0
+    # each timed run is preceded by a one-step call that sizes the buffers
+    sizing = [c for c in ctx.calls if c[3] == 1]
+    assert len(sizing) == len(ctx.calls) // 2
